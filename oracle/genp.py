@@ -1,0 +1,293 @@
+"""FP64 CPU oracle of the randomized-multiplier GENP solve (test infrastructure only).
+
+Pan & Qian, "More on the Power of Randomized Matrix Multiplication":
+section 1.1 proposes to solve A y = b by applying a random multiplier and then
+Gaussian elimination with no pivoting (GENP); Corollary 4.1(ii) (section 4)
+is the reason a *right* Gaussian multiplier makes every leading block of
+C = A G nonsingular and well conditioned when A is nonsingular.  The method
+computed here:
+
+    C = A G                      (multiplier product, section 1.1)
+    C = L U                      (GENP / block Gaussian elimination, section 1.1,
+                                  Theorem 2.2 and the Schur complement of Fact 2.1)
+    Y = U^{-1} L^{-1} B          (substitutions)
+    X = G Y                      (so that A X = A G (AG)^{-1} B = B)
+    X += G (LU)^{-1} (B - A X)   (iterative refinement, section 7.1 / Table 7.1,
+                                  at most two steps per section 7.2)
+
+Everything is plain numpy float64 with no blocking beyond what the paper's
+block Gaussian elimination states.  Library primitives used as steps: the
+matrix product (``@``), ``scipy.linalg.solve_triangular`` inside the block
+variant, and ``numpy.linalg.solve`` (LAPACK, partial pivoting) only as the
+textbook definition x = A^{-1} b in the adjoint.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+U64 = np.finfo(np.float64).eps / 2  # unit roundoff of IEEE double, 2^-53
+
+
+# ---------------------------------------------------------------------------
+# multiplier (Definition 3.2; Toeplitz matrices, section 2.3)
+# ---------------------------------------------------------------------------
+
+def toeplitz_from_params(p: np.ndarray, n: int) -> np.ndarray:
+    """Dense n x n Toeplitz matrix G[i, j] = t_{i-j} stored as p[i - j + n - 1].
+
+    Section 2.3 defines T = (t_{i-j}) by its first row (t_{-h}) and first
+    column (t_h); p holds t_{-(n-1)} .. t_{n-1} in increasing subscript order.
+    """
+    p = np.asarray(p, dtype=np.float64)
+    if p.shape != (2 * n - 1,):
+        raise ValueError(f"need 2n-1 = {2 * n - 1} parameters, got {p.shape}")
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    return p[i - j + n - 1]
+
+
+def dense_multiplier(G: Optional[np.ndarray], p: Optional[np.ndarray], n: int) -> np.ndarray:
+    if G is not None:
+        return np.asarray(G, dtype=np.float64)
+    if p is not None:
+        return toeplitz_from_params(p, n)
+    raise ValueError("need G or p")
+
+
+def precondition(A: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """C = A G, the right multiplier of section 1.1 / Corollary 4.1(ii)."""
+    return np.asarray(A, dtype=np.float64) @ np.asarray(G, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# GENP (section 1.1) and block Gaussian elimination (Theorem 2.2, Fact 2.1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class FactorInfo:
+    """Outcome of an elimination.
+
+    breakdown_col: 1-based index of the first pivot that is non-finite or
+    has |u_kk| <= pivot_tol * max|C| (0 when none).  The elimination stops
+    there, so the factors are only meaningful in rows/columns before it.
+    """
+
+    breakdown_col: int
+    pivots: np.ndarray          # u_kk for k before the breakdown (all n if none)
+    max_abs_c: float
+    max_abs_u: float
+
+    @property
+    def growth(self) -> float:
+        return self.max_abs_u / self.max_abs_c if self.max_abs_c > 0 else np.inf
+
+
+def _is_breakdown(piv: float, tol_abs: float) -> bool:
+    return (not np.isfinite(piv)) or abs(piv) <= tol_abs
+
+
+def genp_unblocked(C: np.ndarray, pivot_tol: float = 0.0):
+    """Outer-product Gaussian elimination with no pivoting (section 1.1).
+
+    For k = 1..n: l_ik = c_ik / c_kk and c_ij -= l_ik c_kj for i, j > k.
+    Returns (LU, info) with the unit lower L stored below the diagonal and
+    U on and above it, the usual packed form.
+    """
+    LU = np.array(C, dtype=np.float64, copy=True)
+    n = LU.shape[0]
+    maxc = float(np.max(np.abs(LU))) if n else 0.0
+    tol_abs = pivot_tol * maxc
+    pivots = []
+    for k in range(n):
+        piv = LU[k, k]
+        if _is_breakdown(piv, tol_abs):
+            return LU, FactorInfo(k + 1, np.array(pivots), maxc, _max_abs_u(LU, k))
+        pivots.append(piv)
+        LU[k + 1:, k] /= piv
+        LU[k + 1:, k + 1:] -= np.outer(LU[k + 1:, k], LU[k, k + 1:])
+    return LU, FactorInfo(0, np.array(pivots), maxc, _max_abs_u(LU, n))
+
+
+def _max_abs_u(LU: np.ndarray, upto: int) -> float:
+    if upto == 0:
+        return 0.0
+    return float(np.max(np.abs(np.triu(LU[:upto, :]))))
+
+
+def genp_blocked(C: np.ndarray, nb: int, pivot_tol: float = 0.0):
+    """Block Gaussian elimination with block size nb (Theorem 2.2).
+
+    For each diagonal block: factor it by GENP, then L21 = C21 U11^{-1},
+    U12 = L11^{-1} C12 and replace C22 by its Schur complement
+    C22 - L21 U12 = C22 - C21 C11^{-1} C12 (Fact 2.1).  In exact arithmetic this is
+    the same factorization as :func:`genp_unblocked`; a ragged last block is fine.
+    """
+    from scipy.linalg import solve_triangular
+
+    if nb < 1:
+        raise ValueError("nb >= 1")
+    LU = np.array(C, dtype=np.float64, copy=True)
+    n = LU.shape[0]
+    maxc = float(np.max(np.abs(LU))) if n else 0.0
+    pivots = []
+    for k in range(0, n, nb):
+        e = min(k + nb, n)
+        D, inf = genp_unblocked(LU[k:e, k:e], 0.0)
+        LU[k:e, k:e] = D
+        # pivot test against the tolerance scaled by max|C| of the whole matrix
+        for t, piv in enumerate(np.diag(D)):
+            if inf.breakdown_col and t + 1 >= inf.breakdown_col:
+                return LU, FactorInfo(k + t + 1, np.array(pivots), maxc, _max_abs_u(LU, k + t))
+            if _is_breakdown(piv, pivot_tol * maxc):
+                return LU, FactorInfo(k + t + 1, np.array(pivots), maxc, _max_abs_u(LU, k + t))
+            pivots.append(piv)
+        if e < n:
+            L11 = np.tril(D, -1) + np.eye(e - k)
+            U11 = np.triu(D)
+            LU[e:, k:e] = solve_triangular(U11.T, LU[e:, k:e].T, lower=True).T
+            LU[k:e, e:] = solve_triangular(L11, LU[k:e, e:], lower=True, unit_diagonal=True)
+            LU[e:, e:] -= LU[e:, k:e] @ LU[k:e, e:]
+    return LU, FactorInfo(0, np.array(pivots), maxc, _max_abs_u(LU, n))
+
+
+def unpack(LU: np.ndarray):
+    """(L, U) from the packed form: L unit lower, U upper."""
+    n = LU.shape[0]
+    return np.tril(LU, -1) + np.eye(n), np.triu(LU)
+
+
+# ---------------------------------------------------------------------------
+# substitutions, recovery, refinement (section 1.1, section 7.1)
+# ---------------------------------------------------------------------------
+
+def forward_unit(LU: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Z = L^{-1} B, L unit lower triangular (row-by-row substitution)."""
+    B = np.asarray(B, dtype=np.float64)
+    Z = np.array(B, copy=True).reshape(B.shape[0], -1)
+    for i in range(LU.shape[0]):
+        if i:
+            Z[i] -= LU[i, :i] @ Z[:i]
+    return Z.reshape(B.shape)
+
+
+def backward_upper(LU: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """Y = U^{-1} Z, U upper triangular (row-by-row substitution, bottom up)."""
+    Z = np.asarray(Z, dtype=np.float64)
+    Y = np.array(Z, copy=True).reshape(Z.shape[0], -1)
+    n = LU.shape[0]
+    for i in range(n - 1, -1, -1):
+        if i < n - 1:
+            Y[i] -= LU[i, i + 1:] @ Y[i + 1:]
+        Y[i] /= LU[i, i]
+    return Y.reshape(Z.shape)
+
+
+def lu_solve(LU: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Y = U^{-1} L^{-1} B."""
+    return backward_upper(LU, forward_unit(LU, B))
+
+
+def solve(LU: np.ndarray, G: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """X = G U^{-1} L^{-1} B: the solution of A X = B from the factors of C = A G."""
+    return G @ lu_solve(LU, B)
+
+
+def residual(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> np.ndarray:
+    return B - A @ X
+
+
+def backward_error_inf(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Normwise backward error per column (Rigal-Gaches, infinity norm).
+
+    eta_j = ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf).
+    """
+    X2 = np.asarray(X).reshape(X.shape[0], -1)
+    B2 = np.asarray(B).reshape(B.shape[0], -1)
+    R = residual(A, X2, B2)
+    a = np.max(np.sum(np.abs(A), axis=1))
+    return np.max(np.abs(R), axis=0) / (a * np.max(np.abs(X2), axis=0) + np.max(np.abs(B2), axis=0))
+
+
+def relative_residual(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """||A y - b|| / ||b|| per column (2-norm), the quantity of Table 7.1."""
+    X2 = np.asarray(X).reshape(X.shape[0], -1)
+    B2 = np.asarray(B).reshape(B.shape[0], -1)
+    return np.linalg.norm(A @ X2 - B2, axis=0) / np.linalg.norm(B2, axis=0)
+
+
+@dataclasses.dataclass
+class SolveResult:
+    X: np.ndarray
+    eta_hist: list            # eta_inf (max over columns) before each step and at the end
+    steps: int
+
+
+def refine(A, G, LU, B, X, max_iter: int = 2, tol: float = 0.0) -> SolveResult:
+    """Iterative refinement in FP64: R = B - A X, X += G (LU)^{-1} R.
+
+    Section 7.1 reports one refinement step after GENP (Table 7.1); section
+    7.2 performs at most two.  Stops early when max_j eta_j <= tol.
+    """
+    X = np.array(X, dtype=np.float64, copy=True)
+    hist = [float(np.max(backward_error_inf(A, X, B)))]
+    steps = 0
+    while steps < max_iter and hist[-1] > tol:
+        R = residual(A, X, B)
+        X += solve(LU, G, R)
+        steps += 1
+        hist.append(float(np.max(backward_error_inf(A, X, B))))
+    return SolveResult(X, hist, steps)
+
+
+def genp_solve(A, B, G, nb: Optional[int] = None, refine_steps: int = 2, tol: float = 0.0,
+               pivot_tol: float = 0.0):
+    """The whole path: C = AG, GENP, substitutions, X = GY, refinement."""
+    C = precondition(A, G)
+    LU, info = genp_unblocked(C, pivot_tol) if nb is None else genp_blocked(C, nb, pivot_tol)
+    if info.breakdown_col:
+        return None, LU, info
+    X = solve(LU, G, B)
+    res = refine(A, G, LU, B, X, refine_steps, tol)
+    return res, LU, info
+
+
+# ---------------------------------------------------------------------------
+# adjoint (the differentiation form: gradient of L = sum(W * X), X = A^{-1} B)
+# ---------------------------------------------------------------------------
+
+def adjoint(A: np.ndarray, X: np.ndarray, W: np.ndarray):
+    """dB = A^{-T} W and dA = -dB X^T.
+
+    From d(A^{-1}B) = -A^{-1} dA A^{-1} B + A^{-1} dB: with L = sum(W * X),
+    dL = <A^{-T} W, dB> - <A^{-T} W X^T, dA>.  Uses the textbook solve
+    (LAPACK partial pivoting) for A^{-T} W.
+    """
+    dB = np.linalg.solve(np.asarray(A).T, W)
+    return dB, -dB @ np.asarray(X).T
+
+
+# ---------------------------------------------------------------------------
+# quantities the tests report
+# ---------------------------------------------------------------------------
+
+def factor_residual(C: np.ndarray, LU: np.ndarray):
+    """(||C - LU||_F / ||C||_F, ||C - LU||_F / || |L||U| ||_F)."""
+    L, U = unpack(LU)
+    E = C - L @ U
+    e = np.linalg.norm(E)
+    return e / np.linalg.norm(C), e / np.linalg.norm(np.abs(L) @ np.abs(U))
+
+
+def gamma(n: int, u: float = U64) -> float:
+    """gamma_n = n u / (1 - n u), the constant of standard rounding-error bounds."""
+    return n * u / (1 - n * u)
+
+
+def flops_method(n: int, nrhs: int, refine_steps: int) -> float:
+    """Algorithmic flop count of one solve: 2n^3 (A G) + GENP + substitutions and
+    recovery (4 n^2 k) + refinement (6 n^2 k per step)."""
+    lu = (2.0 / 3.0) * n ** 3 - 0.5 * n ** 2 - n / 6.0
+    return 2.0 * n ** 3 + lu + 4.0 * n * n * nrhs + refine_steps * 6.0 * n * n * nrhs
