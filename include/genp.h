@@ -1,0 +1,189 @@
+/*
+ * genp.h -- C ABI of the randomized-multiplier GENP solver for AMD MI355X (gfx950).
+ *
+ * Method (Pan & Qian, "More on the Power of Randomized Matrix Multiplication"):
+ * section 1.1 solves a nonsingular system A x = b by multiplying A by a random
+ * matrix and running Gaussian elimination with no pivoting (GENP) on the
+ * product.  Here the multiplier G is applied on the right (Corollary 4.1(ii):
+ * the leading blocks of A H are nonsingular with probability 1 and well
+ * conditioned with high probability whenever A is nonsingular):
+ *
+ *     C = A G  ->  C = L U (no pivoting)  ->  Y = U^{-1} L^{-1} B  ->  X = G Y,
+ *
+ * followed by iterative refinement X += G (LU)^{-1} (B - A X) (section 7.1,
+ * Table 7.1; at most two steps in section 7.2).  G is either a dense Gaussian
+ * matrix or a Gaussian Toeplitz matrix given by its 2n-1 parameters
+ * (Definition 3.2; Toeplitz structure of section 2.3).
+ *
+ * Conventions shared by every call:
+ *  - Matrices are row-major (C order, torch-contiguous): element (i, j) of an
+ *    n x m matrix M with leading dimension ldm is M[i * ldm + j], ldm >= m.
+ *  - Every matrix/vector pointer is a DEVICE pointer on the context's device.
+ *  - Work is ordered on the HIP stream given to genp_create.  Calls that
+ *    report a numerical status (genp_factor, genp_refine, genp_get_info)
+ *    synchronize that stream before returning; the others only enqueue work.
+ *  - Ownership: A and a dense G are BORROWED by genp_precondition and must
+ *    stay valid and unchanged until the next genp_precondition or
+ *    genp_destroy (refinement and the adjoint read them again).  Toeplitz
+ *    parameters are copied.  B, X, W, dB, dA belong to the caller.  The
+ *    working matrix C (later L \ U) and all scratch belong to the context.
+ *  - Status codes: 0 = success; > 0 = numerical outcome with defined outputs;
+ *    < 0 = caller or device error, outputs undefined.  No exception or abort
+ *    crosses this interface.
+ *  - Call order: create -> precondition -> factor -> solve / refine /
+ *    solve_backward (any number of times) -> destroy.  Out of order calls
+ *    return GENP_ESTATE.  One context serves one host thread at a time.
+ */
+#ifndef GENP_H
+#define GENP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct genp_ctx genp_ctx;
+
+/* Working precision of C = A G and of its LU factors. */
+enum {
+    GENP_F64 = 0,   /* FP64 MFMA product and factorization                        */
+    GENP_F32 = 1,   /* FP32 MFMA product and factorization, FP32 storage           */
+    GENP_BF16 = 2   /* BF16 operands with FP32 accumulation for A G and the Schur  */
+                    /* updates; panel and triangular blocks in FP32; FP32 storage  */
+};
+
+/* Kind of multiplier passed to genp_precondition. */
+enum {
+    GENP_G_DENSE = 0,     /* G: n x n dense, row-major, leading dimension ldg        */
+    GENP_G_TOEPLITZ = 1,  /* G: 2n-1 parameters p, G[i][j] = p[i - j + n - 1]        */
+    GENP_G_NONE = 2       /* no multiplier: C = A (plain GENP, for tests)            */
+};
+
+/* Refinement solvers for genp_refine. */
+enum {
+    GENP_SOLVER_LUIR = 0,   /* classical refinement: X += G (LU)^{-1} (B - A X)          */
+    GENP_SOLVER_GMRES = 1   /* FP64 GMRES on A x = r right-preconditioned by G (LU)^{-1} */
+};
+
+enum {
+    GENP_OK = 0,
+    GENP_BREAKDOWN = 1,   /* a pivot was non-finite or |u_kk| <= pivot_tol * max|C|    */
+    GENP_ENOCONV = 2,     /* refinement stopped above tol; the best X is returned      */
+    GENP_EINVAL = -1,     /* bad argument                                              */
+    GENP_EDEVICE = -2,    /* no usable gfx950 device, or a HIP call failed             */
+    GENP_ENOMEM = -3,     /* device allocation failed                                  */
+    GENP_ESTATE = -4,     /* call out of order                                         */
+    GENP_ENOTSUP = -5     /* combination not supported by this build                   */
+};
+
+#define GENP_ETA_HIST 64
+
+/* Diagnostics of the last factorization / refinement. */
+typedef struct {
+    int64_t n, nb;
+    int32_t prec, mult;
+    int64_t breakdown_col;      /* 1-based first failing pivot, 0 = none                  */
+    double min_abs_piv;         /* min |u_kk| over the n pivots (before a breakdown)      */
+    double max_abs_piv;         /* max |u_kk|                                             */
+    double max_abs_c;           /* max |c_ij| of C = A G                                  */
+    double max_abs_u;           /* max |u_ij| of the computed U                           */
+    double growth;              /* max_abs_u / max_abs_c                                  */
+    double anorm_inf;           /* ||A||_inf (computed once per precondition)             */
+    int32_t iters;              /* refinement (outer) steps taken by the last genp_refine */
+    int32_t inner_iters;        /* GMRES inner iterations of the last genp_refine         */
+    double eta;                 /* final max_j eta_j of the last genp_refine              */
+    int32_t n_eta;              /* entries of eta_hist                                    */
+    double eta_hist[GENP_ETA_HIST]; /* eta before each refinement step and at the end     */
+    double ms_precond, ms_factor, ms_solve, ms_refine, ms_backward; /* HIP-event times   */
+} genp_info;
+
+/*
+ * Create a context for n x n systems on the current HIP device.
+ *   n        >= 1.
+ *   prec     GENP_F64 / GENP_F32 / GENP_BF16.
+ *   nb       panel width of the blocked elimination: 64, 128 or 256 (0 = default 256).
+ *   stream   hipStream_t to order all work on (NULL = the null stream).
+ * Allocates the working matrix (padded to a multiple of nb) and scratch.
+ * Errors: GENP_EINVAL, GENP_EDEVICE (no gfx950 device), GENP_ENOMEM.
+ */
+int genp_create(genp_ctx** ctx, int64_t n, int prec, int nb, void* stream);
+
+/* Release everything the context owns.  NULL is accepted. */
+int genp_destroy(genp_ctx* ctx);
+
+/*
+ * C = A G (section 1.1; right multiplier per Corollary 4.1(ii)), in the
+ * context's working precision.  A: n x n FP64 (lda >= n).  mult selects G:
+ * dense (G n x n FP64, ldg >= n), Toeplitz (G = the 2n-1 FP64 parameters,
+ * ldg ignored, copied), or none (G ignored).  Also computes ||A||_inf.
+ * Resets the context to the "preconditioned" state.
+ */
+int genp_precondition(genp_ctx* ctx, const double* A, int64_t lda, int mult,
+                      const double* G, int64_t ldg);
+
+/*
+ * Blocked right-looking GENP of C in place (section 1.1; block Gaussian
+ * elimination of Theorem 2.2; each step replaces the trailing block by its
+ * Schur complement, Fact 2.1).  No pivoting, no row exchanges.
+ *   pivot_tol    breakdown threshold relative to max|C| (0 = only non-finite
+ *                or exactly zero pivots).
+ *   breakdown_col (nullable, host) receives the 1-based first failing pivot
+ *                column, 0 if none.
+ * Returns GENP_OK or GENP_BREAKDOWN (factors are then only meaningful in the
+ * columns before breakdown_col).  Synchronizes the stream.
+ */
+int genp_factor(genp_ctx* ctx, double pivot_tol, int64_t* breakdown_col);
+
+/*
+ * X = G U^{-1} L^{-1} B for nrhs right-hand sides (B: n x nrhs, ldb >= nrhs;
+ * X: n x nrhs, ldx >= nrhs; X may equal B).  FP64 arithmetic over the stored
+ * factors.  Requires a successful genp_factor.
+ */
+int genp_solve(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
+               double* X, int64_t ldx);
+
+/*
+ * Iterative refinement of X (in/out) against the original A and B in FP64:
+ * solver GENP_SOLVER_LUIR repeats R = B - A X, X += G (LU)^{-1} R (section
+ * 7.1); GENP_SOLVER_GMRES runs restarted FP64 GMRES preconditioned by the
+ * factors for the correction.  Stops when max_j eta_j <= tol or after
+ * max_iter outer steps, where eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf +
+ * ||b_j||_inf).  eta_out (nullable, host, nrhs doubles) receives the final
+ * eta_j.  Returns GENP_OK or GENP_ENOCONV (X holds the best iterate).
+ * Synchronizes the stream.
+ */
+int genp_refine(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
+                double* X, int64_t ldx, int max_iter, double tol, int solver,
+                double* eta_out);
+
+/*
+ * Adjoint of X = A^{-1} B for the loss sum(W .* X): dB = A^{-T} W computed
+ * from the stored factors as L^{-T} U^{-T} (G^T W), followed by refine_iters
+ * FP64 refinement steps against A^T; if dA is not NULL, dA = -dB X^T
+ * (n x n, ldda >= n).  W, X: n x nrhs (ldw, ldx >= nrhs); dB: n x nrhs.
+ * Requires a successful genp_factor.
+ */
+int genp_solve_backward(genp_ctx* ctx, const double* W, int64_t ldw,
+                        const double* X, int64_t ldx, int64_t nrhs,
+                        double* dB, int64_t lddb, double* dA, int64_t ldda,
+                        int refine_iters);
+
+/* Copy diagnostics (host struct).  Synchronizes the stream. */
+int genp_get_info(const genp_ctx* ctx, genp_info* info);
+
+/*
+ * Copy the n x n working matrix (C after genp_precondition, packed L \ U
+ * after genp_factor) to out (device, FP64, ldo >= n), widening FP32 storage.
+ * For tests and diagnostics.
+ */
+int genp_copy_work(const genp_ctx* ctx, double* out, int64_t ldo);
+
+/* Static description of a status code. */
+const char* genp_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENP_H */

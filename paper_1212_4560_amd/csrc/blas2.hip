@@ -1,0 +1,323 @@
+// Memory-bound kernels of the GENP path: matrix-vector products for the
+// substitutions, the recovery X = G Y and the residual B - A X (few right-hand
+// sides), norms for the
+// backward error, and small copy/fill helpers.
+//
+// Row-mode matrix-vector products give one wave per row so every load of the
+// matrix is a coalesced 512-byte run; transposed operands use one thread per
+// row and read down the columns, which is again coalesced across the wave.
+// Reductions that feed a maximum use atomicMax on the bit pattern of a
+// non-negative double: the result is exact and order independent.
+#include "common.h"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    // NaN-propagating maximum (fmax would drop a NaN)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = (w > v || isnan(w)) ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__global__ void pad_identity_kernel(T* C, long long ldc, int n, int n_pad) {
+    // rows >= n: whole row; rows < n: columns >= n
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long padcols = n_pad - n;
+    const long long top = (long long)n * padcols;
+    if (idx < top) {
+        const int i = (int)(idx / padcols), j = n + (int)(idx % padcols);
+        C[(long long)i * ldc + j] = T(0);
+        return;
+    }
+    const long long e = idx - top;
+    if (e >= padcols * (long long)n_pad) return;
+    const int i = n + (int)(e / n_pad), j = (int)(e % n_pad);
+    C[(long long)i * ldc + j] = (i == j) ? T(1) : T(0);
+}
+
+template <typename T>
+__global__ void max_abs_kernel(const T* __restrict__ X, long long ldx, int rows, int cols, int upper,
+                               unsigned long long* out) {
+    double m = 0.0;
+    const long long tot = (long long)rows * cols;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / cols), j = (int)(e % cols);
+        if (upper && j < i) continue;
+        const double a = fabs((double)X[(long long)i * ldx + j]);
+        m = (a > m || isnan(a)) ? a : m;
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+}
+
+__global__ void row_abs_sum_max_kernel(const double* __restrict__ A, long long lda, int n,
+                                       unsigned long long* out) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const double* r = A + (long long)row * lda;
+    double s = 0.0;
+    for (int k = lane; k < n; k += 64) s += fabs(r[k]);
+    s = wave_sum(s);
+    if (lane == 0) atomic_max_nonneg(out, s);
+}
+
+__global__ void col_abs_max_kernel(const double* __restrict__ X, long long ldx, int rows, int cols,
+                                   unsigned long long* out) {
+    // block: 256 threads = cols-strided over a chunk of rows
+    const int c = threadIdx.x % cols;
+    const int rstart = blockIdx.x * (blockDim.x / cols) + threadIdx.x / cols;
+    const int rstep = gridDim.x * (blockDim.x / cols);
+    if (threadIdx.x >= (blockDim.x / cols) * cols) return;
+    double m = 0.0;
+    for (int i = rstart; i < rows; i += rstep) {
+        const double a = fabs(X[(long long)i * ldx + c]);
+        m = (a > m || isnan(a)) ? a : m;
+    }
+    atomic_max_nonneg(out + c, m);
+}
+
+template <typename T>
+__global__ void copy_work_kernel(const T* __restrict__ C, long long ldc, int n, double* __restrict__ out,
+                                 long long ldo) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * n) return;
+    const int i = (int)(e / n), j = (int)(e % n);
+    out[(long long)i * ldo + j] = (double)C[(long long)i * ldc + j];
+}
+
+__global__ void copy2d_kernel(const double* __restrict__ s, long long lds, double* __restrict__ d,
+                              long long ldd, int rows, int cols) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    d[(long long)i * ldd + j] = s[(long long)i * lds + j];
+}
+
+__global__ void axpy2d_kernel(double alpha, const double* __restrict__ x, long long ldx,
+                              double* __restrict__ y, long long ldy, int rows, int cols) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    y[(long long)i * ldy + j] += alpha * x[(long long)i * ldx + j];
+}
+
+__global__ void fill2d_kernel(double v, double* __restrict__ x, long long ldx, int rows, int cols) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    x[(long long)i * ldx + j] = v;
+}
+
+// Row mode: one wave per output row, NR right-hand sides (NR <= 4).
+template <int NR, int AMODE, typename TA>
+__global__ void __launch_bounds__(256)
+gemv_row_kernel(int M, int K, double alpha, const TA* __restrict__ A, long long lda,
+                const double* __restrict__ X, long long ldx, double beta, const double* Yin,
+                long long ldyi, double* Y, long long ldy) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= M) return;
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    const TA* ar = (AMODE == OP_TOEP) ? A + (long long)row + lda - 1 : A + (long long)row * lda;
+    int k = lane;
+    for (; k + 192 < K; k += 256) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            a[u] = (AMODE == OP_TOEP) ? (double)ar[-(long long)(k + 64 * u)] : (double)ar[k + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], X[(long long)(k + 64 * u) * ldx + c], acc[c]);
+    }
+    for (; k < K; k += 64) {
+        const double a = (AMODE == OP_TOEP) ? (double)ar[-(long long)k] : (double)ar[k];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = fma(a, X[(long long)k * ldx + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane < NR) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            if (c == lane) v = acc[c];
+        v *= alpha;
+        if (beta != 0.0) v += beta * Yin[(long long)row * ldyi + lane];
+        Y[(long long)row * ldy + lane] = v;
+    }
+}
+
+// Column mode for transposed operands: A(i, k) = A[k * lda + i], one thread per row.
+template <int NR, typename TA>
+__global__ void __launch_bounds__(256)
+gemv_col_kernel(int M, int K, double alpha, const TA* __restrict__ A, long long lda,
+                const double* __restrict__ X, long long ldx, double beta, const double* Yin,
+                long long ldyi, double* Y, long long ldy) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= M) return;
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    int k = 0;
+    for (; k + 3 < K; k += 4) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = (double)A[(long long)(k + u) * lda + row];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], X[(long long)(k + u) * ldx + c], acc[c]);
+    }
+    for (; k < K; ++k) {
+        const double a = (double)A[(long long)k * lda + row];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = fma(a, X[(long long)k * ldx + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        double v = alpha * acc[c];
+        if (beta != 0.0) v += beta * Yin[(long long)row * ldyi + c];
+        Y[(long long)row * ldy + c] = v;
+    }
+}
+
+template <int NR, typename TA>
+hipError_t gemv_dispatch_t(int M, int K, double alpha, const TA* A, long long lda, int amode,
+                           const double* X, long long ldx, double beta, const double* Yin,
+                           long long ldyi, double* Y, long long ldy, hipStream_t s) {
+    if (amode == OP_T) {
+        hipLaunchKernelGGL((gemv_col_kernel<NR, TA>), dim3((M + 255) / 256), dim3(256), 0, s, M, K,
+                           alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
+    } else if (amode == OP_N) {
+        hipLaunchKernelGGL((gemv_row_kernel<NR, OP_N, TA>), dim3((M + 3) / 4), dim3(256), 0, s, M, K,
+                           alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
+    } else {
+        hipLaunchKernelGGL((gemv_row_kernel<NR, OP_TOEP, TA>), dim3((M + 3) / 4), dim3(256), 0, s, M,
+                           K, alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
+    }
+    return hipGetLastError();
+}
+
+template <typename TA>
+hipError_t gemv_dispatch(int M, int K, int nr, double alpha, const TA* A, long long lda, int amode,
+                         const double* X, long long ldx, double beta, const double* Yin,
+                         long long ldyi, double* Y, long long ldy, hipStream_t s) {
+    switch (nr) {
+        case 1: return gemv_dispatch_t<1>(M, K, alpha, A, lda, amode, X, ldx, beta, Yin, ldyi, Y, ldy, s);
+        case 2: return gemv_dispatch_t<2>(M, K, alpha, A, lda, amode, X, ldx, beta, Yin, ldyi, Y, ldy, s);
+        case 3: return gemv_dispatch_t<3>(M, K, alpha, A, lda, amode, X, ldx, beta, Yin, ldyi, Y, ldy, s);
+        case 4: return gemv_dispatch_t<4>(M, K, alpha, A, lda, amode, X, ldx, beta, Yin, ldyi, Y, ldy, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_pad_identity(int prec, void* C, long long ldc, int n, int n_pad, hipStream_t s) {
+    if (n_pad <= n) return hipSuccess;
+    const long long tot = (long long)n * (n_pad - n) + (long long)(n_pad - n) * n_pad;
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(pad_identity_kernel<double>, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+                           (double*)C, ldc, n, n_pad);
+    else
+        hipLaunchKernelGGL(pad_identity_kernel<float>, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+                           (float*)C, ldc, n, n_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_abs(int prec, const void* X, long long ldx, int rows, int cols, int upper,
+                          unsigned long long* out, hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<long long>(blocks_for(tot, 256), 4096);
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(max_abs_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)X, ldx,
+                           rows, cols, upper, out);
+    else
+        hipLaunchKernelGGL(max_abs_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)X, ldx, rows,
+                           cols, upper, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_abs_sum_max(const double* A, long long lda, int n, unsigned long long* out,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(row_abs_sum_max_kernel, dim3((n + 3) / 4), dim3(256), 0, s, A, lda, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_abs_max(const double* X, long long ldx, int rows, int cols,
+                              unsigned long long* out, hipStream_t s) {
+    if (cols <= 0 || cols > 256 || rows <= 0) return cols > 256 ? hipErrorInvalidValue : hipSuccess;
+    const int per = 256 / cols;
+    const unsigned g = (unsigned)std::min<long long>((rows + per - 1) / per, 1024);
+    hipLaunchKernelGGL(col_abs_max_kernel, dim3(g), dim3(256), 0, s, X, ldx, rows, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_work(int prec, const void* C, long long ldc, int n, double* out, long long ldo,
+                            hipStream_t s) {
+    const long long tot = (long long)n * n;
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(copy_work_kernel<double>, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+                           (const double*)C, ldc, n, out, ldo);
+    else
+        hipLaunchKernelGGL(copy_work_kernel<float>, dim3(blocks_for(tot, 256)), dim3(256), 0, s,
+                           (const float*)C, ldc, n, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy2d(const double* src, long long lds, double* dst, long long ldd, int rows, int cols,
+                         hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy2d_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, src, lds, dst, ldd,
+                       rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy2d(double alpha, const double* X, long long ldx, double* Y, long long ldy, int rows,
+                         int cols, hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axpy2d_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, alpha, X, ldx, Y, ldy,
+                       rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill2d(double v, double* X, long long ldx, int rows, int cols, hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill2d_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, v, X, ldx, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_f64(int M, int K, int nrhs, double alpha, const void* A, long long lda, int amode,
+                           int a_f32, const double* X, long long ldx, double beta, const double* Yin,
+                           long long ldyi, double* Y, long long ldy, hipStream_t s) {
+    if (M <= 0 || nrhs <= 0) return hipSuccess;
+    if (a_f32)
+        return gemv_dispatch<float>(M, K, nrhs, alpha, (const float*)A, lda, amode, X, ldx, beta, Yin,
+                                    ldyi, Y, ldy, s);
+    return gemv_dispatch<double>(M, K, nrhs, alpha, (const double*)A, lda, amode, X, ldx, beta, Yin, ldyi,
+                                 Y, ldy, s);
+}

@@ -1,0 +1,112 @@
+// Shared device helpers and launcher declarations of the GENP HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+// Operand access of a GEMM operand (i = row, k = column of the logical operand).
+enum OpMode : int {
+    OP_N = 0,     // row-major: X[i * ld + k]
+    OP_T = 1,     // transposed storage: X[k * ld + i]
+    OP_TOEP = 2   // Toeplitz: X(i, k) = p[i - k + t - 1], t = ld, 2t-1 parameters
+};
+
+// Working precisions (mirror of the public enum).
+enum : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+// Per-panel pivot statistics written by the diagonal-block kernels.
+struct PanelStats {
+    double min_abs;       // min |u_kk| over the valid pivots of the block
+    double max_abs;       // max |u_kk|
+    long long first_bad;  // global 0-based index of the first failing pivot, or -1
+    long long pad;
+};
+
+// Monotone encoding of a non-negative double (or NaN) for atomicMax on its bits.
+__device__ inline void atomic_max_nonneg(unsigned long long* addr, double v) {
+    atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline int xcd_remap(int bid, int total) {
+    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of tiles so neighbouring tiles share its L2.
+    const int x = bid & 7, q = total >> 3, r = total & 7;
+    return x * q + (x < r ? x : r) + (bid >> 3);
+}
+
+// ---------------------------------------------------------------- launchers ---
+struct GemmF64Args {
+    int M, N, K;
+    const double* A; long long lda; int amode;
+    const double* B; long long ldb; int bmode;
+    double alpha, beta;
+    const double* Cin; long long ldci;   // read only when beta != 0
+    double* D; long long ldd;
+    int ksplit;                          // > 1: D receives ksplit partial products
+    long long split_stride;              //      at D + s * split_stride (beta ignored)
+};
+// tile: 0 = 128x128 (2x2 waves), 1 = 256x64 (4x1), 2 = 64x256 (1x4), 3 = 64x64,
+//       4 = 128x64 (2x1), 5 = 64x128 (1x2)
+hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s);
+
+// D = alpha * sum_s P[s] + beta * Cin over an M x N block (split-K reduction)
+hipError_t launch_splitk_reduce_f64(int M, int N, int ksplit, const double* P, long long ldp,
+                                    long long split_stride, double alpha, double beta,
+                                    const double* Cin, long long ldci, double* D, long long ldd,
+                                    hipStream_t s);
+
+// GEMM in FP32 storage: C(fp32) = A(fp64->fp32) * B(fp64->fp32) or fp32 operands.
+struct GemmLpArgs {
+    int M, N, K;
+    const void* A; long long lda; int amode; int a_f64;   // a_f64: operand stored as FP64
+    const void* B; long long ldb; int bmode; int b_f64;
+    float alpha, beta;
+    const float* Cin; long long ldci;
+    float* D; long long ldd;
+    int bf16;                            // 1: round operands to BF16, BF16 MFMA, FP32 accumulate
+};
+hipError_t launch_gemm_lp(const GemmLpArgs& a, int tile, hipStream_t s);
+
+// Diagonal block LU (no pivoting) in place, one workgroup; records PanelStats.
+hipError_t launch_diag_lu(int prec, void* Dblk, long long ldd, int nb, int nvalid,
+                          long long col0, const double* maxc, double pivot_tol,
+                          PanelStats* st, hipStream_t s);
+// Fill the padding of an n_pad x n_pad working matrix: zeros off the diagonal, ones on it.
+hipError_t launch_pad_identity(int prec, void* C, long long ldc, int n, int n_pad, hipStream_t s);
+hipError_t launch_max_abs(int prec, const void* X, long long ldx, int rows, int cols, int upper_only,
+                          unsigned long long* out_bits, hipStream_t s);
+hipError_t launch_row_abs_sum_max(const double* A, long long lda, int n,
+                                  unsigned long long* out_bits, hipStream_t s);
+hipError_t launch_col_abs_max(const double* X, long long ldx, int rows, int cols,
+                              unsigned long long* out_bits, hipStream_t s);
+hipError_t launch_copy_work(int prec, const void* C, long long ldc, int n, double* out,
+                            long long ldo, hipStream_t s);
+hipError_t launch_copy2d(const double* src, long long lds, double* dst, long long ldd,
+                         int rows, int cols, hipStream_t s);
+hipError_t launch_axpy2d(double alpha, const double* X, long long ldx, double* Y, long long ldy,
+                         int rows, int cols, hipStream_t s);
+hipError_t launch_fill2d(double v, double* X, long long ldx, int rows, int cols, hipStream_t s);
+
+// y[i][c] = beta * yin[i][c] + alpha * sum_k op(A)(i, k) x[k][c] for nrhs <= 4 (one wave per row).
+hipError_t launch_gemv_f64(int M, int K, int nrhs, double alpha,
+                           const void* A, long long lda, int amode, int a_f32,
+                           const double* X, long long ldx, double beta,
+                           const double* Yin, long long ldyi, double* Y, long long ldy,
+                           hipStream_t s);
+
+// Triangular block solves by substitution.  T is nb x nb (nb <= 256, multiple of 16),
+// X holds ncols right-hand sides and is overwritten with the solution.
+enum TrsmKind : int {
+    TRSM_L_UNIT = 0,    // L X = B, L unit lower (row-major T), X nb x ncols row-major
+    TRSM_U = 1,         // U X = B, U upper
+    TRSM_UT = 2,        // U^T X = B (T holds U)
+    TRSM_LT_UNIT = 3,   // L^T X = B (T holds unit lower L)
+    TRSM_RIGHT_U = 4    // X U = B with X ncols x nb row-major (rows are the right-hand sides)
+};
+hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long ldt, int nb, void* X,
+                       long long ldx, int ncols, hipStream_t s);

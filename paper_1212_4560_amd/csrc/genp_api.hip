@@ -1,0 +1,641 @@
+// Host side of the GENP library: the C ABI of include/genp.h, context and
+// workspace management, and the orchestration of the kernels into the method's
+// steps (section 1.1): C = A G, blocked GENP, substitutions, recovery X = G Y,
+// refinement (section 7.1) and the adjoint solve.
+#include "../../include/genp.h"
+#include "common.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#define HIPCK(x)                                      \
+    do {                                              \
+        hipError_t e_ = (x);                          \
+        if (e_ != hipSuccess) return GENP_EDEVICE;    \
+    } while (0)
+#define CK(x)                                         \
+    do {                                              \
+        int r_ = (x);                                 \
+        if (r_ != GENP_OK) return r_;                 \
+    } while (0)
+
+namespace {
+
+enum { ST_CREATED = 0, ST_PRECOND = 1, ST_FACTORED = 2, ST_BROKEN = 3 };
+enum { EV_PRE = 0, EV_FAC = 1, EV_SOL = 2, EV_REF = 3, EV_BWD = 4, EV_N = 5 };
+
+// device reduction slots (bit patterns of non-negative doubles)
+enum { R_MAXC = 0, R_MAXU = 1, R_ANORM = 2, R_COLS = 8 };   // R_COLS: 3 * 256 per-column maxima
+
+}  // namespace
+
+struct genp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0, n_pad = 0, nb = 256;
+    int prec = GENP_F64;
+    void* C = nullptr;
+    int64_t ldc = 0;
+    PanelStats* stats = nullptr;
+    unsigned long long* red = nullptr;
+    // borrowed / copied inputs
+    const double* A = nullptr;
+    int64_t lda = 0;
+    int mult = GENP_G_DENSE;
+    const double* G = nullptr;
+    int64_t ldg = 0;
+    double* p = nullptr;       // Toeplitz parameters (owned copy)
+    double* p_rev = nullptr;   // reversed: the parameters of G^T
+    // right-hand-side scratch, capacity kcap columns
+    int64_t kcap = 0;
+    double* Z = nullptr;       // n_pad x kcap
+    double* R = nullptr;       // n_pad x kcap
+    double* Dx = nullptr;      // n_pad x kcap
+    double* part = nullptr;    // split-K partials: KSPLIT_MAX x n_pad x kcap
+    int state = ST_CREATED;
+    genp_info info{};
+    hipEvent_t ev0[EV_N]{}, ev1[EV_N]{};
+    bool ev_used[EV_N]{};
+    double anorm = 0.0;
+};
+
+namespace {
+
+constexpr int KSPLIT_MAX = 8;
+
+size_t esize(int prec) { return prec == GENP_F64 ? 8 : 4; }
+
+int ensure_rhs(genp_ctx* c, int64_t k) {
+    if (k <= c->kcap) return GENP_OK;
+    const int64_t cap = std::max<int64_t>(k, 4);
+    hipFree(c->Z);
+    hipFree(c->R);
+    hipFree(c->Dx);
+    hipFree(c->part);
+    c->Z = c->R = c->Dx = c->part = nullptr;
+    c->kcap = 0;
+    const size_t sz = (size_t)c->n_pad * cap * sizeof(double);
+    if (hipMalloc(&c->Z, sz) != hipSuccess || hipMalloc(&c->R, sz) != hipSuccess ||
+        hipMalloc(&c->Dx, sz) != hipSuccess || hipMalloc(&c->part, sz * KSPLIT_MAX) != hipSuccess)
+        return GENP_ENOMEM;
+    c->kcap = cap;
+    return GENP_OK;
+}
+
+void ev_begin(genp_ctx* c, int e) {
+    hipEventRecord(c->ev0[e], c->stream);
+}
+void ev_end(genp_ctx* c, int e) {
+    hipEventRecord(c->ev1[e], c->stream);
+    c->ev_used[e] = true;
+}
+
+double bits_to_double(unsigned long long b) {
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+// y (M x k) = beta * yin + alpha * op(A) (M x K) * X (K x k); FP64 arithmetic.
+// Few right-hand sides: one wave per row; more: FP64 MFMA with split-K.
+int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_t lda, int amode,
+           int a_f32, const double* X, int64_t ldx, double beta, const double* Yin, int64_t ldyi,
+           double* Y, int64_t ldy) {
+    if (M <= 0 || k <= 0) return GENP_OK;
+    if (K <= 0) {
+        if (beta == 0.0) HIPCK(launch_fill2d(0.0, Y, ldy, M, k, c->stream));
+        else if (beta != 1.0 || Yin != Y) return GENP_ENOTSUP;
+        return GENP_OK;
+    }
+    if (k <= 4) {
+        HIPCK(launch_gemv_f64(M, K, k, alpha, A, lda, amode, a_f32, X, ldx, beta, Yin, ldyi, Y, ldy,
+                              c->stream));
+        return GENP_OK;
+    }
+    if (a_f32) return GENP_ENOTSUP;
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        const int kc = std::min(64, k - c0);
+        GemmF64Args g{};
+        g.M = M;
+        g.N = kc;
+        g.K = K;
+        g.A = (const double*)A;
+        g.lda = lda;
+        g.amode = amode;
+        g.B = X + c0;
+        g.ldb = ldx;
+        g.bmode = OP_N;
+        g.alpha = alpha;
+        g.beta = beta;
+        g.Cin = Yin ? Yin + c0 : nullptr;
+        g.ldci = ldyi;
+        const int ntm = (M + 127) / 128;
+        int ks = std::max(1, std::min(KSPLIT_MAX, (512 + ntm - 1) / ntm));
+        ks = std::min(ks, std::max(1, K / 256));
+        if (ks > 1 && (int64_t)M * kc * ks > c->n_pad * c->kcap * KSPLIT_MAX) ks = 1;
+        if (ks == 1) {
+            g.D = Y + c0;
+            g.ldd = ldy;
+            g.ksplit = 1;
+            HIPCK(launch_gemm_f64(g, 4, c->stream));
+        } else {
+            g.D = c->part;
+            g.ldd = kc;
+            g.ksplit = ks;
+            g.split_stride = (long long)M * kc;
+            HIPCK(launch_gemm_f64(g, 4, c->stream));
+            HIPCK(launch_splitk_reduce_f64(M, kc, ks, c->part, kc, (long long)M * kc, 1.0, beta,
+                                           Yin ? Yin + c0 : nullptr, ldyi, Y + c0, ldy, c->stream));
+        }
+    }
+    return GENP_OK;
+}
+
+// Z (n_pad x k, ldz) := U^{-1} L^{-1} Z, block by block: substitution with the
+// diagonal block, then the block column below (above) updates the remaining rows.
+int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
+    const int64_t nb = c->nb, nblk = c->n_pad / nb;
+    const int f32 = c->prec != GENP_F64;
+    const size_t es = esize(c->prec);
+    const char* Cb = (const char*)c->C;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t r0 = b * nb;
+        HIPCK(launch_trsm(TRSM_L_UNIT, f32, 0, Cb + (r0 * c->ldc + r0) * es, c->ldc, (int)nb, Z + r0 * ldz,
+                          ldz, k, c->stream));
+        const int64_t below = c->n_pad - r0 - nb;
+        if (below > 0) {
+            const void* Lp = Cb + ((r0 + nb) * c->ldc + r0) * es;
+            CK(skinny(c, (int)below, (int)nb, k, -1.0, Lp, c->ldc, OP_N, f32, Z + r0 * ldz, ldz, 1.0,
+                      Z + (r0 + nb) * ldz, ldz, Z + (r0 + nb) * ldz, ldz));
+        }
+    }
+    for (int64_t b = nblk - 1; b >= 0; --b) {
+        const int64_t r0 = b * nb;
+        HIPCK(launch_trsm(TRSM_U, f32, 0, Cb + (r0 * c->ldc + r0) * es, c->ldc, (int)nb, Z + r0 * ldz, ldz,
+                          k, c->stream));
+        if (r0 > 0) {
+            const void* Up = Cb + r0 * es;
+            CK(skinny(c, (int)r0, (int)nb, k, -1.0, Up, c->ldc, OP_N, f32, Z + r0 * ldz, ldz, 1.0, Z, ldz,
+                      Z, ldz));
+        }
+    }
+    return GENP_OK;
+}
+
+// Z (n_pad x k) := L^{-T} U^{-T} Z (the transposed solve of the adjoint).
+int lu_solve_trans_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
+    const int64_t nb = c->nb, nblk = c->n_pad / nb;
+    const int f32 = c->prec != GENP_F64;
+    const size_t es = esize(c->prec);
+    const char* Cb = (const char*)c->C;
+    // U^T is lower triangular: forward substitution
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t r0 = b * nb;
+        HIPCK(launch_trsm(TRSM_UT, f32, 0, Cb + (r0 * c->ldc + r0) * es, c->ldc, (int)nb, Z + r0 * ldz, ldz,
+                          k, c->stream));
+        const int64_t below = c->n_pad - r0 - nb;
+        if (below > 0) {
+            // (U^T)(r0+nb+i, r0+t) = U(r0+t, r0+nb+i): transposed access of the U row block
+            const void* Up = Cb + (r0 * c->ldc + r0 + nb) * es;
+            CK(skinny(c, (int)below, (int)nb, k, -1.0, Up, c->ldc, OP_T, f32, Z + r0 * ldz, ldz, 1.0,
+                      Z + (r0 + nb) * ldz, ldz, Z + (r0 + nb) * ldz, ldz));
+        }
+    }
+    // L^T is unit upper triangular: backward substitution
+    for (int64_t b = nblk - 1; b >= 0; --b) {
+        const int64_t r0 = b * nb;
+        HIPCK(launch_trsm(TRSM_LT_UNIT, f32, 0, Cb + (r0 * c->ldc + r0) * es, c->ldc, (int)nb, Z + r0 * ldz,
+                          ldz, k, c->stream));
+        if (r0 > 0) {
+            // (L^T)(i, r0+t) = L(r0+t, i) for i < r0
+            const void* Lp = Cb + (r0 * c->ldc) * es;
+            CK(skinny(c, (int)r0, (int)nb, k, -1.0, Lp, c->ldc, OP_T, f32, Z + r0 * ldz, ldz, 1.0, Z, ldz,
+                      Z, ldz));
+        }
+    }
+    return GENP_OK;
+}
+
+// Y (n x k) = alpha * G Z + beta * Yin, or with G^T (trans), for the stored multiplier.
+int apply_g(genp_ctx* c, int trans, int k, double alpha, const double* Zin, int64_t ldz, double beta,
+            const double* Yin, int64_t ldyi, double* Y, int64_t ldy) {
+    const int n = (int)c->n;
+    if (c->mult == GENP_G_NONE) {
+        if (beta != 0.0 || alpha != 1.0) return GENP_ENOTSUP;
+        HIPCK(launch_copy2d(Zin, ldz, Y, ldy, n, k, c->stream));
+        return GENP_OK;
+    }
+    if (c->mult == GENP_G_TOEPLITZ)
+        return skinny(c, n, n, k, alpha, trans ? c->p_rev : c->p, n, OP_TOEP, 0, Zin, ldz, beta, Yin, ldyi,
+                      Y, ldy);
+    return skinny(c, n, n, k, alpha, c->G, c->ldg, trans ? OP_T : OP_N, 0, Zin, ldz, beta, Yin, ldyi, Y,
+                  ldy);
+}
+
+// X (n x k) = G U^{-1} L^{-1} Bin, using Z as workspace (n_pad x k, ldz = k).
+int solve_into(genp_ctx* c, const double* Bin, int64_t ldb, int k, double* X, int64_t ldx) {
+    double* Z = c->Z;
+    const int64_t ldz = k;
+    HIPCK(launch_copy2d(Bin, ldb, Z, ldz, (int)c->n, k, c->stream));
+    if (c->n_pad > c->n)
+        HIPCK(launch_fill2d(0.0, Z + c->n * ldz, ldz, (int)(c->n_pad - c->n), k, c->stream));
+    CK(lu_solve_inplace(c, Z, ldz, k));
+    return apply_g(c, 0, k, 1.0, Z, ldz, 0.0, nullptr, 0, X, ldx);
+}
+
+// eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf), host result.
+int backward_error(genp_ctx* c, const double* R, int64_t ldr, const double* X, int64_t ldx,
+                   const double* B, int64_t ldb, int k, std::vector<double>& eta) {
+    unsigned long long* cols = c->red + R_COLS;
+    HIPCK(hipMemsetAsync(cols, 0, sizeof(unsigned long long) * 3 * 256, c->stream));
+    HIPCK(launch_col_abs_max(R, ldr, (int)c->n, k, cols, c->stream));
+    HIPCK(launch_col_abs_max(X, ldx, (int)c->n, k, cols + 256, c->stream));
+    HIPCK(launch_col_abs_max(B, ldb, (int)c->n, k, cols + 512, c->stream));
+    std::vector<unsigned long long> h(3 * 256);
+    HIPCK(hipMemcpyAsync(h.data(), cols, sizeof(unsigned long long) * 3 * 256, hipMemcpyDeviceToHost,
+                         c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    eta.resize(k);
+    for (int j = 0; j < k; ++j) {
+        const double r = bits_to_double(h[j]), x = bits_to_double(h[256 + j]), b = bits_to_double(h[512 + j]);
+        const double den = c->anorm * x + b;
+        eta[j] = (den > 0) ? r / den : (r > 0 ? INFINITY : 0.0);
+        if (isnan(r) || isnan(x)) eta[j] = NAN;
+    }
+    return GENP_OK;
+}
+
+double max_of(const std::vector<double>& v) {
+    double m = 0.0;
+    for (double e : v) {
+        if (isnan(e)) return NAN;
+        m = std::max(m, e);
+    }
+    return m;
+}
+
+int check_ctx(const genp_ctx* c) {
+    if (!c) return GENP_EINVAL;
+    return (hipSetDevice(c->device) == hipSuccess) ? GENP_OK : GENP_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* genp_strerror(int s) {
+    switch (s) {
+        case GENP_OK: return "ok";
+        case GENP_BREAKDOWN: return "breakdown: a pivot of the elimination without pivoting failed";
+        case GENP_ENOCONV: return "refinement did not reach the requested backward error";
+        case GENP_EINVAL: return "invalid argument";
+        case GENP_EDEVICE: return "no usable gfx950 device, or a HIP call failed";
+        case GENP_ENOMEM: return "device allocation failed";
+        case GENP_ESTATE: return "call out of order";
+        case GENP_ENOTSUP: return "combination not supported";
+        default: return "unknown status";
+    }
+}
+
+int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
+    if (!out) return GENP_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > (1 << 20)) return GENP_EINVAL;
+    if (prec != GENP_F64 && prec != GENP_F32 && prec != GENP_BF16) return GENP_EINVAL;
+    if (nb == 0) nb = 256;
+    if (nb != 64 && nb != 128 && nb != 256) return GENP_EINVAL;
+    int dev = 0, cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt < 1) return GENP_EDEVICE;
+    if (hipGetDevice(&dev) != hipSuccess) return GENP_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GENP_EDEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GENP_EDEVICE;
+    genp_ctx* c = new (std::nothrow) genp_ctx();
+    if (!c) return GENP_ENOMEM;
+    c->device = dev;
+    c->stream = (hipStream_t)stream;
+    c->n = n;
+    c->nb = nb;
+    c->prec = prec;
+    c->n_pad = (n + nb - 1) / nb * nb;
+    c->ldc = c->n_pad;
+    const size_t nblk = c->n_pad / nb;
+    bool ok = hipMalloc(&c->C, (size_t)c->n_pad * c->ldc * esize(prec)) == hipSuccess &&
+              hipMalloc(&c->stats, nblk * sizeof(PanelStats)) == hipSuccess &&
+              hipMalloc(&c->red, (R_COLS + 3 * 256) * sizeof(unsigned long long)) == hipSuccess;
+    for (int e = 0; ok && e < EV_N; ++e)
+        ok = hipEventCreate(&c->ev0[e]) == hipSuccess && hipEventCreate(&c->ev1[e]) == hipSuccess;
+    if (ok) ok = ensure_rhs(c, 4) == GENP_OK;
+    if (!ok) {
+        genp_destroy(c);
+        return GENP_ENOMEM;
+    }
+    c->info.n = n;
+    c->info.nb = nb;
+    c->info.prec = prec;
+    *out = c;
+    return GENP_OK;
+}
+
+int genp_destroy(genp_ctx* c) {
+    if (!c) return GENP_OK;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    hipFree(c->C);
+    hipFree(c->stats);
+    hipFree(c->red);
+    hipFree(c->p);
+    hipFree(c->p_rev);
+    hipFree(c->Z);
+    hipFree(c->R);
+    hipFree(c->Dx);
+    hipFree(c->part);
+    for (int e = 0; e < EV_N; ++e) {
+        if (c->ev0[e]) hipEventDestroy(c->ev0[e]);
+        if (c->ev1[e]) hipEventDestroy(c->ev1[e]);
+    }
+    delete c;
+    return GENP_OK;
+}
+
+int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const double* G, int64_t ldg) {
+    CK(check_ctx(c));
+    const int64_t n = c->n;
+    if (!A || lda < n) return GENP_EINVAL;
+    if (mult != GENP_G_DENSE && mult != GENP_G_TOEPLITZ && mult != GENP_G_NONE) return GENP_EINVAL;
+    if (mult != GENP_G_NONE && !G) return GENP_EINVAL;
+    if (mult == GENP_G_DENSE && ldg < n) return GENP_EINVAL;
+    if (c->prec != GENP_F64) return GENP_ENOTSUP;
+    c->state = ST_CREATED;
+    c->A = A;
+    c->lda = lda;
+    c->mult = mult;
+    c->G = (mult == GENP_G_DENSE) ? G : nullptr;
+    c->ldg = ldg;
+    ev_begin(c, EV_PRE);
+    if (mult == GENP_G_TOEPLITZ) {
+        if (!c->p) {
+            if (hipMalloc(&c->p, (2 * n - 1) * sizeof(double)) != hipSuccess ||
+                hipMalloc(&c->p_rev, (2 * n - 1) * sizeof(double)) != hipSuccess)
+                return GENP_ENOMEM;
+        }
+        HIPCK(hipMemcpyAsync(c->p, G, (2 * n - 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        // G^T(i, k) = G(k, i) = p[k - i + n - 1] = p_rev[i - k + n - 1] with p_rev[t] = p[2n - 2 - t]
+        HIPCK(launch_copy2d(G, 1, c->p_rev + (2 * n - 2), -1, (int)(2 * n - 1), 1, c->stream));
+    }
+    HIPCK(hipMemsetAsync(c->red, 0, sizeof(unsigned long long) * R_COLS, c->stream));
+    if (mult == GENP_G_NONE) {
+        HIPCK(launch_copy2d(A, lda, (double*)c->C, c->ldc, (int)n, (int)n, c->stream));
+    } else {
+        GemmF64Args g{};
+        g.M = g.N = g.K = (int)n;
+        g.A = A;
+        g.lda = lda;
+        g.amode = OP_N;
+        if (mult == GENP_G_DENSE) {
+            g.B = G;
+            g.ldb = ldg;
+            g.bmode = OP_N;
+        } else {
+            g.B = c->p;
+            g.ldb = n;
+            g.bmode = OP_TOEP;
+        }
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        g.D = (double*)c->C;
+        g.ldd = c->ldc;
+        g.ksplit = 1;
+        HIPCK(launch_gemm_f64(g, 0, c->stream));
+    }
+    HIPCK(launch_pad_identity(c->prec, c->C, c->ldc, (int)n, (int)c->n_pad, c->stream));
+    HIPCK(launch_max_abs(c->prec, c->C, c->ldc, (int)n, (int)n, 0, c->red + R_MAXC, c->stream));
+    HIPCK(launch_row_abs_sum_max(A, lda, (int)n, c->red + R_ANORM, c->stream));
+    ev_end(c, EV_PRE);
+    unsigned long long h[3];
+    HIPCK(hipMemcpyAsync(h, c->red, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->anorm = bits_to_double(h[R_ANORM]);
+    c->info.max_abs_c = bits_to_double(h[R_MAXC]);
+    c->info.anorm_inf = c->anorm;
+    c->info.mult = mult;
+    c->state = ST_PRECOND;
+    return GENP_OK;
+}
+
+int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
+    CK(check_ctx(c));
+    if (c->state != ST_PRECOND) return GENP_ESTATE;
+    if (!(pivot_tol >= 0.0)) return GENP_EINVAL;
+    const int64_t nb = c->nb, np = c->n_pad, ldc = c->ldc;
+    double* C = (double*)c->C;
+    const double* maxc = (const double*)(c->red + R_MAXC);
+    ev_begin(c, EV_FAC);
+    for (int64_t k = 0; k < np; k += nb) {
+        const int64_t b = k / nb;
+        double* Dk = C + k * ldc + k;
+        const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
+        HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + b, c->stream));
+        const int64_t m = np - k - nb;
+        if (m <= 0) continue;
+        // U12 = L11^{-1} A12 and L21 = A21 U11^{-1}, in place, by substitution
+        HIPCK(launch_trsm(TRSM_L_UNIT, 0, 0, Dk, ldc, (int)nb, Dk + nb, ldc, (int)m, c->stream));
+        HIPCK(launch_trsm(TRSM_RIGHT_U, 0, 0, Dk, ldc, (int)nb, Dk + nb * ldc, ldc, (int)m, c->stream));
+        // Schur complement: A22 -= L21 U12
+        GemmF64Args g{};
+        g.ksplit = 1;
+        g.M = (int)m;
+        g.N = (int)m;
+        g.K = (int)nb;
+        g.A = Dk + nb * ldc;
+        g.lda = ldc;
+        g.amode = OP_N;
+        g.B = Dk + nb;
+        g.ldb = ldc;
+        g.bmode = OP_N;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        g.Cin = Dk + nb * ldc + nb;
+        g.ldci = ldc;
+        g.D = Dk + nb * ldc + nb;
+        g.ldd = ldc;
+        HIPCK(launch_gemm_f64(g, 0, c->stream));
+    }
+    HIPCK(launch_max_abs(c->prec, c->C, ldc, (int)c->n, (int)c->n, 1, c->red + R_MAXU, c->stream));
+    ev_end(c, EV_FAC);
+    const int64_t nblk = np / nb;
+    std::vector<PanelStats> st(nblk);
+    unsigned long long mu = 0;
+    HIPCK(hipMemcpyAsync(st.data(), c->stats, nblk * sizeof(PanelStats), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipMemcpyAsync(&mu, c->red + R_MAXU, sizeof mu, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    int64_t bad = -1;
+    double mn = INFINITY, mx = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        if (b * nb >= c->n) break;
+        mn = std::min(mn, st[b].min_abs);
+        mx = std::max(mx, st[b].max_abs);
+        if (st[b].first_bad >= 0) {
+            bad = st[b].first_bad;
+            break;
+        }
+    }
+    c->info.breakdown_col = bad >= 0 ? bad + 1 : 0;
+    c->info.min_abs_piv = mn;
+    c->info.max_abs_piv = mx;
+    c->info.max_abs_u = bits_to_double(mu);
+    c->info.growth = c->info.max_abs_c > 0 ? c->info.max_abs_u / c->info.max_abs_c : INFINITY;
+    if (breakdown_col) *breakdown_col = c->info.breakdown_col;
+    if (bad >= 0) {
+        c->state = ST_BROKEN;
+        return GENP_BREAKDOWN;
+    }
+    c->state = ST_FACTORED;
+    return GENP_OK;
+}
+
+int genp_solve(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx) {
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    if (!B || !X || nrhs < 1 || ldb < nrhs || ldx < nrhs) return GENP_EINVAL;
+    CK(ensure_rhs(c, nrhs));
+    ev_begin(c, EV_SOL);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += 256) {
+        const int k = (int)std::min<int64_t>(256, nrhs - c0);
+        CK(solve_into(c, B + c0, ldb, k, X + c0, ldx));
+    }
+    ev_end(c, EV_SOL);
+    return GENP_OK;
+}
+
+int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, int max_iter,
+                double tol, int solver, double* eta_out) {
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    if (!B || !X || nrhs < 1 || nrhs > 256 || ldb < nrhs || ldx < nrhs || max_iter < 0 || !(tol >= 0))
+        return GENP_EINVAL;
+    if (solver != GENP_SOLVER_LUIR) return GENP_ENOTSUP;
+    CK(ensure_rhs(c, nrhs));
+    const int k = (int)nrhs;
+    const int n = (int)c->n;
+    ev_begin(c, EV_REF);
+    std::vector<double> eta;
+    c->info.n_eta = 0;
+    double best = INFINITY;
+    int it = 0;
+    int status = GENP_OK;
+    for (;;) {
+        // R = B - A X
+        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, OP_N, 0, X, ldx, 1.0, B, ldb, c->R, k));
+        CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta));
+        const double e = max_of(eta);
+        if (c->info.n_eta < GENP_ETA_HIST) c->info.eta_hist[c->info.n_eta++] = e;
+        if (!(e <= best)) {
+            if (it > 0) {
+                // the last correction made things worse (or produced NaN): undo it
+                HIPCK(launch_axpy2d(-1.0, c->Dx, k, X, ldx, n, k, c->stream));
+                CK(skinny(c, n, n, k, -1.0, c->A, c->lda, OP_N, 0, X, ldx, 1.0, B, ldb, c->R, k));
+                CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta));
+                status = GENP_ENOCONV;
+                break;
+            }
+        }
+        best = std::min(best, e);
+        if (e <= tol) break;
+        if (it >= max_iter) {
+            status = (tol > 0) ? GENP_ENOCONV : GENP_OK;
+            break;
+        }
+        // Dx = G (LU)^{-1} R ; X += Dx
+        CK(solve_into(c, c->R, k, k, c->Dx, k));
+        HIPCK(launch_axpy2d(1.0, c->Dx, k, X, ldx, n, k, c->stream));
+        ++it;
+    }
+    ev_end(c, EV_REF);
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->info.iters = it;
+    c->info.inner_iters = 0;
+    c->info.eta = max_of(eta);
+    if (eta_out)
+        for (int j = 0; j < k; ++j) eta_out[j] = eta[j];
+    return status;
+}
+
+int genp_solve_backward(genp_ctx* c, const double* W, int64_t ldw, const double* X, int64_t ldx, int64_t nrhs,
+                        double* dB, int64_t lddb, double* dA, int64_t ldda, int refine_iters) {
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    if (!W || !X || !dB || nrhs < 1 || nrhs > 256 || ldw < nrhs || ldx < nrhs || lddb < nrhs ||
+        refine_iters < 0 || (dA && ldda < c->n))
+        return GENP_EINVAL;
+    CK(ensure_rhs(c, nrhs));
+    const int k = (int)nrhs, n = (int)c->n;
+    ev_begin(c, EV_BWD);
+    // dB = L^{-T} U^{-T} G^T W ; then refinement against A^T
+    for (int step = 0; step <= refine_iters; ++step) {
+        const double* rhs = W;
+        int64_t ldr = ldw;
+        if (step > 0) {
+            // R = W - A^T dB
+            CK(skinny(c, n, n, k, -1.0, c->A, c->lda, OP_T, 0, dB, lddb, 1.0, W, ldw, c->R, k));
+            rhs = c->R;
+            ldr = k;
+        }
+        // Z = G^T rhs (rows n..n_pad zero)
+        if (c->n_pad > c->n) HIPCK(launch_fill2d(0.0, c->Z + (int64_t)n * k, k, (int)(c->n_pad - n), k, c->stream));
+        CK(apply_g(c, 1, k, 1.0, rhs, ldr, 0.0, nullptr, 0, c->Z, k));
+        CK(lu_solve_trans_inplace(c, c->Z, k, k));
+        if (step == 0) HIPCK(launch_copy2d(c->Z, k, dB, lddb, n, k, c->stream));
+        else HIPCK(launch_axpy2d(1.0, c->Z, k, dB, lddb, n, k, c->stream));
+    }
+    if (dA) {
+        // dA = -dB X^T
+        GemmF64Args g{};
+        g.M = g.N = n;
+        g.K = k;
+        g.A = dB;
+        g.lda = lddb;
+        g.amode = OP_N;
+        g.B = X;
+        g.ldb = ldx;
+        g.bmode = OP_T;
+        g.alpha = -1.0;
+        g.beta = 0.0;
+        g.D = dA;
+        g.ldd = ldda;
+        g.ksplit = 1;
+        HIPCK(launch_gemm_f64(g, 0, c->stream));
+    }
+    ev_end(c, EV_BWD);
+    return GENP_OK;
+}
+
+int genp_get_info(const genp_ctx* cc, genp_info* out) {
+    genp_ctx* c = const_cast<genp_ctx*>(cc);
+    CK(check_ctx(c));
+    if (!out) return GENP_EINVAL;
+    HIPCK(hipStreamSynchronize(c->stream));
+    float ms;
+    double* slots[EV_N] = {&c->info.ms_precond, &c->info.ms_factor, &c->info.ms_solve, &c->info.ms_refine,
+                           &c->info.ms_backward};
+    for (int e = 0; e < EV_N; ++e)
+        if (c->ev_used[e] && hipEventElapsedTime(&ms, c->ev0[e], c->ev1[e]) == hipSuccess) *slots[e] = ms;
+    *out = c->info;
+    return GENP_OK;
+}
+
+int genp_copy_work(const genp_ctx* cc, double* out, int64_t ldo) {
+    genp_ctx* c = const_cast<genp_ctx*>(cc);
+    CK(check_ctx(c));
+    if (!out || ldo < c->n) return GENP_EINVAL;
+    if (c->state == ST_CREATED) return GENP_ESTATE;
+    HIPCK(launch_copy_work(c->prec, c->C, c->ldc, (int)c->n, out, ldo, c->stream));
+    return GENP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+"""Python binding of ``libgenp.so`` (ctypes): argument marshalling only.
+
+Every step of the method runs in the HIP library; torch supplies device
+memory (tensors) and the stream.  The functions mirror the C ABI of
+``include/genp.h`` one to one:
+
+    genp_create / genp_precondition / genp_factor / genp_solve /
+    genp_refine / genp_solve_backward / genp_get_info / genp_copy_work
+
+plus :func:`solve` (the whole path in one call) and :class:`GenpSolve`, a
+``torch.autograd.Function`` whose backward is the library's adjoint.
+
+There is no fallback: if the library is missing or no gfx950 device is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgenp.so")
+
+F64, F32, BF16 = 0, 1, 2
+G_DENSE, G_TOEPLITZ, G_NONE = 0, 1, 2
+SOLVER_LUIR, SOLVER_GMRES = 0, 1
+OK, BREAKDOWN, ENOCONV = 0, 1, 2
+EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP = -1, -2, -3, -4, -5
+ETA_HIST = 64
+
+PRECS = {"f64": F64, "f32": F32, "bf16": BF16}
+SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
+
+# the entry points declared in include/genp.h
+EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_factor", "genp_solve",
+           "genp_refine", "genp_solve_backward", "genp_get_info", "genp_copy_work", "genp_strerror")
+
+
+class GenpInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("nb", ctypes.c_int64),
+        ("prec", ctypes.c_int32), ("mult", ctypes.c_int32),
+        ("breakdown_col", ctypes.c_int64),
+        ("min_abs_piv", ctypes.c_double), ("max_abs_piv", ctypes.c_double),
+        ("max_abs_c", ctypes.c_double), ("max_abs_u", ctypes.c_double),
+        ("growth", ctypes.c_double), ("anorm_inf", ctypes.c_double),
+        ("iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+        ("eta", ctypes.c_double), ("n_eta", ctypes.c_int32),
+        ("eta_hist", ctypes.c_double * ETA_HIST),
+        ("ms_precond", ctypes.c_double), ("ms_factor", ctypes.c_double),
+        ("ms_solve", ctypes.c_double), ("ms_refine", ctypes.c_double),
+        ("ms_backward", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "eta_hist"}
+        d["eta_hist"] = [self.eta_hist[i] for i in range(self.n_eta)]
+        return d
+
+
+class GenpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_1212_4560_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.genp_create.argtypes = [ctypes.POINTER(vp), i64, i32, i32, vp]
+    L.genp_destroy.argtypes = [vp]
+    L.genp_precondition.argtypes = [vp, vp, i64, i32, vp, i64]
+    L.genp_factor.argtypes = [vp, dbl, ctypes.POINTER(i64)]
+    L.genp_solve.argtypes = [vp, vp, i64, i64, vp, i64]
+    L.genp_refine.argtypes = [vp, vp, i64, i64, vp, i64, i32, dbl, i32, ctypes.POINTER(dbl)]
+    L.genp_solve_backward.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp, i64, i32]
+    L.genp_get_info.argtypes = [vp, ctypes.POINTER(GenpInfo)]
+    L.genp_copy_work.argtypes = [vp, vp, i64]
+    L.genp_strerror.argtypes = [i32]
+    L.genp_strerror.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "genp_strerror":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().genp_strerror(status).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def _check(status: int, where: str, allow=(OK,)) -> int:
+    if status not in allow:
+        raise GenpError(status, where)
+    return status
+
+
+def _mat(t, name: str, rows: int, cols: Optional[int] = None):
+    """(pointer, leading dimension) of a float64 CUDA tensor with unit column stride."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name}: need a float64 CUDA tensor")
+    if t.dim() == 1:
+        if t.stride(0) != 1 or t.shape[0] != rows:
+            raise ValueError(f"{name}: bad shape/stride")
+        return t.data_ptr(), 1
+    if t.dim() != 2 or t.shape[0] != rows or (cols is not None and t.shape[1] != cols):
+        raise ValueError(f"{name}: expected shape ({rows}, {cols}), got {tuple(t.shape)}")
+    if t.stride(1) != 1 and t.shape[1] > 1:
+        raise ValueError(f"{name}: columns must be contiguous")
+    return t.data_ptr(), max(t.stride(0), t.shape[1])
+
+
+class Solver:
+    """One genp_ctx: n x n systems, a working precision and a panel width."""
+
+    def __init__(self, n: int, prec: str = "f64", nb: int = 256, stream=None):
+        import torch
+        L = load()
+        self.n = int(n)
+        self.prec = prec
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.genp_create(ctypes.byref(h), self.n, PRECS[prec], int(nb), ctypes.c_void_p(self.stream.cuda_stream)),
+               "genp_create")
+        self._h = h
+        self._keep = ()   # tensors the context borrows (A, dense G)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.genp_destroy(h)
+        self._h = None
+        self._keep = ()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def precondition(self, A, G=None, p=None):
+        """C = A G (dense G, or Toeplitz with parameters p, or no multiplier)."""
+        n = self.n
+        a, lda = _mat(A, "A", n, n)
+        if G is not None:
+            g, ldg = _mat(G, "G", n, n)
+            mult = G_DENSE
+        elif p is not None:
+            g, ldg = _mat(p, "p", 2 * n - 1)
+            mult = G_TOEPLITZ
+            ldg = n
+        else:
+            g, ldg, mult = 0, n, G_NONE
+        _check(load().genp_precondition(self._h, a, lda, mult, g, ldg), "genp_precondition")
+        self._keep = (A, G, p)
+        return self
+
+    def factor(self, pivot_tol: float = 0.0) -> int:
+        """Blocked GENP; returns the 1-based breakdown column (0 = none)."""
+        bk = ctypes.c_int64(0)
+        _check(load().genp_factor(self._h, float(pivot_tol), ctypes.byref(bk)), "genp_factor",
+               allow=(OK, BREAKDOWN))
+        return int(bk.value)
+
+    def solve(self, B, X=None):
+        import torch
+        k = B.shape[1]
+        b, ldb = _mat(B, "B", self.n)
+        if X is None:
+            X = torch.empty((self.n, k), dtype=torch.float64, device=B.device)
+        x, ldx = _mat(X, "X", self.n, k)
+        _check(load().genp_solve(self._h, b, ldb, k, x, ldx), "genp_solve")
+        return X
+
+    def refine(self, B, X, max_iter: int = 2, tol: float = 0.0, solver: str = "luir"):
+        """In-place refinement of X; returns (status, eta per column)."""
+        k = B.shape[1]
+        b, ldb = _mat(B, "B", self.n, k)
+        x, ldx = _mat(X, "X", self.n, k)
+        eta = (ctypes.c_double * k)()
+        st = _check(load().genp_refine(self._h, b, ldb, k, x, ldx, int(max_iter), float(tol),
+                                       SOLVERS[solver], eta), "genp_refine", allow=(OK, ENOCONV))
+        return st, [eta[i] for i in range(k)]
+
+    def solve_backward(self, W, X, want_dA: bool = True, refine_iters: int = 1):
+        import torch
+        k = W.shape[1]
+        w, ldw = _mat(W, "W", self.n, k)
+        x, ldx = _mat(X, "X", self.n, k)
+        dB = torch.empty((self.n, k), dtype=torch.float64, device=W.device)
+        db, lddb = _mat(dB, "dB", self.n, k)
+        dA = None
+        da, ldda = 0, self.n
+        if want_dA:
+            dA = torch.empty((self.n, self.n), dtype=torch.float64, device=W.device)
+            da, ldda = _mat(dA, "dA", self.n, self.n)
+        _check(load().genp_solve_backward(self._h, w, ldw, x, ldx, k, db, lddb, da, ldda,
+                                          int(refine_iters)), "genp_solve_backward")
+        return dB, dA
+
+    def info(self) -> dict:
+        inf = GenpInfo()
+        _check(load().genp_get_info(self._h, ctypes.byref(inf)), "genp_get_info")
+        return inf.as_dict()
+
+    def work(self):
+        """FP64 copy of the working matrix (C, or L \\ U after factor)."""
+        import torch
+        out = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda")
+        o, ldo = _mat(out, "out", self.n, self.n)
+        _check(load().genp_copy_work(self._h, o, ldo), "genp_copy_work")
+        return out
+
+
+def solve(A, B, G=None, p=None, prec: str = "f64", nb: int = 256, refine: int = 2,
+          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir"):
+    """The whole path: C = A G, GENP, substitutions, X = G Y, refinement.
+
+    Returns (X, info dict, solver object).  Raises GenpError on breakdown.
+    """
+    s = Solver(A.shape[0], prec, nb)
+    s.precondition(A, G=G, p=p)
+    bk = s.factor(pivot_tol)
+    if bk:
+        raise GenpError(BREAKDOWN, f"genp_factor (column {bk})")
+    X = s.solve(B)
+    if refine > 0:
+        s.refine(B, X, refine, tol, solver)
+    return X, s.info(), s
+
+
+def _autograd_function():
+    import torch
+
+    class GenpSolve(torch.autograd.Function):
+        """X = A^{-1} B through the randomized GENP path; backward = library adjoint.
+
+        Gradients: dB = A^{-T} gX (L^{-T} U^{-T} G^T gX plus refinement),
+        dA = -dB X^T.  The multiplier receives no gradient.
+        """
+
+        @staticmethod
+        def forward(ctx, A, B, G=None, p=None, prec="f64", nb=256, refine=2, refine_bwd=1):
+            X, _, s = solve(A.detach(), B.detach(), G=G, p=p, prec=prec, nb=nb, refine=refine)
+            ctx.solver = s
+            ctx.refine_bwd = refine_bwd
+            ctx.save_for_backward(X)
+            return X
+
+        @staticmethod
+        def backward(ctx, gX):
+            (X,) = ctx.saved_tensors
+            dB, dA = ctx.solver.solve_backward(gX.contiguous(), X, want_dA=ctx.needs_input_grad[0],
+                                               refine_iters=ctx.refine_bwd)
+            return dA, dB, None, None, None, None, None, None
+
+    return GenpSolve
+
+
+_genp_solve_cls = None
+
+
+def __getattr__(name):
+    global _genp_solve_cls
+    if name == "GenpSolve":
+        if _genp_solve_cls is None:
+            _genp_solve_cls = _autograd_function()
+        return _genp_solve_cls
+    raise AttributeError(name)

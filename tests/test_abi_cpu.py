@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every entry point of include/genp.h (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1212_4560_amd import genp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "genp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(genp_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    if not os.path.exists(genp.LIB_PATH):
+        pytest.fail("libgenp.so is not built: run `python -m paper_1212_4560_amd.build`")
+    return genp.load()
+
+
+def test_header_declares_the_abi():
+    assert _declared() == sorted(genp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    nm = os.popen(f"nm -D --defined-only {genp.LIB_PATH}").read()
+    exported = set(re.findall(r" T (genp_[a-z_]+)", nm))
+    assert set(_declared()) <= exported
+
+
+def test_strerror_covers_codes():
+    _lib()
+    for code in (0, 1, 2, -1, -2, -3, -4, -5):
+        s = genp.strerror(code)
+        assert s and "unknown" not in s
+    assert "unknown" in genp.strerror(99)
+
+
+def test_invalid_arguments_rejected_before_device():
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.genp_create(ctypes.byref(h), 0, 0, 256, None) == genp.EINVAL
+    assert L.genp_create(ctypes.byref(h), 10, 7, 256, None) == genp.EINVAL
+    assert L.genp_create(ctypes.byref(h), 10, 0, 96, None) == genp.EINVAL
+    assert L.genp_create(None, 10, 0, 256, None) == genp.EINVAL
+    assert L.genp_destroy(None) == genp.OK
+    for fn, args in (("genp_factor", (None, 0.0, None)), ("genp_get_info", (None, None)),
+                     ("genp_copy_work", (None, None, 1))):
+        assert getattr(L, fn)(*args) == genp.EINVAL
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.genp_create(ctypes.byref(h), 16, 0, 64, None) == genp.EDEVICE
+    assert not h.value

@@ -1,0 +1,306 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances are derived from the arithmetic:
+* C = A G: both sides satisfy |C_hat - C| <= gamma_n |A||G| (standard dot-product
+  bound), so they differ by at most 2 gamma_n |A||G| entrywise.
+* factors: ||C - L U||_F <= 1e-13 || |L||U| ||_F (growth-normalized backward
+  error of the elimination) and, where the leading blocks are well conditioned
+  (strongly diagonally dominant C), entrywise agreement with the oracle's
+  factors to 1e-12 relative.
+* solutions: eta_inf(x_gpu) <= 1e-14 computed by the oracle from the GPU's x,
+  and ||x_gpu - x_orc||_inf <= 10 kappa_inf(A) max(eta_gpu, eta_orc, u) ||x_orc||_inf.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import genp as og  # noqa: E402
+from paper_1212_4560_amd import genp, workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ C = A G ----
+
+@pytest.mark.parametrize("n", [1, 7, 64, 200, 256, 517])
+@pytest.mark.parametrize("mult", ["dense", "toeplitz"])
+def test_precondition_entrywise(n, mult):
+    _say(f"precondition n={n} mult={mult}")
+    g = np.random.default_rng(n)
+    A = g.standard_normal((n, n))
+    if mult == "dense":
+        G = g.standard_normal((n, n))
+        p = None
+    else:
+        p = g.standard_normal(2 * n - 1)
+        G = og.toeplitz_from_params(p, n)
+    s = genp.Solver(n, "f64", 64)
+    s.precondition(dev(A), G=dev(G) if p is None else None, p=dev(p) if p is not None else None)
+    C = host(s.work())
+    Co = og.precondition(A, G)
+    bound = 2 * og.gamma(n) * (np.abs(A) @ np.abs(G))
+    assert np.all(np.abs(C - Co) <= bound + 1e-300)
+    info = s.info()
+    assert info["max_abs_c"] == np.max(np.abs(C))
+    assert abs(info["anorm_inf"] - np.max(np.sum(np.abs(A), axis=1))) <= 1e-13 * info["anorm_inf"]
+
+
+def test_precondition_strided_inputs():
+    n = 130
+    g = np.random.default_rng(3)
+    Abig = g.standard_normal((n, n + 9))
+    Gbig = g.standard_normal((n, n + 5))
+    s = genp.Solver(n, "f64", 128)
+    s.precondition(dev(Abig)[:, :n], G=dev(Gbig)[:, :n])
+    C = host(s.work())
+    Co = Abig[:, :n] @ Gbig[:, :n]
+    assert np.all(np.abs(C - Co) <= 2 * og.gamma(n) * (np.abs(Abig[:, :n]) @ np.abs(Gbig[:, :n])))
+
+
+# ------------------------------------------------------------------ factors ----
+
+@pytest.mark.parametrize("n,nb", [(1, 64), (33, 64), (64, 64), (255, 64), (256, 256), (257, 128),
+                                  (700, 256), (1000, 128), (1031, 64)])
+def test_factor_matches_oracle_well_conditioned(n, nb):
+    """No multiplier, strongly diagonally dominant C: factors agree entrywise."""
+    _say(f"factor n={n} nb={nb}")
+    g = np.random.default_rng(n + nb)
+    C = g.standard_normal((n, n)) + 2.0 * n * np.eye(n)
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(dev(C))
+    assert s.factor() == 0
+    LU = host(s.work())
+    LUo, info = og.genp_unblocked(C)
+    assert np.max(np.abs(LU - LUo)) <= 1e-12 * np.max(np.abs(LUo))
+    i = s.info()
+    assert i["breakdown_col"] == 0
+    assert abs(i["min_abs_piv"] - np.min(np.abs(np.diag(LUo)))) <= 1e-12 * i["min_abs_piv"]
+    assert abs(i["max_abs_piv"] - np.max(np.abs(np.diag(LUo)))) <= 1e-12 * i["max_abs_piv"]
+    assert abs(i["growth"] - info.growth) <= 1e-12 * info.growth
+
+
+@pytest.mark.parametrize("n,nb,mult", [(256, 256, "dense"), (256, 64, "dense"), (600, 128, "toeplitz"),
+                                       (1100, 256, "dense")])
+def test_factor_backward_error_with_multiplier(n, nb, mult):
+    _say(f"factor-residual n={n} nb={nb} {mult}")
+    w = wl.rank_deficient_lead(n=n, seed=n)
+    if mult == "toeplitz":
+        p = np.random.default_rng(7).standard_normal(2 * n - 1)
+        G = og.toeplitz_from_params(p, n)
+    else:
+        p, G = None, w.G
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(dev(w.A), G=dev(G) if p is None else None, p=dev(p) if p is not None else None)
+    C = host(s.work())
+    assert s.factor(n * og.U64) == 0
+    LU = host(s.work())
+    L, U = og.unpack(LU)
+    E = np.linalg.norm(C - L @ U)
+    assert E <= 1e-13 * np.linalg.norm(np.abs(L) @ np.abs(U))
+    # raw residual reported next to the oracle's for the same C (agree within 10x)
+    LUo, _ = og.genp_blocked(C, nb)
+    raw_gpu, _ = og.factor_residual(C, LU)
+    raw_orc, _ = og.factor_residual(C, LUo)
+    _say(f"  raw ||C-LU||/||C||: gpu {raw_gpu:.2e} oracle {raw_orc:.2e}")
+    assert raw_gpu <= 10 * max(raw_orc, 1e-16 * n)
+
+
+def test_breakdown_on_singular_leading_block():
+    """GENP on A itself (no multiplier) breaks down at column 5; on A G it does not."""
+    w = wl.make("c1_n256_rankdef")
+    tol = 1e-10   # far below every legitimate pivot of A G, far above rounding of the singular block
+    _, io = og.genp_unblocked(w.A, tol)
+    assert io.breakdown_col == 5
+    s = genp.Solver(256, "f64", 64)
+    s.precondition(dev(w.A))
+    assert s.factor(tol) == 5
+    i = s.info()
+    assert i["breakdown_col"] == 5
+    with pytest.raises(genp.GenpError) as e:
+        s.solve(dev(w.B))
+    assert e.value.status == genp.ESTATE
+    s2 = genp.Solver(256, "f64", 64)
+    s2.precondition(dev(w.A), G=dev(w.G))
+    assert s2.factor(tol) == 0
+
+
+def test_nonfinite_input_is_a_breakdown():
+    n = 70
+    A = np.random.default_rng(0).standard_normal((n, n)) + 50 * np.eye(n)
+    A[3, 3] = np.nan
+    s = genp.Solver(n, "f64", 64)
+    s.precondition(dev(A))
+    bk = s.factor()
+    assert 1 <= bk <= 4
+
+
+# ------------------------------------------------------------ solve / refine ----
+
+def _check_solution(A, B, X, eta_gpu, kappa):
+    eta = og.backward_error_inf(A, X, B)
+    assert np.all(eta <= 1e-14), eta
+    Xo = np.linalg.solve(A, B)
+    eta_o = og.backward_error_inf(A, Xo, B)
+    tol = 10 * kappa * max(np.max(eta), np.max(eta_o), og.U64)
+    assert np.max(np.abs(X - Xo)) <= tol * np.max(np.abs(Xo))
+    assert np.all(np.asarray(eta_gpu) <= 1e-14)
+
+
+@pytest.mark.parametrize("name,n,nrhs,nb", [
+    ("c1_n256_rankdef", 256, 1, 64),
+    ("c1_n256_rankdef", 256, 1, 256),
+    ("c2_n4096_haar1e4_dense", 700, 16, 256),
+    ("c2_n4096_haar1e4_dense", 513, 3, 128),
+    ("c3_n16384_haar1e6_toeplitz", 600, 1, 64),
+    ("c4a_n16384_haar1e6_toeplitz", 520, 64, 256),
+    ("c5_n8192_scaled_lowrank", 384, 70, 128),
+])
+def test_solve_refine_backward_error(name, n, nrhs, nb):
+    _say(f"solve {name} n={n} nrhs={nrhs} nb={nb}")
+    w = wl.make(name, n=n, nrhs=nrhs)
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(dev(w.A), G=dev(w.G) if w.G is not None else None,
+                   p=dev(w.p) if w.p is not None else None)
+    assert s.factor() == 0
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    X0 = host(X).copy()
+    st, eta = s.refine(Bd, X, max_iter=2, tol=0.0)
+    Xh = host(X)
+    # the unrefined solution is the oracle's solve of the same factors up to rounding
+    G = og.dense_multiplier(w.G, w.p, n)
+    LUg = host(s.work())
+    Xs = og.solve(LUg, G, w.B)
+    assert np.max(np.abs(X0 - Xs)) <= 1e-8 * np.max(np.abs(Xs))
+    _check_solution(w.A, w.B, Xh, eta, np.linalg.cond(w.A, np.inf))
+    i = s.info()
+    assert i["iters"] <= 2 and i["n_eta"] >= 2 and i["eta_hist"][-1] <= 1e-14
+
+
+def test_refine_stops_at_tolerance_and_reports_enoconv():
+    w = wl.make("c2_n4096_haar1e4_dense", n=300, nrhs=2)
+    s = genp.Solver(300, "f64", 64)
+    s.precondition(dev(w.A), G=dev(w.G))
+    s.factor()
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, max_iter=5, tol=1e-15)
+    assert st == genp.OK and max(eta) <= 1e-15 and s.info()["iters"] <= 3
+    X2 = s.solve(Bd)
+    st2, _ = s.refine(Bd, X2, max_iter=0, tol=1e-30)
+    assert st2 == genp.ENOCONV
+
+
+def test_solve_is_deterministic():
+    w = wl.make("c2_n4096_haar1e4_dense", n=512, nrhs=8)
+    out = []
+    for _ in range(2):
+        s = genp.Solver(512, "f64", 128)
+        s.precondition(dev(w.A), G=dev(w.G))
+        s.factor()
+        X = s.solve(dev(w.B))
+        s.refine(dev(w.B), X, 2)
+        out.append(host(X))
+    assert np.array_equal(out[0], out[1])
+
+
+def test_state_and_argument_errors():
+    n = 64
+    s = genp.Solver(n, "f64", 64)
+    B = dev(np.ones((n, 1)))
+    with pytest.raises(genp.GenpError) as e:
+        s.solve(B)
+    assert e.value.status == genp.ESTATE
+    with pytest.raises(genp.GenpError) as e:
+        s.factor()
+    assert e.value.status == genp.ESTATE
+    with pytest.raises(genp.GenpError) as e:
+        genp.Solver(n, "f64", 100)
+    assert e.value.status == genp.EINVAL
+
+
+# ------------------------------------------------------------------ adjoint ----
+
+@pytest.mark.parametrize("n,nrhs,nb", [(64, 4, 64), (300, 16, 128), (257, 1, 256)])
+def test_adjoint_matches_oracle(n, nrhs, nb):
+    _say(f"adjoint n={n} nrhs={nrhs}")
+    w = wl.make("c5_n8192_scaled_lowrank", n=n, nrhs=nrhs)
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(dev(w.A), G=dev(w.G))
+    assert s.factor() == 0
+    X = s.solve(dev(w.B))
+    s.refine(dev(w.B), X, 2)
+    dB, dA = s.solve_backward(dev(w.W), X, want_dA=True, refine_iters=1)
+    Xh = host(X)
+    dBo, dAo = og.adjoint(w.A, Xh, w.W)
+    kappa = np.linalg.cond(w.A, np.inf)
+    tol = 10 * kappa * 1e-15
+    assert np.max(np.abs(host(dB) - dBo)) <= tol * np.max(np.abs(dBo))
+    assert np.max(np.abs(host(dA) - dAo)) <= tol * np.max(np.abs(dAo))
+
+
+def test_autograd_central_differences_n64():
+    n, k = 64, 3
+    w = wl.make("c5_n8192_scaled_lowrank", n=n, nrhs=k)
+    GenpSolve = genp.GenpSolve
+    A = dev(w.A).requires_grad_(True)
+    B = dev(w.B).requires_grad_(True)
+    G = dev(w.G)
+    W = dev(w.W)
+    X = GenpSolve.apply(A, B, G)
+    loss = (W * X).sum()
+    loss.backward()
+    gA, gB = host(A.grad), host(B.grad)
+
+    def L(Ah, Bh):
+        Xf, _, _ = genp.solve(dev(Ah), dev(Bh), G=G, refine=2)
+        return float(np.sum(w.W * host(Xf)))
+
+    g = np.random.default_rng(1)
+    h = 1e-6 * np.max(np.abs(w.A))
+    for _ in range(6):
+        i, j = g.integers(0, n, 2)
+        E = np.zeros((n, n))
+        E[i, j] = h
+        fd = (L(w.A + E, w.B) - L(w.A - E, w.B)) / (2 * h)
+        assert abs(fd - gA[i, j]) <= 1e-6 * max(abs(gA[i, j]), 1e-2 * np.max(np.abs(gA)))
+    D = g.standard_normal((n, n))
+    hd = 1e-6
+    fd = (L(w.A + hd * D, w.B) - L(w.A - hd * D, w.B)) / (2 * hd)
+    assert abs(fd - np.sum(gA * D)) <= 1e-6 * abs(fd)
+    i, c = 5, 1
+    E = np.zeros((n, k))
+    E[i, c] = 1e-6
+    fd = (L(w.A, w.B + E) - L(w.A, w.B - E)) / 2e-6
+    assert abs(fd - gB[i, c]) <= 1e-6 * max(abs(gB[i, c]), 1e-2 * np.max(np.abs(gB)))
+
+
+def test_gradient_does_not_depend_on_multiplier():
+    n, k = 128, 2
+    w = wl.make("c5_n8192_scaled_lowrank", n=n, nrhs=k)
+    grads = []
+    for seed in (11, 12):
+        G = dev(wl.gaussian((n, n), seed))
+        A = dev(w.A).requires_grad_(True)
+        X = genp.GenpSolve.apply(A, dev(w.B), G)
+        (dev(w.W) * X).sum().backward()
+        grads.append(host(A.grad))
+    kappa = np.linalg.cond(w.A, np.inf)
+    assert np.max(np.abs(grads[0] - grads[1])) <= 10 * kappa * 1e-15 * np.max(np.abs(grads[0]))
