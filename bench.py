@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the randomized-multiplier GENP solve on one MI355X.
+
+One step = the whole path on one resident system: C = A G, blocked GENP,
+substitutions, X = G Y and FP64 refinement until the normwise backward error
+is <= 1e-14 (at most 2 steps).  Default workload: n = 16384,
+A = U diag(s) V^T (Haar U, V; s log-spaced 1..1e6), Gaussian Toeplitz G from
+2n-1 parameters, one right-hand side; inputs are seeded, synthetic and built
+on the GPU before the timed region.
+
+Prints ONE JSON line.  GFLOP/s counts the method's algorithmic flops
+2n^3 + (2/3 n^3 - n^2/2 - n/6) + 4 n^2 k + it * 6 n^2 k.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s, MI355X
+HBM_PEAK_GBS = 8000.0
+
+
+def method_flops(n: int, k: int, it: int) -> float:
+    lu = (2.0 / 3.0) * n ** 3 - 0.5 * n ** 2 - n / 6.0
+    return 2.0 * n ** 3 + lu + 4.0 * n * n * k + it * 6.0 * n * n * k
+
+
+def schur_flops(n: int, nb: int) -> float:
+    """Flops of the Schur-update GEMMs: 2 m^2 nb per step, m = trailing size."""
+    n_pad = (n + nb - 1) // nb * nb
+    return sum(2.0 * (n_pad - (b + 1) * nb) ** 2 * nb for b in range(n_pad // nb))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(name: str, n_sample: int, prec_note: str) -> dict:
+    """The FP64 oracle (block elimination, nb = 256) on the host cores, same recipe at n_sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import genp as og
+    from paper_1212_4560_amd import workloads as wl
+
+    w = wl.make(name, n=n_sample, nrhs=1, device="cuda")
+    A, B = w.A.cpu().numpy(), w.B.cpu().numpy()
+    G = og.dense_multiplier(w.G.cpu().numpy() if w.G is not None else None,
+                            w.p.cpu().numpy() if w.p is not None else None, n_sample)
+    del w
+    t0 = time.perf_counter()
+    res, LU, info = og.genp_solve(A, B, G, nb=256, refine_steps=2, tol=1e-14)
+    dt = time.perf_counter() - t0
+    threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    steps = res.steps if res is not None else 0
+    gf = method_flops(n_sample, 1, steps) / dt / 1e9
+    return {"value": round(gf, 2), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{name} recipe at n={n_sample}, 1 RHS, FP64 block GENP (nb=256) + {steps} refinement "
+                      f"step(s), {dt:.1f} s wall; {prec_note}",
+            "eta": float(res.eta_hist[-1]) if res is not None else None}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3_n16384_haar1e6_toeplitz")
+    ap.add_argument("--n", type=int, default=None, help="override n (parity/debug runs)")
+    ap.add_argument("--nrhs", type=int, default=None)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-14)
+    ap.add_argument("--max-refine", type=int, default=2)
+    ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host-check", action="store_true",
+                    help="skip the oracle's backward-error check of the final X")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method is run on a single MI355X); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1212_4560_amd import genp, workloads as wl
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    w = wl.make(args.workload, n=args.n, nrhs=args.nrhs, device="cuda")
+    torch.cuda.synchronize()
+    n, k = w.n, w.nrhs
+    log(f"[bench] inputs {args.workload} n={n} k={k} built in {time.perf_counter() - t0:.1f}s")
+
+    stream = torch.cuda.current_stream()
+    s = genp.Solver(n, args.prec, args.nb, stream=stream)
+    X = torch.empty((n, k), dtype=torch.float64, device="cuda")
+
+    def step():
+        s.precondition(w.A, G=w.G, p=w.p)
+        bk = s.factor(0.0)
+        if bk:
+            raise RuntimeError(f"breakdown at column {bk}")
+        s.solve(w.B, X)
+        st, eta = s.refine(w.B, X, args.max_refine, args.tol)
+        inf = s.info()
+        return inf
+
+    for i in range(args.warmup):
+        inf = step()
+        log(f"[bench] warmup {i}: factor {inf['ms_factor']:.1f} ms, eta {inf['eta']:.2e}")
+    torch.cuda.synchronize()
+    infos = []
+    ag_ms = []
+    t_start = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for i in range(args.steps):
+        inf = step()
+        infos.append(inf)
+        ag_ms.append(inf["ms_ag"])
+        log(f"[bench] step {i}: precond {inf['ms_precond']:.1f} (A*G {inf['ms_ag']:.1f}) factor "
+            f"{inf['ms_factor']:.1f} (schur {inf['ms_schur']:.1f}, panel {inf['ms_panel']:.1f}) solve "
+            f"{inf['ms_solve']:.1f} refine {inf['ms_refine']:.1f} ms; it={inf['iters']} eta={inf['eta']:.2e}")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    its = [i["iters"] for i in infos]
+    flops = sum(method_flops(n, k, it) for it in its) / len(its)
+    value = flops / (ms_per_step * 1e-3) / 1e9
+    eta_lib = max(i["eta"] for i in infos)
+
+    # the oracle's backward error of the final X (host FP64)
+    eta_orc = None
+    if not args.no_host_check:
+        from oracle import genp as og
+        Ah = w.A.cpu().numpy()
+        eta_orc = float(np.max(og.backward_error_inf(Ah, X.cpu().numpy(), w.B.cpu().numpy())))
+        del Ah
+
+    ag_avg = sum(ag_ms) / len(ag_ms)
+    achieved = 2.0 * n ** 3 / (ag_avg * 1e-3) / 1e12
+    roof = {"kernel": "gemm_f64_kernel (C = A G, Toeplitz G generated in-kernel)", "bound": "mfma",
+            "achieved": round(achieved, 2), "peak": PEAK[args.prec], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[args.prec], 4), "traffic": None,
+            "avg_ms": round(ag_avg, 3), "algorithmic_flop_per_launch": 2.0 * n ** 3}
+    last = infos[-1]
+    out = {
+        "metric": "GENP solve GFLOP/s at n=16384, mixed+refine vs FP64, backward err <=1e-14",
+        "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "nrhs": k, "precision": args.prec, "nb": args.nb,
+                   "multiplier": w.mult, "smax": w.smax, "refine_tol": args.tol},
+        "eta_lib": eta_lib, "eta_oracle": eta_orc, "refine_steps": its,
+        "stage_ms": {"precondition": round(last["ms_precond"], 3), "ag_gemm": round(last["ms_ag"], 3),
+                     "factor": round(last["ms_factor"], 3), "schur_gemms": round(last["ms_schur"], 3),
+                     "panels": round(last["ms_panel"], 3), "solve": round(last["ms_solve"], 3),
+                     "refine": round(last["ms_refine"], 3)},
+        "schur_tflops": round(schur_flops(n, args.nb) / (last["ms_schur"] * 1e-3) / 1e12, 2)
+        if last["ms_schur"] > 0 else None,
+        "growth": last["growth"], "wall_s": round(wall, 2),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        del s
+        torch.cuda.empty_cache()
+        log(f"[bench] cpu baseline: oracle at n={args.cpu_sample_n}")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n, "threads = all host cores")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -96,6 +96,10 @@ typedef struct {
     int32_t n_eta;              /* entries of eta_hist                                    */
     double eta_hist[GENP_ETA_HIST]; /* eta before each refinement step and at the end     */
     double ms_precond, ms_factor, ms_solve, ms_refine, ms_backward; /* HIP-event times   */
+    double ms_ag;               /* the C = A G product kernel alone (last genp_precondition) */
+    double ms_schur;            /* sum over the Schur-update GEMMs of the last genp_factor   */
+    double ms_panel;            /* sum over diagonal-block LU + block solves of that factor  */
+    int32_t n_schur;            /* number of Schur-update launches summed in ms_schur        */
 } genp_info;
 
 /*

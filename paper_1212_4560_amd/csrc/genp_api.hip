@@ -60,6 +60,9 @@ struct genp_ctx {
     genp_info info{};
     hipEvent_t ev0[EV_N]{}, ev1[EV_N]{};
     bool ev_used[EV_N]{};
+    hipEvent_t ev_ag[2]{};
+    std::vector<hipEvent_t> ev_step;   // per elimination step: panel start, Schur start, Schur end
+    int64_t n_steps_timed = 0;
     double anorm = 0.0;
 };
 
@@ -329,6 +332,12 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
               hipMalloc(&c->red, (R_COLS + 3 * 256) * sizeof(unsigned long long)) == hipSuccess;
     for (int e = 0; ok && e < EV_N; ++e)
         ok = hipEventCreate(&c->ev0[e]) == hipSuccess && hipEventCreate(&c->ev1[e]) == hipSuccess;
+    for (int e = 0; ok && e < 2; ++e) ok = hipEventCreate(&c->ev_ag[e]) == hipSuccess;
+    if (ok) {
+        c->ev_step.assign(3 * nblk, nullptr);
+        for (auto& e : c->ev_step)
+            if (ok) ok = hipEventCreate(&e) == hipSuccess;
+    }
     if (ok) ok = ensure_rhs(c, 4) == GENP_OK;
     if (!ok) {
         genp_destroy(c);
@@ -359,6 +368,10 @@ int genp_destroy(genp_ctx* c) {
         if (c->ev0[e]) hipEventDestroy(c->ev0[e]);
         if (c->ev1[e]) hipEventDestroy(c->ev1[e]);
     }
+    for (auto e : c->ev_ag)
+        if (e) hipEventDestroy(e);
+    for (auto e : c->ev_step)
+        if (e) hipEventDestroy(e);
     delete c;
     return GENP_OK;
 }
@@ -411,7 +424,9 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
         g.D = (double*)c->C;
         g.ldd = c->ldc;
         g.ksplit = 1;
+        HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
         HIPCK(launch_gemm_f64(g, 0, c->stream));
+        HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
     }
     HIPCK(launch_pad_identity(c->prec, c->C, c->ldc, (int)n, (int)c->n_pad, c->stream));
     HIPCK(launch_max_abs(c->prec, c->C, c->ldc, (int)n, (int)n, 0, c->red + R_MAXC, c->stream));
@@ -420,6 +435,9 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
     unsigned long long h[3];
     HIPCK(hipMemcpyAsync(h, c->red, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
+    float ms_ag = 0.f;
+    c->info.ms_ag = (mult != GENP_G_NONE && hipEventElapsedTime(&ms_ag, c->ev_ag[0], c->ev_ag[1]) == hipSuccess)
+                        ? ms_ag : 0.0;
     c->anorm = bits_to_double(h[R_ANORM]);
     c->info.max_abs_c = bits_to_double(h[R_MAXC]);
     c->info.anorm_inf = c->anorm;
@@ -440,9 +458,14 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         const int64_t b = k / nb;
         double* Dk = C + k * ldc + k;
         const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
+        HIPCK(hipEventRecord(c->ev_step[3 * b], c->stream));
         HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + b, c->stream));
         const int64_t m = np - k - nb;
-        if (m <= 0) continue;
+        if (m <= 0) {
+            HIPCK(hipEventRecord(c->ev_step[3 * b + 1], c->stream));
+            HIPCK(hipEventRecord(c->ev_step[3 * b + 2], c->stream));
+            continue;
+        }
         // U12 = L11^{-1} A12 and L21 = A21 U11^{-1}, in place, by substitution
         HIPCK(launch_trsm(TRSM_L_UNIT, 0, 0, Dk, ldc, (int)nb, Dk + nb, ldc, (int)m, c->stream));
         HIPCK(launch_trsm(TRSM_RIGHT_U, 0, 0, Dk, ldc, (int)nb, Dk + nb * ldc, ldc, (int)m, c->stream));
@@ -464,7 +487,9 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         g.ldci = ldc;
         g.D = Dk + nb * ldc + nb;
         g.ldd = ldc;
+        HIPCK(hipEventRecord(c->ev_step[3 * b + 1], c->stream));
         HIPCK(launch_gemm_f64(g, 0, c->stream));
+        HIPCK(hipEventRecord(c->ev_step[3 * b + 2], c->stream));
     }
     HIPCK(launch_max_abs(c->prec, c->C, ldc, (int)c->n, (int)c->n, 1, c->red + R_MAXU, c->stream));
     ev_end(c, EV_FAC);
@@ -474,6 +499,19 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     HIPCK(hipMemcpyAsync(st.data(), c->stats, nblk * sizeof(PanelStats), hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipMemcpyAsync(&mu, c->red + R_MAXU, sizeof mu, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
+    double ms_s = 0.0, ms_p = 0.0;
+    int ns = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        float t0 = 0.f, t1 = 0.f;
+        if (hipEventElapsedTime(&t0, c->ev_step[3 * b], c->ev_step[3 * b + 1]) == hipSuccess) ms_p += t0;
+        if (b * nb + nb < np && hipEventElapsedTime(&t1, c->ev_step[3 * b + 1], c->ev_step[3 * b + 2]) == hipSuccess) {
+            ms_s += t1;
+            ++ns;
+        }
+    }
+    c->info.ms_schur = ms_s;
+    c->info.ms_panel = ms_p;
+    c->info.n_schur = ns;
     int64_t bad = -1;
     double mn = INFINITY, mx = 0.0;
     for (int64_t b = 0; b < nblk; ++b) {

@@ -51,6 +51,8 @@ class GenpInfo(ctypes.Structure):
         ("ms_precond", ctypes.c_double), ("ms_factor", ctypes.c_double),
         ("ms_solve", ctypes.c_double), ("ms_refine", ctypes.c_double),
         ("ms_backward", ctypes.c_double),
+        ("ms_ag", ctypes.c_double), ("ms_schur", ctypes.c_double), ("ms_panel", ctypes.c_double),
+        ("n_schur", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
