@@ -110,3 +110,7 @@ enum TrsmKind : int {
 };
 hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long ldt, int nb, void* X,
                        long long ldx, int ncols, hipStream_t s);
+// Whole triangular solve T X = B (T = the n_pad x n_pad factor as in launch_trsm's kinds,
+// except TRSM_RIGHT_U) for 1..4 right-hand sides, one launch per bs-row block.
+hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
+                            long long ldx, int nr, hipStream_t s);

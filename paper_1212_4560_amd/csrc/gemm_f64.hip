@@ -192,12 +192,27 @@ gemm_f64_kernel(GemmF64Args g) {
         }
     }
 
-    // epilogue
+    // epilogue.  Cin may alias D (in-place Schur update), so the compiler cannot move
+    // a load above an earlier store: the loads of each 16-row strip are issued as a
+    // batch before its stores.
     double* D = g.D;
     const bool split = g.ksplit > 1;
     if (split) D += (long long)blockIdx.y * g.split_stride;
+    const bool rd = !split && g.beta != 0.0;
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
+        double cv[4][4];
+        if (rd) {
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                const int col = n0 + wn * 64 + ni * 16 + lr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * 64 + mi * 16 + lq + 4 * r;
+                    cv[ni][r] = (row < g.M && col < g.N) ? g.Cin[(long long)row * g.ldci + col] : 0.0;
+                }
+            }
+        }
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
             const int col = n0 + wn * 64 + ni * 16 + lr;
@@ -206,7 +221,7 @@ gemm_f64_kernel(GemmF64Args g) {
                 const int row = m0 + wm * 64 + mi * 16 + lq + 4 * r;
                 if (row < g.M && col < g.N) {
                     double v = g.alpha * acc[mi][ni][r];
-                    if (!split && g.beta != 0.0) v += g.beta * g.Cin[(long long)row * g.ldci + col];
+                    if (rd) v = fma(g.beta, cv[ni][r], v);
                     D[(long long)row * g.ldd + col] = v;
                 }
             }

@@ -7,6 +7,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -61,8 +62,11 @@ struct genp_ctx {
     hipEvent_t ev0[EV_N]{}, ev1[EV_N]{};
     bool ev_used[EV_N]{};
     hipEvent_t ev_ag[2]{};
-    std::vector<hipEvent_t> ev_step;   // per elimination step: panel start, Schur start, Schur end
-    int64_t n_steps_timed = 0;
+    // per elimination step: Schur start/end (main stream), panel start/end (panel stream),
+    // cross-update done, panel done (ordering only)
+    std::vector<hipEvent_t> ev_step;
+    hipStream_t side = nullptr;        // look-ahead stream for the next panel (default priority)
+    bool lookahead = true;
     double anorm = 0.0;
 };
 
@@ -165,6 +169,13 @@ int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const int f32 = c->prec != GENP_F64;
     const size_t es = esize(c->prec);
     const char* Cb = (const char*)c->C;
+    if (k <= 4) {
+        // few right-hand sides: one fused launch per 128-row block (update + triangle)
+        const int bs = nb >= 128 ? 128 : 64;
+        HIPCK(launch_trsv_full(TRSM_L_UNIT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
+        HIPCK(launch_trsv_full(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
+        return GENP_OK;
+    }
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t r0 = b * nb;
         HIPCK(launch_trsm(TRSM_L_UNIT, f32, 0, Cb + (r0 * c->ldc + r0) * es, c->ldc, (int)nb, Z + r0 * ldz,
@@ -195,6 +206,12 @@ int lu_solve_trans_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const int f32 = c->prec != GENP_F64;
     const size_t es = esize(c->prec);
     const char* Cb = (const char*)c->C;
+    if (k <= 4) {
+        const int bs = nb >= 128 ? 128 : 64;
+        HIPCK(launch_trsv_full(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
+        HIPCK(launch_trsv_full(TRSM_LT_UNIT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
+        return GENP_OK;
+    }
     // U^T is lower triangular: forward substitution
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t r0 = b * nb;
@@ -334,9 +351,15 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
         ok = hipEventCreate(&c->ev0[e]) == hipSuccess && hipEventCreate(&c->ev1[e]) == hipSuccess;
     for (int e = 0; ok && e < 2; ++e) ok = hipEventCreate(&c->ev_ag[e]) == hipSuccess;
     if (ok) {
-        c->ev_step.assign(3 * nblk, nullptr);
-        for (auto& e : c->ev_step)
-            if (ok) ok = hipEventCreate(&e) == hipSuccess;
+        c->ev_step.assign(6 * nblk, nullptr);
+        for (size_t i = 0; ok && i < c->ev_step.size(); ++i)
+            ok = (i % 6 < 4 ? hipEventCreate(&c->ev_step[i])
+                            : hipEventCreateWithFlags(&c->ev_step[i], hipEventDisableTiming)) == hipSuccess;
+    }
+    if (ok) ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        const char* la = getenv("GENP_LOOKAHEAD");
+        c->lookahead = !(la && la[0] == '0');
     }
     if (ok) ok = ensure_rhs(c, 4) == GENP_OK;
     if (!ok) {
@@ -372,6 +395,7 @@ int genp_destroy(genp_ctx* c) {
         if (e) hipEventDestroy(e);
     for (auto e : c->ev_step)
         if (e) hipEventDestroy(e);
+    if (c->side) hipStreamDestroy(c->side);
     delete c;
     return GENP_OK;
 }
@@ -453,43 +477,69 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     const int64_t nb = c->nb, np = c->n_pad, ldc = c->ldc;
     double* C = (double*)c->C;
     const double* maxc = (const double*)(c->red + R_MAXC);
-    ev_begin(c, EV_FAC);
-    for (int64_t k = 0; k < np; k += nb) {
-        const int64_t b = k / nb;
+    const int64_t K = np / nb;
+    hipStream_t S = c->stream, P = c->side;
+    auto ev = [&](int64_t b, int i) { return c->ev_step[6 * b + i]; };
+    // panel j: diagonal block LU, then U12 = L11^{-1} A12 and L21 = A21 U11^{-1} by substitution
+    auto panel = [&](int64_t j, hipStream_t st) -> int {
+        const int64_t k = j * nb;
         double* Dk = C + k * ldc + k;
         const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
-        HIPCK(hipEventRecord(c->ev_step[3 * b], c->stream));
-        HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + b, c->stream));
+        HIPCK(hipEventRecord(ev(j, 2), st));
+        HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
         const int64_t m = np - k - nb;
-        if (m <= 0) {
-            HIPCK(hipEventRecord(c->ev_step[3 * b + 1], c->stream));
-            HIPCK(hipEventRecord(c->ev_step[3 * b + 2], c->stream));
-            continue;
+        if (m > 0) {
+            HIPCK(launch_trsm(TRSM_L_UNIT, 0, 0, Dk, ldc, (int)nb, Dk + nb, ldc, (int)m, st));
+            HIPCK(launch_trsm(TRSM_RIGHT_U, 0, 0, Dk, ldc, (int)nb, Dk + nb * ldc, ldc, (int)m, st));
         }
-        // U12 = L11^{-1} A12 and L21 = A21 U11^{-1}, in place, by substitution
-        HIPCK(launch_trsm(TRSM_L_UNIT, 0, 0, Dk, ldc, (int)nb, Dk + nb, ldc, (int)m, c->stream));
-        HIPCK(launch_trsm(TRSM_RIGHT_U, 0, 0, Dk, ldc, (int)nb, Dk + nb * ldc, ldc, (int)m, c->stream));
-        // Schur complement: A22 -= L21 U12
+        HIPCK(hipEventRecord(ev(j, 3), st));
+        return GENP_OK;
+    };
+    // Schur update of step j restricted to rows [r0, r0 + M) x cols [c0, c0 + N) of the trailing block
+    auto schur = [&](int64_t j, int64_t r0, int64_t c0, int64_t M, int64_t N, hipStream_t st) -> int {
+        if (M <= 0 || N <= 0) return GENP_OK;
+        const int64_t k = j * nb;
         GemmF64Args g{};
         g.ksplit = 1;
-        g.M = (int)m;
-        g.N = (int)m;
+        g.M = (int)M;
+        g.N = (int)N;
         g.K = (int)nb;
-        g.A = Dk + nb * ldc;
+        g.A = C + r0 * ldc + k;          // L21 rows r0..
         g.lda = ldc;
         g.amode = OP_N;
-        g.B = Dk + nb;
+        g.B = C + k * ldc + c0;          // U12 cols c0..
         g.ldb = ldc;
         g.bmode = OP_N;
         g.alpha = -1.0;
         g.beta = 1.0;
-        g.Cin = Dk + nb * ldc + nb;
+        g.Cin = C + r0 * ldc + c0;
         g.ldci = ldc;
-        g.D = Dk + nb * ldc + nb;
+        g.D = C + r0 * ldc + c0;
         g.ldd = ldc;
-        HIPCK(hipEventRecord(c->ev_step[3 * b + 1], c->stream));
-        HIPCK(launch_gemm_f64(g, 0, c->stream));
-        HIPCK(hipEventRecord(c->ev_step[3 * b + 2], c->stream));
+        HIPCK(launch_gemm_f64(g, 0, st));
+        return GENP_OK;
+    };
+    ev_begin(c, EV_FAC);
+    CK(panel(0, S));
+    for (int64_t j = 0; j + 1 < K; ++j) {
+        const int64_t r1 = (j + 1) * nb, m = np - r1;
+        HIPCK(hipEventRecord(ev(j, 0), S));
+        if (c->lookahead) {
+            // cross: block column j+1 and block row j+1 first, so panel j+1 can start
+            CK(schur(j, r1, r1, m, nb, S));
+            CK(schur(j, r1, r1 + nb, nb, m - nb, S));
+            HIPCK(hipEventRecord(ev(j, 4), S));
+            HIPCK(hipStreamWaitEvent(P, ev(j, 4), 0));
+            CK(panel(j + 1, P));
+            HIPCK(hipEventRecord(ev(j + 1, 5), P));
+            CK(schur(j, r1 + nb, r1 + nb, m - nb, m - nb, S));
+            HIPCK(hipEventRecord(ev(j, 1), S));
+            HIPCK(hipStreamWaitEvent(S, ev(j + 1, 5), 0));
+        } else {
+            CK(schur(j, r1, r1, m, m, S));
+            HIPCK(hipEventRecord(ev(j, 1), S));
+            CK(panel(j + 1, S));
+        }
     }
     HIPCK(launch_max_abs(c->prec, c->C, ldc, (int)c->n, (int)c->n, 1, c->red + R_MAXU, c->stream));
     ev_end(c, EV_FAC);
@@ -503,8 +553,8 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     int ns = 0;
     for (int64_t b = 0; b < nblk; ++b) {
         float t0 = 0.f, t1 = 0.f;
-        if (hipEventElapsedTime(&t0, c->ev_step[3 * b], c->ev_step[3 * b + 1]) == hipSuccess) ms_p += t0;
-        if (b * nb + nb < np && hipEventElapsedTime(&t1, c->ev_step[3 * b + 1], c->ev_step[3 * b + 2]) == hipSuccess) {
+        if (hipEventElapsedTime(&t0, c->ev_step[6 * b + 2], c->ev_step[6 * b + 3]) == hipSuccess) ms_p += t0;
+        if (b + 1 < nblk && hipEventElapsedTime(&t1, c->ev_step[6 * b], c->ev_step[6 * b + 1]) == hipSuccess) {
             ms_s += t1;
             ++ns;
         }

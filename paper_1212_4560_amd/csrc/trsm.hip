@@ -1,95 +1,266 @@
-// Triangular solves with an nb x nb triangular block by substitution (no
+// Triangular solves by substitution (no
 // explicit inverse): the two block solves of each elimination step,
 // L21 = A21 U11^{-1} and U12 = L11^{-1} A12, and the diagonal-block solves of
 // the substitutions Y = U^{-1} L^{-1} B and of the adjoint (U^T, L^T).
 //
-// Every case is written as a left solve T X = B with an nb x nb triangular T
-// and the right-hand sides as the columns of X.  A workgroup owns CB columns of
-// X, staged in LDS, and sweeps the rows of T: at step i every row r below
-// (above) i subtracts T(r, i) / T(i, i) times the unscaled row i; the rows are
-// divided by the diagonal at the end.  Columns of T are staged in LDS 16 at a
-// time (coalesced loads: by rows of T, or down its columns when T is accessed
-// transposed).  Right solves X U = B become U^T X^T = B^T with both operands
-// accessed transposed.  Substitution keeps the backward error of the block
-// solves at the level of the elimination itself; multiplying by a computed
-// inverse would add a factor of the block's condition number.
+// Every case is a left solve T X = B with an nb x nb triangular T and the
+// right-hand sides as the columns of X (right solves X U = B become
+// U^T X^T = B^T, both operands accessed transposed).  Substitution keeps the
+// backward error of the block solves at the level of the elimination itself;
+// multiplying by a computed inverse would add a factor of the block's
+// condition number.
+//
+// trsm_cols_kernel (many right-hand sides): a workgroup owns 16 columns of X;
+// thread (c, g) keeps rows 16g..16g+15 of column c in registers.  T is swept
+// in 16 x 16 blocks: the owner group solves its diagonal block thread-locally,
+// publishes the 16 values through LDS, and the groups below (above) subtract
+// the off-diagonal block times them.  One LDS stage of a 16-column strip of T
+// and two barriers per 16 rows; the footprint (256 threads, 37 KB LDS) lets it
+// run beside a Schur-GEMM workgroup.
+//
+// trsv_step_kernel (1..4 right-hand sides, whole triangular factor): see below.
 #include "common.h"
+
+#include <type_traits>
 
 namespace {
 
-constexpr int CB = 16;   // right-hand sides per workgroup
-constexpr int TC = 16;   // columns of T staged per LDS chunk
 constexpr int MAXNB = 256;
+constexpr int SB = 16;       // sub-block of the sweep and columns per workgroup
+
+template <bool TT>
+__device__ inline long long tat(int r, int c, long long ld) {
+    return TT ? (long long)c * ld + r : (long long)r * ld + c;
+}
 
 template <bool LOWER, bool UNIT, bool TT, bool XT, typename TF, typename TX>
 __global__ void __launch_bounds__(256)
-trsm_left_kernel(const TF* __restrict__ T, long long ldt, int nb, TX* X, long long ldx, int ncols) {
-    __shared__ double Xs[MAXNB][CB + 1];
-    __shared__ double Ts[MAXNB][TC + 1];
-    __shared__ double Tinv[TC];
+trsm_cols_kernel(const TF* __restrict__ T, long long ldt, int nb, TX* X, long long ldx, int ncols) {
+    __shared__ double Ts[MAXNB][SB + 1];   // strip of T: all rows, 32 columns
+    __shared__ double Xs[SB][SB + 1];      // the 32 solved rows of the current block
     const int tid = threadIdx.x;
-    const int c0 = blockIdx.x * CB;
-    const int cb = min(CB, ncols - c0);
-    auto xat = [&](int r, int c) -> long long {
-        return XT ? (long long)(c0 + c) * ldx + r : (long long)r * ldx + c0 + c;
+    const int c = tid % SB, g = tid / SB;  // column within the workgroup, row group
+    const int ng = nb / SB;
+    const int col = blockIdx.x * SB + c;
+    const bool act = g < ng && col < ncols;
+    auto xat = [&](int r) -> long long {
+        return XT ? (long long)col * ldx + r : (long long)r * ldx + col;
     };
-    auto tat = [&](int r, int c) -> long long {
-        return TT ? (long long)c * ldt + r : (long long)r * ldt + c;
-    };
-    // stage X: for XT the rows of X^T are contiguous in r
-    for (int e = tid; e < nb * CB; e += blockDim.x) {
-        int r, c;
-        if (XT) { c = e / nb; r = e % nb; }
-        else { r = e / CB; c = e % CB; }
-        Xs[r][c] = (c < cb) ? (double)X[xat(r, c)] : 0.0;
-    }
-    const int r = tid;
-    for (int step = 0; step < nb; step += TC) {
-        // chunk of T columns [i0, i0 + TC) in sweep order
-        const int i0 = LOWER ? step : nb - step - TC;
-        __syncthreads();
-        for (int e = tid; e < nb * TC; e += blockDim.x) {
-            int rr, t;
-            if (TT) { t = e / nb; rr = e % nb; }
-            else { rr = e / TC; t = e % TC; }
-            Ts[rr][t] = (double)T[tat(rr, i0 + t)];
-        }
-        __syncthreads();
-        if (!UNIT && tid < TC) Tinv[tid] = 1.0 / Ts[i0 + tid][tid];
-        __syncthreads();
-        for (int u = 0; u < TC; ++u) {
-            const int t = LOWER ? u : TC - 1 - u;
-            const int i = i0 + t;
-            if (r < nb && (LOWER ? r > i : r < i)) {
-                double m = Ts[r][t];
-                if (!UNIT) m *= Tinv[t];
+    double x[SB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) Xs[r][c] = fma(-m, Xs[i][c], Xs[r][c]);
+    for (int i = 0; i < SB; ++i) x[i] = act ? (double)X[xat(g * SB + i)] : 0.0;
+
+    for (int s = 0; s < ng; ++s) {
+        const int ib = LOWER ? s : ng - 1 - s;
+        const int c0 = ib * SB;
+        // rows of the strip that are used: the diagonal block and the rows still to update
+        const int r_lo = LOWER ? c0 : 0, r_hi = LOWER ? nb : c0 + SB;
+        __syncthreads();
+        {
+            // at most MAXNB * SB / 256 = 16 elements per thread: issue every load first
+            const int nrow = r_hi - r_lo;
+            double v[MAXNB * SB / 256];
+#pragma unroll
+            for (int q = 0; q < MAXNB * SB / 256; ++q) {
+                const int e = tid + q * 256;
+                int r, t;
+                if (TT) { t = e / nrow; r = r_lo + e % nrow; }
+                else { r = r_lo + e / SB; t = e % SB; }
+                v[q] = (e < nrow * SB) ? (double)T[tat<TT>(r, c0 + t, ldt)] : 0.0;
             }
-            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < MAXNB * SB / 256; ++q) {
+                const int e = tid + q * 256;
+                int r, t;
+                if (TT) { t = e / nrow; r = r_lo + e % nrow; }
+                else { r = r_lo + e / SB; t = e % SB; }
+                if (e < nrow * SB) Ts[r][t] = v[q];
+            }
+        }
+        __syncthreads();
+        if (g == ib && act) {
+            // x <- T_bb^{-1} x, thread-local column sweep (critical path SB FMAs)
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int t = LOWER ? u : SB - 1 - u;
+                if (!UNIT) x[t] /= Ts[c0 + t][t];
+#pragma unroll
+                for (int w = 0; w < SB; ++w) {
+                    if (LOWER ? (w > t) : (w < t)) x[w] = fma(-Ts[c0 + w][t], x[t], x[w]);
+                }
+            }
+        }
+        if (g == ib) {
+#pragma unroll
+            for (int i = 0; i < SB; ++i) Xs[i][c] = x[i];
+        }
+        __syncthreads();
+        if (act && (LOWER ? g > ib : g < ib)) {
+            double xb[SB];
+#pragma unroll
+            for (int t = 0; t < SB; ++t) xb[t] = Xs[t][c];
+#pragma unroll
+            for (int i = 0; i < SB; ++i) {
+                double v = x[i];
+                const double* trow = &Ts[g * SB + i][0];
+#pragma unroll
+                for (int t = 0; t < SB; ++t) v = fma(-trow[t], xb[t], v);
+                x[i] = v;
+            }
         }
     }
-    if (!UNIT) {
-        // x_r = y_r / T(r, r)
-        if (r < nb) {
-            const double d = 1.0 / (double)T[tat(r, r)];
+    if (act) {
 #pragma unroll
-            for (int c = 0; c < CB; ++c) Xs[r][c] *= d;
+        for (int i = 0; i < SB; ++i) X[xat(g * SB + i)] = (TX)x[i];
+    }
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One elimination step of the blocked substitution for 1..4 right-hand sides,
+// block size BS.  Block t is solved here; the block p solved by the previous
+// launch (p = t-1 forward, t+1 backward) is applied first.  Workgroup 0 stages
+// the diagonal block t in LDS (one round of loads), applies x_p to the rows of
+// block t, and then wave 0 sweeps the triangle: lane l holds rows l + 64 s,
+// x_i is broadcast with readlane, the column of T is read from LDS.  The other
+// workgroups apply x_p to every row beyond block t (one wave per row, the row
+// read as one coalesced run).  One launch per block.
+template <bool LOWER, bool UNIT, bool TT, int NR, int BS, typename TF>
+__global__ void __launch_bounds__(256)
+trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, double* X, long long ldx) {
+    constexpr int NS = BS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = n_pad / BS;
+    const int p = LOWER ? t - 1 : t + 1;
+    const bool has_p = p >= 0 && p < nblk;
+    const int pc0 = p * BS;   // first column of block p
+    // x_p (BS x NR) is read by every wave: lane l holds rows l + 64 s of it
+    double xp[NS][NR];
+    if (has_p) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) xp[s][c] = X[(long long)(pc0 + s * 64 + lane) * ldx + c];
+    }
+    // z_r -= T(r, block p) x_p for RPW rows r = rf, rf + rstep, ... (< r_end), one wave;
+    // the loads of all RPW rows are issued before the arithmetic
+    constexpr int RPW = 16;
+    auto apply_rows = [&](int rf, int rstep, int r_end) {
+        double a[RPW][NS];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = rf + q * rstep;
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                a[q][s] = (r < r_end) ? (double)T[tat<TT>(r, pc0 + s * 64 + lane, ldt)] : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = rf + q * rstep;
+            if (r >= r_end) break;
+            double acc[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                acc[c] = 0.0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) acc[c] = fma(a[q][s], xp[s][c], acc[c]);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+            }
+            if (lane < NR) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    if (c == lane) v = acc[c];
+                X[(long long)r * ldx + lane] -= v;
+            }
+        }
+    };
+    if (blockIdx.x > 0) {
+        if (!has_p) return;
+        const int base = (LOWER ? (t + 1) * BS : 0) + (blockIdx.x - 1) * 4 * RPW;
+        const int r_end = LOWER ? n_pad : t * BS;
+        apply_rows(base + wave, 4, r_end);
+        return;
+    }
+    __shared__ double Ts[BS][BS + 1];
+    __shared__ double rdiag[BS];
+    const int r0 = t * BS;
+    constexpr int LPT = BS * BS / 256;   // staged elements per thread, loaded in batches of 16
+#pragma unroll
+    for (int q0 = 0; q0 < LPT; q0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + (q0 + q) * 256;
+            int r, c;
+            if (TT) { c = e / BS; r = e % BS; }
+            else { r = e / BS; c = e % BS; }
+            v[q] = (double)T[tat<TT>(r0 + r, r0 + c, ldt)];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + (q0 + q) * 256;
+            int r, c;
+            if (TT) { c = e / BS; r = e % BS; }
+            else { r = e / BS; c = e % BS; }
+            Ts[r][c] = v[q];
+        }
+    }
+    if (has_p) {
+        for (int rf = wave; rf < BS; rf += 4 * RPW) apply_rows(r0 + rf, 4, r0 + BS);
     }
     __syncthreads();
-    for (int e = tid; e < nb * CB; e += blockDim.x) {
-        int rr, c;
-        if (XT) { c = e / nb; rr = e % nb; }
-        else { rr = e / CB; c = e % CB; }
-        if (c < cb) X[xat(rr, c)] = (TX)Xs[rr][c];
+    if (!UNIT && tid < BS) rdiag[tid] = 1.0 / Ts[tid][tid];
+    __syncthreads();
+    if (wave != 0) return;
+    double x[NS][NR];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) x[s][c] = X[(long long)(r0 + s * 64 + lane) * ldx + c];
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+        const int sblk = LOWER ? sb : NS - 1 - sb;   // the 64-row slice holding the pivots
+        for (int u = 0; u < 64; ++u) {
+            const int li = LOWER ? u : 63 - u;
+            const int i = sblk * 64 + li;
+            double xi[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                xi[c] = readlane_d(x[sblk][c], li);
+                if (!UNIT) xi[c] *= rdiag[i];
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (LOWER ? s < sblk : s > sblk) continue;   // these rows are final
+                const int r = s * 64 + lane;
+                const double m = Ts[r][i];
+                const bool upd = (s != sblk) || (LOWER ? lane > li : lane < li);
+                const bool own = (s == sblk) && lane == li;
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const double nv = fma(-m, xi[c], x[s][c]);
+                    x[s][c] = own ? xi[c] : (upd ? nv : x[s][c]);
+                }
+            }
+        }
     }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) X[(long long)(r0 + s * 64 + lane) * ldx + c] = x[s][c];
 }
 
 template <bool LOWER, bool UNIT, bool TT, bool XT, typename TF, typename TX>
 hipError_t go(const void* T, long long ldt, int nb, void* X, long long ldx, int ncols, hipStream_t s) {
-    hipLaunchKernelGGL((trsm_left_kernel<LOWER, UNIT, TT, XT, TF, TX>), dim3((ncols + CB - 1) / CB), dim3(256), 0,
-                       s, (const TF*)T, ldt, nb, (TX*)X, ldx, ncols);
+    hipLaunchKernelGGL((trsm_cols_kernel<LOWER, UNIT, TT, XT, TF, TX>), dim3((ncols + SB - 1) / SB), dim3(256),
+                       0, s, (const TF*)T, ldt, nb, (TX*)X, ldx, ncols);
     return hipGetLastError();
 }
 
@@ -110,10 +281,63 @@ hipError_t dispatch(int kind, const void* T, long long ldt, int nb, void* X, lon
 
 hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long ldt, int nb, void* X,
                        long long ldx, int ncols, hipStream_t s) {
-    if (nb <= 0 || nb > MAXNB || nb % TC) return hipErrorInvalidValue;
+    if (nb <= 0 || nb > MAXNB || nb % SB) return hipErrorInvalidValue;
     if (ncols <= 0) return hipSuccess;
     if (!t_f32 && !x_f32) return dispatch<double, double>(kind, T, ldt, nb, X, ldx, ncols, s);
     if (t_f32 && !x_f32) return dispatch<float, double>(kind, T, ldt, nb, X, ldx, ncols, s);
     if (t_f32 && x_f32) return dispatch<float, float>(kind, T, ldt, nb, X, ldx, ncols, s);
     return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <bool LOWER, bool UNIT, bool TT, int BS, typename TF>
+hipError_t trsv_go(const void* T, long long ldt, int n_pad, double* X, long long ldx, int nr, hipStream_t s) {
+    const int nblk = n_pad / BS;
+    for (int q = 0; q < nblk; ++q) {
+        const int t = LOWER ? q : nblk - 1 - q;
+        const int rows_rest = LOWER ? n_pad - (t + 1) * BS : t * BS;
+        const int has_p = LOWER ? t > 0 : t < nblk - 1;
+        const unsigned grid = 1 + (has_p ? (unsigned)((rows_rest + 63) / 64) : 0u);
+        switch (nr) {
+#define GENP_TRSV_CASE(NR)                                                                                  \
+    case NR:                                                                                                \
+        hipLaunchKernelGGL((trsv_step_kernel<LOWER, UNIT, TT, NR, BS, TF>), dim3(grid), dim3(256), 0, s,     \
+                           (const TF*)T, ldt, n_pad, t, X, ldx);                                            \
+        break;
+            GENP_TRSV_CASE(1)
+            GENP_TRSV_CASE(2)
+            GENP_TRSV_CASE(3)
+            GENP_TRSV_CASE(4)
+#undef GENP_TRSV_CASE
+            default: return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int BS, typename TF>
+hipError_t trsv_kind(int kind, const void* T, long long ldt, int n_pad, double* X, long long ldx, int nr,
+                     hipStream_t s) {
+    switch (kind) {
+        case TRSM_L_UNIT: return trsv_go<true, true, false, BS, TF>(T, ldt, n_pad, X, ldx, nr, s);
+        case TRSM_U: return trsv_go<false, false, false, BS, TF>(T, ldt, n_pad, X, ldx, nr, s);
+        case TRSM_UT: return trsv_go<true, false, true, BS, TF>(T, ldt, n_pad, X, ldx, nr, s);
+        case TRSM_LT_UNIT: return trsv_go<false, true, true, BS, TF>(T, ldt, n_pad, X, ldx, nr, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
+                            long long ldx, int nr, hipStream_t s) {
+    if (nr < 1 || nr > 4 || (bs != 64 && bs != 128) || n_pad % bs) return hipErrorInvalidValue;
+    if (bs == 128)
+        return t_f32 ? trsv_kind<128, float>(kind, T, ldt, n_pad, X, ldx, nr, s)
+                     : trsv_kind<128, double>(kind, T, ldt, n_pad, X, ldx, nr, s);
+    return t_f32 ? trsv_kind<64, float>(kind, T, ldt, n_pad, X, ldx, nr, s)
+                 : trsv_kind<64, double>(kind, T, ldt, n_pad, X, ldx, nr, s);
 }
