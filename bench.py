@@ -78,6 +78,7 @@ def main() -> int:
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-14)
     ap.add_argument("--max-refine", type=int, default=2)
+    ap.add_argument("--solver", default="luir", choices=["luir", "gmres"])
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-check", action="store_true",
@@ -111,7 +112,7 @@ def main() -> int:
         if bk:
             raise RuntimeError(f"breakdown at column {bk}")
         s.solve(w.B, X)
-        st, eta = s.refine(w.B, X, args.max_refine, args.tol)
+        st, eta = s.refine(w.B, X, args.max_refine, args.tol, args.solver)
         inf = s.info()
         return inf
 
@@ -131,7 +132,8 @@ def main() -> int:
         ag_ms.append(inf["ms_ag"])
         log(f"[bench] step {i}: precond {inf['ms_precond']:.1f} (A*G {inf['ms_ag']:.1f}) factor "
             f"{inf['ms_factor']:.1f} (schur {inf['ms_schur']:.1f}, panel {inf['ms_panel']:.1f}) solve "
-            f"{inf['ms_solve']:.1f} refine {inf['ms_refine']:.1f} ms; it={inf['iters']} eta={inf['eta']:.2e}")
+            f"{inf['ms_solve']:.1f} refine {inf['ms_refine']:.1f} ms; it={inf['iters']} inner={inf['inner_iters']} "
+            f"eta={inf['eta']:.2e}")
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start

@@ -108,12 +108,27 @@ __global__ void copy2d_kernel(const double* __restrict__ s, long long lds, doubl
     d[(long long)i * ldd + j] = s[(long long)i * lds + j];
 }
 
+__global__ void convert_kernel(const double* __restrict__ s, long long lds, float* __restrict__ d,
+                               long long ldd, int rows, int cols) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    d[(long long)i * ldd + j] = (float)s[(long long)i * lds + j];
+}
+
 __global__ void axpy2d_kernel(double alpha, const double* __restrict__ x, long long ldx,
                               double* __restrict__ y, long long ldy, int rows, int cols) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)rows * cols) return;
     const int i = (int)(e / cols), j = (int)(e % cols);
     y[(long long)i * ldy + j] += alpha * x[(long long)i * ldx + j];
+}
+
+__global__ void scale2d_kernel(double alpha, double* x, long long ldx, int rows, int cols) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    x[(long long)i * ldx + j] *= alpha;
 }
 
 __global__ void fill2d_kernel(double v, double* __restrict__ x, long long ldx, int rows, int cols) {
@@ -320,4 +335,19 @@ hipError_t launch_gemv_f64(int M, int K, int nrhs, double alpha, const void* A, 
                                     ldyi, Y, ldy, s);
     return gemv_dispatch<double>(M, K, nrhs, alpha, (const double*)A, lda, amode, X, ldx, beta, Yin, ldyi,
                                  Y, ldy, s);
+}
+
+hipError_t launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,
+                                  hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(convert_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale2d(double alpha, double* X, long long ldx, int rows, int cols, hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale2d_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, alpha, X, ldx, rows, cols);
+    return hipGetLastError();
 }

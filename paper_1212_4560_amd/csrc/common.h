@@ -49,6 +49,7 @@ struct GemmF64Args {
     double* D; long long ldd;
     int ksplit;                          // > 1: D receives ksplit partial products
     long long split_stride;              //      at D + s * split_stride (beta ignored)
+    int a_f32;                           // A operand stored as FP32 (widened on load)
 };
 // tile: 0 = 128x128 (2x2 waves), 1 = 256x64 (4x1), 2 = 64x256 (1x4), 3 = 64x64,
 //       4 = 128x64 (2x1), 5 = 64x128 (1x2)
@@ -114,3 +115,6 @@ hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long 
 // except TRSM_RIGHT_U) for 1..4 right-hand sides, one launch per bs-row block.
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
                             long long ldx, int nr, hipStream_t s);
+hipError_t launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,
+                                  hipStream_t s);
+hipError_t launch_scale2d(double alpha, double* X, long long ldx, int rows, int cols, hipStream_t s);

@@ -18,17 +18,17 @@ namespace {
 
 constexpr int BK = 16;
 
-template <int MODE>
-__device__ inline double load_op(const double* __restrict__ X, long long ld, int i, int k,
+template <int MODE, typename TA>
+__device__ inline double load_op(const TA* __restrict__ X, long long ld, int i, int k,
                                  int rows, int cols) {
     // element (i, k) of an operand of logical size rows x cols; 0 outside
     if (i >= rows || k >= cols) return 0.0;
-    if (MODE == OP_N) return X[(long long)i * ld + k];
-    if (MODE == OP_T) return X[(long long)k * ld + i];
+    if (MODE == OP_N) return (double)X[(long long)i * ld + k];
+    if (MODE == OP_T) return (double)X[(long long)k * ld + i];
     return 0.0;
 }
 
-template <int WM, int WN, int AMODE, int BMODE>
+template <int WM, int WN, int AMODE, int BMODE, bool AF32 = false>
 __global__ void __launch_bounds__(64 * WM * WN, 2)
 gemm_f64_kernel(GemmF64Args g) {
     constexpr int T = 64 * WM * WN;
@@ -87,7 +87,8 @@ gemm_f64_kernel(GemmF64Args g) {
                 int i, k;
                 if constexpr (AMODE == OP_N) { i = e / BK; k = e % BK; }
                 else { k = e / BMt; i = e % BMt; }
-                ra[r] = load_op<AMODE>(g.A, g.lda, m0 + i, k0 + k, g.M, kend);
+                if constexpr (AF32) ra[r] = load_op<AMODE>((const float*)g.A, g.lda, m0 + i, k0 + k, g.M, kend);
+                else ra[r] = load_op<AMODE>(g.A, g.lda, m0 + i, k0 + k, g.M, kend);
             }
         }
         if constexpr (BMODE == OP_TOEP) {
@@ -242,11 +243,11 @@ __global__ void splitk_reduce_kernel(int M, int N, int ks, const double* __restr
     D[(long long)i * ldd + j] = v;
 }
 
-template <int WM, int WN, int AM, int BMd>
+template <int WM, int WN, int AM, int BMd, bool AF32 = false>
 hipError_t launch_t(const GemmF64Args& a, hipStream_t s) {
     const int ntm = (a.M + 64 * WM - 1) / (64 * WM), ntn = (a.N + 64 * WN - 1) / (64 * WN);
     dim3 grid(ntm * ntn, a.ksplit > 1 ? a.ksplit : 1);
-    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, AM, BMd>), grid, dim3(64 * WM * WN), 0, s, a);
+    hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, AM, BMd, AF32>), grid, dim3(64 * WM * WN), 0, s, a);
     return hipGetLastError();
 }
 
@@ -266,6 +267,13 @@ hipError_t dispatch_modes(const GemmF64Args& a, hipStream_t s) {
 
 hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    if (a.a_f32) {
+        // FP32 factors times FP64 right-hand sides (the correction solves of the precision form)
+        if (tile != 4 || a.bmode != OP_N) return hipErrorInvalidValue;
+        if (a.amode == OP_N) return launch_t<2, 1, OP_N, OP_N, true>(a, s);
+        if (a.amode == OP_T) return launch_t<2, 1, OP_T, OP_N, true>(a, s);
+        return hipErrorInvalidValue;
+    }
     switch (tile) {
         case 0: return dispatch_modes<2, 2>(a, s);
         case 1: return dispatch_modes<4, 1>(a, s);

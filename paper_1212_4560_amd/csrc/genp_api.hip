@@ -57,6 +57,12 @@ struct genp_ctx {
     double* R = nullptr;       // n_pad x kcap
     double* Dx = nullptr;      // n_pad x kcap
     double* part = nullptr;    // split-K partials: KSPLIT_MAX x n_pad x kcap
+    // GMRES-IR: Krylov basis (restart + 1 vectors of n_pad), two n_pad work vectors, dot partials
+    int gm_restart = 50;
+    double* gm_V = nullptr;
+    double* gm_w = nullptr;
+    double* gm_z = nullptr;
+    double* gm_h = nullptr;
     int state = ST_CREATED;
     genp_info info{};
     hipEvent_t ev0[EV_N]{}, ev1[EV_N]{};
@@ -123,7 +129,7 @@ int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_
                               c->stream));
         return GENP_OK;
     }
-    if (a_f32) return GENP_ENOTSUP;
+    if (a_f32 && amode == OP_TOEP) return GENP_ENOTSUP;
     for (int c0 = 0; c0 < k; c0 += 64) {
         const int kc = std::min(64, k - c0);
         GemmF64Args g{};
@@ -140,6 +146,7 @@ int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_
         g.beta = beta;
         g.Cin = Yin ? Yin + c0 : nullptr;
         g.ldci = ldyi;
+        g.a_f32 = a_f32;
         const int ntm = (M + 127) / 128;
         int ks = std::max(1, std::min(KSPLIT_MAX, (512 + ntm - 1) / ntm));
         ks = std::min(ks, std::max(1, K / 256));
@@ -298,6 +305,115 @@ double max_of(const std::vector<double>& v) {
     return m;
 }
 
+
+// ------------------------------------------------------------------ GMRES-IR ---
+// FP64 restarted GMRES for A d = r with the right preconditioner M^{-1} = G (LU)^{-1}
+// built from the stored (possibly low-precision) factors.  Classical Gram-Schmidt
+// applied twice on the device; Hessenberg QR by Givens rotations on the host.
+
+int ensure_gmres(genp_ctx* c) {
+    if (c->gm_V) return GENP_OK;
+    const size_t np = (size_t)c->n_pad;
+    if (hipMalloc(&c->gm_V, (c->gm_restart + 1) * np * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->gm_w, np * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->gm_z, np * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->gm_h, 2 * (c->gm_restart + 2) * sizeof(double)) != hipSuccess)
+        return GENP_ENOMEM;
+    return GENP_OK;
+}
+
+// out (j+1 doubles, host) = V[0..j] . w ; V rows of length n (stride n_pad)
+int multidot(genp_ctx* c, int j1, const double* w, double* out) {
+    const int n = (int)c->n;
+    HIPCK(launch_gemv_f64(j1, n, 1, 1.0, c->gm_V, c->n_pad, OP_N, 0, w, 1, 0.0, nullptr, 1, c->gm_h, 1, c->stream));
+    HIPCK(hipMemcpyAsync(out, c->gm_h, j1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return GENP_OK;
+}
+
+// w -= V[0..j]^T h  (h on the host, copied to the device)
+int sub_combination(genp_ctx* c, int j1, const double* h, double* w, double sign) {
+    HIPCK(hipMemcpyAsync(c->gm_h, h, j1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCK(launch_gemv_f64((int)c->n, j1, 1, sign, c->gm_V, c->n_pad, OP_T, 0, c->gm_h, 1, 1.0, w, 1, w, 1,
+                          c->stream));
+    return GENP_OK;
+}
+
+// z = M^{-1} v = G U^{-1} L^{-1} v (n rows)
+int precond(genp_ctx* c, const double* v, double* z) { return solve_into(c, v, 1, 1, z, 1); }
+
+// one restart cycle on column r (n, stride 1) -> correction d (n); returns inner iterations
+int gmres_cycle(genp_ctx* c, const double* r, double* d, double tol_rel, int* iters_out) {
+    const int n = (int)c->n, m = c->gm_restart;
+    double beta;
+    {
+        double t;
+        HIPCK(hipMemcpyAsync(c->gm_V, r, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        CK(multidot(c, 1, c->gm_V, &t));
+        beta = sqrt(t);
+    }
+    *iters_out = 0;
+    if (!(beta > 0)) {
+        HIPCK(launch_fill2d(0.0, d, 1, n, 1, c->stream));
+        return GENP_OK;
+    }
+    HIPCK(launch_scale2d(1.0 / beta, c->gm_V, 1, n, 1, c->stream));   // v0 = r / beta
+    std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h(m + 1), h2(m + 1);
+    g[0] = beta;
+    int k = 0;
+    for (; k < m; ++k) {
+        double* vk = c->gm_V + (size_t)k * c->n_pad;
+        double* vk1 = c->gm_V + (size_t)(k + 1) * c->n_pad;
+        CK(precond(c, vk, c->gm_z));
+        // w = A z
+        CK(skinny(c, n, n, 1, 1.0, c->A, c->lda, OP_N, 0, c->gm_z, 1, 0.0, nullptr, 1, c->gm_w, 1));
+        CK(multidot(c, k + 1, c->gm_w, h.data()));
+        CK(sub_combination(c, k + 1, h.data(), c->gm_w, -1.0));
+        CK(multidot(c, k + 1, c->gm_w, h2.data()));
+        CK(sub_combination(c, k + 1, h2.data(), c->gm_w, -1.0));
+        for (int i = 0; i <= k; ++i) h[i] += h2[i];
+        // ||w||: copy w into v_{k+1} and dot it with itself
+        HIPCK(hipMemcpyAsync(vk1, c->gm_w, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        double nn;
+        HIPCK(launch_gemv_f64(1, n, 1, 1.0, vk1, c->n_pad, OP_N, 0, c->gm_w, 1, 0.0, nullptr, 1, c->gm_h, 1,
+                              c->stream));
+        HIPCK(hipMemcpyAsync(&nn, c->gm_h, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(hipStreamSynchronize(c->stream));
+        const double hk1 = sqrt(nn);
+        // apply the previous rotations to the new column, then a new rotation
+        for (int i = 0; i < k; ++i) {
+            const double a = cs[i] * h[i] + sn[i] * h[i + 1];
+            h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+            h[i] = a;
+        }
+        const double den = hypot(h[k], hk1);
+        cs[k] = den > 0 ? h[k] / den : 1.0;
+        sn[k] = den > 0 ? hk1 / den : 0.0;
+        h[k] = den;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        for (int i = 0; i <= k; ++i) H[i * m + k] = h[i];
+        const bool done = fabs(g[k + 1]) <= tol_rel * beta || !(hk1 > 0) || !isfinite(hk1);
+        if (!done) HIPCK(launch_scale2d(1.0 / hk1, vk1, 1, n, 1, c->stream));
+        if (done) {
+            ++k;
+            break;
+        }
+    }
+    *iters_out = k;
+    // y = R^{-1} g (upper triangular k x k), u = V y, d = M^{-1} u
+    std::vector<double> y(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int t = i + 1; t < k; ++t) v -= H[i * m + t] * y[t];
+        y[i] = (H[i * m + i] != 0.0) ? v / H[i * m + i] : 0.0;
+    }
+    HIPCK(launch_fill2d(0.0, c->gm_w, 1, n, 1, c->stream));
+    if (k > 0) CK(sub_combination(c, k, y.data(), c->gm_w, 1.0));
+    CK(precond(c, c->gm_w, d));
+    return GENP_OK;
+}
+
 int check_ctx(const genp_ctx* c) {
     if (!c) return GENP_EINVAL;
     return (hipSetDevice(c->device) == hipSuccess) ? GENP_OK : GENP_EDEVICE;
@@ -387,6 +503,10 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->R);
     hipFree(c->Dx);
     hipFree(c->part);
+    hipFree(c->gm_V);
+    hipFree(c->gm_w);
+    hipFree(c->gm_z);
+    hipFree(c->gm_h);
     for (int e = 0; e < EV_N; ++e) {
         if (c->ev0[e]) hipEventDestroy(c->ev0[e]);
         if (c->ev1[e]) hipEventDestroy(c->ev1[e]);
@@ -407,7 +527,6 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
     if (mult != GENP_G_DENSE && mult != GENP_G_TOEPLITZ && mult != GENP_G_NONE) return GENP_EINVAL;
     if (mult != GENP_G_NONE && !G) return GENP_EINVAL;
     if (mult == GENP_G_DENSE && ldg < n) return GENP_EINVAL;
-    if (c->prec != GENP_F64) return GENP_ENOTSUP;
     c->state = ST_CREATED;
     c->A = A;
     c->lda = lda;
@@ -427,8 +546,9 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
     }
     HIPCK(hipMemsetAsync(c->red, 0, sizeof(unsigned long long) * R_COLS, c->stream));
     if (mult == GENP_G_NONE) {
-        HIPCK(launch_copy2d(A, lda, (double*)c->C, c->ldc, (int)n, (int)n, c->stream));
-    } else {
+        if (c->prec == GENP_F64) HIPCK(launch_copy2d(A, lda, (double*)c->C, c->ldc, (int)n, (int)n, c->stream));
+        else HIPCK(launch_convert_f64_f32(A, lda, (float*)c->C, c->ldc, (int)n, (int)n, c->stream));
+    } else if (c->prec == GENP_F64) {
         GemmF64Args g{};
         g.M = g.N = g.K = (int)n;
         g.A = A;
@@ -450,6 +570,26 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
         g.ksplit = 1;
         HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
         HIPCK(launch_gemm_f64(g, 0, c->stream));
+        HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
+    } else {
+        // precision form: operands rounded FP64 -> FP32 (-> BF16) in the loader, FP32 accumulation
+        GemmLpArgs g{};
+        g.M = g.N = g.K = (int)n;
+        g.A = A;
+        g.lda = lda;
+        g.amode = OP_N;
+        g.a_f64 = 1;
+        g.B = (mult == GENP_G_DENSE) ? (const void*)G : (const void*)c->p;
+        g.ldb = (mult == GENP_G_DENSE) ? ldg : n;
+        g.bmode = (mult == GENP_G_DENSE) ? OP_N : OP_TOEP;
+        g.b_f64 = 1;
+        g.alpha = 1.f;
+        g.beta = 0.f;
+        g.D = (float*)c->C;
+        g.ldd = c->ldc;
+        g.bf16 = c->prec == GENP_BF16;
+        HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
+        HIPCK(launch_gemm_lp(g, 0, c->stream));
         HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
     }
     HIPCK(launch_pad_identity(c->prec, c->C, c->ldc, (int)n, (int)c->n_pad, c->stream));
@@ -475,7 +615,10 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     if (c->state != ST_PRECOND) return GENP_ESTATE;
     if (!(pivot_tol >= 0.0)) return GENP_EINVAL;
     const int64_t nb = c->nb, np = c->n_pad, ldc = c->ldc;
-    double* C = (double*)c->C;
+    const int lp = c->prec != GENP_F64;
+    const size_t es = esize(c->prec);
+    char* Cb = (char*)c->C;
+    auto at = [&](int64_t r, int64_t col) -> void* { return Cb + (r * ldc + col) * es; };
     const double* maxc = (const double*)(c->red + R_MAXC);
     const int64_t K = np / nb;
     hipStream_t S = c->stream, P = c->side;
@@ -483,14 +626,14 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     // panel j: diagonal block LU, then U12 = L11^{-1} A12 and L21 = A21 U11^{-1} by substitution
     auto panel = [&](int64_t j, hipStream_t st) -> int {
         const int64_t k = j * nb;
-        double* Dk = C + k * ldc + k;
+        void* Dk = at(k, k);
         const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
         HIPCK(hipEventRecord(ev(j, 2), st));
         HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
         const int64_t m = np - k - nb;
         if (m > 0) {
-            HIPCK(launch_trsm(TRSM_L_UNIT, 0, 0, Dk, ldc, (int)nb, Dk + nb, ldc, (int)m, st));
-            HIPCK(launch_trsm(TRSM_RIGHT_U, 0, 0, Dk, ldc, (int)nb, Dk + nb * ldc, ldc, (int)m, st));
+            HIPCK(launch_trsm(TRSM_L_UNIT, lp, lp, Dk, ldc, (int)nb, at(k, k + nb), ldc, (int)m, st));
+            HIPCK(launch_trsm(TRSM_RIGHT_U, lp, lp, Dk, ldc, (int)nb, at(k + nb, k), ldc, (int)m, st));
         }
         HIPCK(hipEventRecord(ev(j, 3), st));
         return GENP_OK;
@@ -499,6 +642,28 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     auto schur = [&](int64_t j, int64_t r0, int64_t c0, int64_t M, int64_t N, hipStream_t st) -> int {
         if (M <= 0 || N <= 0) return GENP_OK;
         const int64_t k = j * nb;
+        if (lp) {
+            GemmLpArgs g{};
+            g.M = (int)M;
+            g.N = (int)N;
+            g.K = (int)nb;
+            g.A = at(r0, k);             // L21 rows r0..
+            g.lda = ldc;
+            g.amode = OP_N;
+            g.B = at(k, c0);             // U12 cols c0..
+            g.ldb = ldc;
+            g.bmode = OP_N;
+            g.alpha = -1.f;
+            g.beta = 1.f;
+            g.Cin = (const float*)at(r0, c0);
+            g.ldci = ldc;
+            g.D = (float*)at(r0, c0);
+            g.ldd = ldc;
+            g.bf16 = c->prec == GENP_BF16;
+            HIPCK(launch_gemm_lp(g, 0, st));
+            return GENP_OK;
+        }
+        double* C = (double*)c->C;
         GemmF64Args g{};
         g.ksplit = 1;
         g.M = (int)M;
@@ -607,8 +772,10 @@ int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double*
     if (c->state != ST_FACTORED) return GENP_ESTATE;
     if (!B || !X || nrhs < 1 || nrhs > 256 || ldb < nrhs || ldx < nrhs || max_iter < 0 || !(tol >= 0))
         return GENP_EINVAL;
-    if (solver != GENP_SOLVER_LUIR) return GENP_ENOTSUP;
+    if (solver != GENP_SOLVER_LUIR && solver != GENP_SOLVER_GMRES) return GENP_EINVAL;
     CK(ensure_rhs(c, nrhs));
+    if (solver == GENP_SOLVER_GMRES) CK(ensure_gmres(c));
+    int inner_total = 0;
     const int k = (int)nrhs;
     const int n = (int)c->n;
     ev_begin(c, EV_REF);
@@ -639,15 +806,27 @@ int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double*
             status = (tol > 0) ? GENP_ENOCONV : GENP_OK;
             break;
         }
-        // Dx = G (LU)^{-1} R ; X += Dx
-        CK(solve_into(c, c->R, k, k, c->Dx, k));
+        if (solver == GENP_SOLVER_LUIR) {
+            // Dx = G (LU)^{-1} R ; X += Dx
+            CK(solve_into(c, c->R, k, k, c->Dx, k));
+        } else {
+            // Dx_j = GMRES(A d = r_j, right preconditioner G (LU)^{-1}), column by column
+            for (int j = 0; j < k; ++j) {
+                HIPCK(launch_copy2d(c->R + j, k, c->gm_z, 1, n, 1, c->stream));
+                HIPCK(hipMemcpyAsync(c->Z, c->gm_z, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                int its = 0;
+                CK(gmres_cycle(c, c->Z, c->gm_z, 1e-10, &its));
+                inner_total += its;
+                HIPCK(launch_copy2d(c->gm_z, 1, c->Dx + j, k, n, 1, c->stream));
+            }
+        }
         HIPCK(launch_axpy2d(1.0, c->Dx, k, X, ldx, n, k, c->stream));
         ++it;
     }
     ev_end(c, EV_REF);
     HIPCK(hipStreamSynchronize(c->stream));
     c->info.iters = it;
-    c->info.inner_iters = 0;
+    c->info.inner_iters = inner_total;
     c->info.eta = max_of(eta);
     if (eta_out)
         for (int j = 0; j < k; ++j) eta_out[j] = eta[j];
