@@ -1,7 +1,7 @@
 // Diagonal-block factorization of the blocked elimination.
 //
 // GENP (section 1.1) on an nb x nb diagonal block, in place, with no pivot
-// search and no row exchanges: right-looking, 32 columns at a time, each step
+// search and no row exchanges: right-looking, 16 columns at a time, each step
 // replacing the trailing block by its Schur complement (Fact 2.1).  Pivot
 // statistics and the first failing pivot (non-finite, or
 // |u_kk| <= pivot_tol * max|C|) are recorded.
@@ -11,125 +11,148 @@
 
 namespace {
 
-constexpr int PW = 32;    // inner panel width
+constexpr int PW = 16;    // inner panel width
 constexpr int MAXNB = 256;
+constexpr int TB = 8;     // 16x16 tiles per batch of the trailing update
 
-// One workgroup of 256 threads (one wave per SIMD) whose registers and LDS fit
-// in the footprint of one Schur-GEMM workgroup, so the factorization of the
-// next diagonal block can run beside the trailing update.
-//
-// For each 32-column panel: thread r keeps row r of the panel in registers;
-// the pivot row is published through a double-buffered LDS row, so each
-// elimination step costs one barrier.  The factored panel goes to LDS (XOR
-// swizzled: the writes of a wave spread over the banks, the broadcast reads
-// of the update hit one address).  Thread j then solves column j of the
-// 32-row block of U to its right by a column sweep (critical path 31 FMAs)
-// and applies the rank-32 Schur update to column j of the trailing block,
-// 8 rows per batch of loads.
+__device__ inline double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One workgroup of 256 threads (one wave per SIMD), FP64 arithmetic for either
+// storage type.  For each 16-column panel:
+//  1. wave 0 factors the panel alone, with no barrier: lane l holds rows
+//     l, l+64, l+128, l+192 of it in registers and the pivot row is broadcast
+//     with readlane;
+//  2. one thread per column solves the 16 rows of U right of the panel with the
+//     unit lower 16 x 16 block (column sweep);
+//  3. the trailing block takes the rank-16 Schur update (Fact 2.1) on the
+//     matrix cores: 16 x 16 tiles, 8 per wave per batch of loads, operands from
+//     LDS (the panel below the diagonal and the new rows of U).
 template <typename T>
 __global__ void __launch_bounds__(256)
 diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long col0,
                const double* __restrict__ maxc, double pivot_tol, PanelStats* __restrict__ st) {
-    __shared__ double P[MAXNB][PW];
-    __shared__ double prow[2][PW];
-    const int tid = threadIdx.x;
+    __shared__ double Ls[MAXNB][PW + 1];        // panel rows kb.. (row r - kb), 16 columns
+    __shared__ double Rs[PW][MAXNB - PW + 1];   // rows kb..kb+15 of U right of the panel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double tol_abs = pivot_tol * maxc[0];
     double s_min = INFINITY, s_max = 0.0;
     long long s_bad = -1;
     for (int kb = 0; kb < nb; kb += PW) {
         const int rows = nb - kb;
-        // an opaque copy of the thread index: keeps the compiler from hoisting the
-        // 32 per-step comparisons out of this loop (that exhausts the registers)
-        int me = tid;
-        asm volatile("" : "+v"(me));
-        double p[PW];
+        if (wave == 0) {
+            double p[4][PW];
 #pragma unroll
-        for (int c = 0; c < PW; ++c) p[c] = (me < rows) ? (double)D[(long long)(kb + me) * ldd + kb + c] : 0.0;
-        if (tid == 0) {
+            for (int s = 0; s < 4; ++s) {
+                const int r = s * 64 + lane;
 #pragma unroll
-            for (int c = 0; c < PW; ++c) prow[0][c] = p[c];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PW; ++k) {
-            const double* pr = prow[k & 1];
-            const double piv = pr[k];
-            if (tid == 0 && kb + k < nvalid) {
-                const double a = fabs((double)piv);
-                if (s_bad < 0 && (!isfinite(a) || a <= tol_abs)) s_bad = col0 + kb + k;
-                if (s_bad < 0) {
-                    s_min = fmin(s_min, a);
-                    s_max = fmax(s_max, a);
-                }
+                for (int c = 0; c < PW; ++c) p[s][c] = (r < rows) ? (double)D[(long long)(kb + r) * ldd + kb + c] : 0.0;
             }
-            if (me > k && me < rows) {
-                const double l = p[k] / piv;
-                p[k] = l;
-#pragma unroll
-                for (int c = k + 1; c < PW; ++c) p[c] = fma(-l, pr[c], p[c]);
-            }
-            if (k + 1 < PW && me == k + 1) {
-#pragma unroll
-                for (int c = 0; c < PW; ++c) prow[(k + 1) & 1][c] = p[c];
-            }
-            __syncthreads();
-        }
-        if (me < rows) {
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
-                D[(long long)(kb + me) * ldd + kb + c] = (T)p[c];
-                P[me][c ^ (me & 31)] = p[c];
+                // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
+                double prow[PW];
+#pragma unroll
+                for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(p[0][t], c) : 0.0;
+                const double piv = prow[c];
+                if (lane == 0 && kb + c < nvalid) {
+                    const double a = fabs(piv);
+                    if (s_bad < 0 && (!isfinite(a) || a <= tol_abs)) s_bad = col0 + kb + c;
+                    if (s_bad < 0) {
+                        s_min = fmin(s_min, a);
+                        s_max = fmax(s_max, a);
+                    }
+                }
+                const double rp = 1.0 / piv;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = s * 64 + lane;
+                    if (r > c && r < rows) {
+                        const double l = p[s][c] * rp;
+                        p[s][c] = l;
+#pragma unroll
+                        for (int t = 0; t < PW; ++t)
+                            if (t > c) p[s][t] = fma(-l, prow[t], p[s][t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int r = s * 64 + lane;
+                if (r < rows) {
+#pragma unroll
+                    for (int c = 0; c < PW; ++c) {
+                        D[(long long)(kb + r) * ldd + kb + c] = (T)p[s][c];
+                        Ls[r][c] = p[s][c];
+                    }
+                }
             }
         }
         __syncthreads();
-        const int ncols = nb - kb - PW;
-        if (ncols > 0 && me < ncols) {
-            const int j = me;
-            // x <- L_kk^{-1} x for column j of the 32 rows right of the panel (unit lower)
-            double x[PW];
+        const int ncols = rows - PW;
+        if (ncols > 0) {
+            if (tid < ncols) {
+                // rows kb..kb+15, column kb+16+tid: x <- L11^{-1} x (unit lower, column sweep)
+                double x[PW];
 #pragma unroll
-            for (int i = 0; i < PW; ++i) x[i] = (double)D[(long long)(kb + i) * ldd + kb + PW + j];
+                for (int i = 0; i < PW; ++i) x[i] = (double)D[(long long)(kb + i) * ldd + kb + PW + tid];
 #pragma unroll
-            for (int t = 0; t < PW; ++t) {
+                for (int t = 0; t < PW; ++t)
 #pragma unroll
-                for (int i = t + 1; i < PW; ++i) x[i] = fma(-P[i][t ^ (i & 31)], x[t], x[i]);
-                __builtin_amdgcn_sched_barrier(0);   // bound the loads the scheduler hoists
+                    for (int i = 0; i < PW; ++i)
+                        if (i > t) x[i] = fma(-Ls[i][t], x[t], x[i]);
+#pragma unroll
+                for (int i = 0; i < PW; ++i) {
+                    D[(long long)(kb + i) * ldd + kb + PW + tid] = (T)x[i];
+                    Rs[i][tid] = x[i];
+                }
             }
+            __syncthreads();
+            // trailing block rows/cols kb+16..: 16 x 16 tiles, A22 -= L21 U12 on the matrix cores.
+            // f64 16x16x4 layout: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
+            // accumulator lane l, element r -> (row l/16 + 4r, col l%16).
+            const int nt = ncols / PW, ntiles = nt * nt;
+            const int lr = lane & 15, lq = lane >> 4;
+            for (int t0 = wave * TB; t0 < ntiles; t0 += 4 * TB) {
+                f64x4 acc[TB];
 #pragma unroll
-            for (int i = 0; i < PW; ++i) D[(long long)(kb + i) * ldd + kb + PW + j] = (T)x[i];
-            // trailing block, column j: A22 -= L21 * U12 (rank 32); rows in batches of 16
-            // whose loads are issued one batch ahead
-            const int trows = rows - PW;
-            constexpr int RB = 16;
-            double va[RB], vb[RB];
-            auto ld_batch = [&](double* v, int r0) {
+                for (int b = 0; b < TB; ++b) {
+                    const int tile = t0 + b;
+                    const int ti = tile / nt, tj = tile % nt;
 #pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const int r = r0 + u;
-                    v[u] = (r < trows) ? (double)D[(long long)(kb + PW + r) * ldd + kb + PW + j] : 0.0;
-                }
-            };
-            auto do_batch = [&](const double* v, int r0) {
-#pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const int r = r0 + u;
-                    if (r < trows) {
-                        const int pr = PW + r;
-                        double acc = v[u];
-#pragma unroll
-                        for (int t = 0; t < PW; ++t) acc = fma(-P[pr][t ^ (pr & 31)], x[t], acc);
-                        D[(long long)(kb + PW + r) * ldd + kb + PW + j] = (T)acc;
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = kb + PW + ti * 16 + lq + 4 * r, col = kb + PW + tj * 16 + lr;
+                        acc[b][r] = (tile < ntiles) ? (double)D[(long long)row * ldd + col] : 0.0;
                     }
-                    __builtin_amdgcn_sched_barrier(0);
                 }
-            };
-            if (trows > 0) ld_batch(va, 0);
-            for (int r0 = 0; r0 < trows; r0 += 2 * RB) {
-                if (r0 + RB < trows) ld_batch(vb, r0 + RB);
-                do_batch(va, r0);
-                if (r0 + RB < trows) {
-                    if (r0 + 2 * RB < trows) ld_batch(va, r0 + 2 * RB);
-                    do_batch(vb, r0 + RB);
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                    const int tile = t0 + b;
+                    if (tile < ntiles) {
+                        const int ti = tile / nt, tj = tile % nt;
+#pragma unroll
+                        for (int kk = 0; kk < PW; kk += 4) {
+                            const double a = Ls[PW + ti * 16 + lr][kk + lq];
+                            const double bb = Rs[kk + lq][tj * 16 + lr];
+                            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, bb, acc[b], 0, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                    const int tile = t0 + b;
+                    if (tile < ntiles) {
+                        const int ti = tile / nt, tj = tile % nt;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = kb + PW + ti * 16 + lq + 4 * r, col = kb + PW + tj * 16 + lr;
+                            D[(long long)row * ldd + col] = (T)acc[b][r];
+                        }
+                    }
                 }
             }
         }
@@ -146,7 +169,7 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
 
 hipError_t launch_diag_lu(int prec, void* Dblk, long long ldd, int nb, int nvalid, long long col0,
                           const double* maxc, double pivot_tol, PanelStats* st, hipStream_t s) {
-    if (nb <= 0 || nb > MAXNB || nb % PW) return hipErrorInvalidValue;
+    if (nb <= 0 || nb > MAXNB || nb % PW) return hipErrorInvalidValue;   // nb: multiple of 16, <= 256
     if (prec == PREC_F64)
         hipLaunchKernelGGL(diag_lu_kernel<double>, dim3(1), dim3(256), 0, s, (double*)Dblk, ldd, nb,
                            nvalid, col0, maxc, pivot_tol, st);
