@@ -37,6 +37,60 @@ def schur_flops(n: int, nb: int) -> float:
     return sum(2.0 * (n_pad - (b + 1) * nb) ** 2 * nb for b in range(n_pad // nb))
 
 
+def traffic_if_current(n: int):
+    """HBM bytes per launch of the A*G kernel from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy kernel), or
+    None when the kernel source has changed since they were taken or n differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_f64_ag_n16384_traffic.json")
+    src = os.path.join(ROOT, "paper_1212_4560_amd", "csrc", "gemm_f64.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != h or rec.get("n") != n:
+        return None
+    return rec.get("traffic_bytes")
+
+
+def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
+    """The precision form on the same inputs: FP32 and BF16-operand factors with FP64
+    GMRES-IR (restart 50, at most 2 outer steps).  One warm-up, one timed run each."""
+    import torch
+    from paper_1212_4560_amd import genp
+    res = []
+    n, k = w.n, w.nrhs
+    for prec in ("f32", "bf16"):
+        s = genp.Solver(n, prec, args.nb)
+        X = torch.empty((n, k), dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream()
+        for rep in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.precondition(w.A, G=w.G, p=w.p)
+            bk = s.factor(0.0)
+            st, eta = (None, [float("nan")])
+            if not bk:
+                s.solve(w.B, X)
+                st, eta = s.refine(w.B, X, 2, args.tol, "gmres")
+            e1.record(stream)
+            torch.cuda.synchronize()
+        inf = s.info()
+        ms = e0.elapsed_time(e1)
+        ok = bool(st == genp.OK and max(eta) <= args.tol)
+        res.append({"prec": prec, "solver": "gmres", "ms": round(ms, 2), "eta": max(eta),
+                    "reached_tol": ok, "outer": inf["iters"], "inner": inf["inner_iters"],
+                    "ms_precond": round(inf["ms_precond"], 2), "ms_factor": round(inf["ms_factor"], 2),
+                    "ms_refine": round(inf["ms_refine"], 2), "growth": inf["growth"],
+                    "speedup_vs_f64": round(f64_ms / ms, 3)})
+        log(f"[bench] mixed {prec}: {ms:.1f} ms, eta {max(eta):.2e}, outer {inf['iters']} inner "
+            f"{inf['inner_iters']}, reached tol: {ok}")
+        del s
+    return res
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -79,7 +133,13 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-14)
     ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--solver", default="luir", choices=["luir", "gmres"])
-    ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--cpu-sample-n", type=int, default=10240)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form comparison")
+    ap.add_argument("--gaussian-inputs", action="store_true",
+                    help="counter runs: A ~ N(0,1) of the same shape instead of the Haar construction "
+                         "(no QR; the kernels' memory traffic does not depend on the values)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain copy kernel of the n x n working matrix (PMC calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-check", action="store_true",
                     help="skip the oracle's backward-error check of the final X")
@@ -97,7 +157,19 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    w = wl.make(args.workload, n=args.n, nrhs=args.nrhs, device="cuda")
+    if args.gaussian_inputs:
+        spec = dict(wl.NAMED[args.workload])
+        nn = args.n or spec["n"]
+        kk = args.nrhs or spec["nrhs"]
+        g = np.random.default_rng(spec.get("seed", 0))
+        Ag = torch.from_numpy(g.standard_normal((nn, nn))).to("cuda")
+        mult = spec.get("mult", wl.MULT_DENSE)
+        Gg = torch.from_numpy(g.standard_normal((nn, nn))).to("cuda") if mult == wl.MULT_DENSE else None
+        pg = torch.from_numpy(g.standard_normal(2 * nn - 1)).to("cuda") if mult == wl.MULT_TOEPLITZ else None
+        Bg = torch.from_numpy(g.standard_normal((nn, kk))).to("cuda")
+        w = wl.Workload(args.workload + "_gaussianA", nn, spec.get("seed", 0), Ag, Bg, mult, G=Gg, p=pg)
+    else:
+        w = wl.make(args.workload, n=args.n, nrhs=args.nrhs, device="cuda")
     torch.cuda.synchronize()
     n, k = w.n, w.nrhs
     log(f"[bench] inputs {args.workload} n={n} k={k} built in {time.perf_counter() - t0:.1f}s")
@@ -137,6 +209,7 @@ def main() -> int:
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    log(f"[bench] timed {args.steps} steps in {wall:.2f} s")
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     its = [i["iters"] for i in infos]
     flops = sum(method_flops(n, k, it) for it in its) / len(its)
@@ -175,6 +248,12 @@ def main() -> int:
         "growth": last["growth"], "wall_s": round(wall, 2),
         "roofline": roof,
     }
+    if args.calibrate_copy:
+        s.work()   # genp_copy_work: one kernel that reads 8 n^2 bytes and writes 8 n^2 bytes
+        torch.cuda.synchronize()
+    roof["traffic"] = traffic_if_current(n)
+    if not args.no_mixed and args.prec == "f64":
+        out["mixed"] = mixed_comparison(w, args, ms_per_step, value)
     if not args.no_cpu_baseline:
         del s
         torch.cuda.empty_cache()

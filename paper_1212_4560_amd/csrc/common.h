@@ -50,6 +50,7 @@ struct GemmF64Args {
     int ksplit;                          // > 1: D receives ksplit partial products
     long long split_stride;              //      at D + s * split_stride (beta ignored)
     int a_f32;                           // A operand stored as FP32 (widened on load)
+    int group_m;                         // tile-rows per group of the tile order (0 = 8)
 };
 // tile: 0 = 128x128 (2x2 waves), 1 = 256x64 (4x1), 2 = 64x256 (1x4), 3 = 64x64,
 //       4 = 128x64 (2x1), 5 = 64x128 (1x2)

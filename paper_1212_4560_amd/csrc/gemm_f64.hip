@@ -50,7 +50,10 @@ gemm_f64_kernel(GemmF64Args g) {
     const int ntm = (g.M + BMt - 1) / BMt, ntn = (g.N + BNt - 1) / BNt;
     const int total = ntm * ntn;
     const int pid = xcd_remap(blockIdx.x, total);
-    constexpr int GROUP = 8;
+    // tile order: groups of GROUP tile-rows, column-major inside a group.  With a generated
+    // (Toeplitz) B the only streamed operand is A, so GROUP = 1 lets all concurrent blocks of
+    // an XCD share each chunk of one A row-panel in its L2.
+    const int GROUP = g.group_m > 0 ? g.group_m : 8;
     const int group = pid / (GROUP * ntn);
     const int first_m = group * GROUP;
     const int gsz = min(ntm - first_m, GROUP);

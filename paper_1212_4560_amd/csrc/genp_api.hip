@@ -562,6 +562,7 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
             g.B = c->p;
             g.ldb = n;
             g.bmode = OP_TOEP;
+            g.group_m = 1;
         }
         g.alpha = 1.0;
         g.beta = 0.0;
