@@ -133,7 +133,7 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-14)
     ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--solver", default="luir", choices=["luir", "gmres"])
-    ap.add_argument("--cpu-sample-n", type=int, default=10240)
+    ap.add_argument("--cpu-sample-n", type=int, default=12288)
     ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--gaussian-inputs", action="store_true",
                     help="counter runs: A ~ N(0,1) of the same shape instead of the Haar construction "
