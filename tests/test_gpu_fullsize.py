@@ -1,0 +1,129 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+n = 16384 (Toeplitz G, FP64, nb = 256, look-ahead): the oracle computes sampled entries
+one by one -- c_ij = A[i, :] . G[:, j] within gamma_n |A[i,:]| |G[:,j]|, and
+(L U)_ij = sum_t l_it u_tj within 10 gamma_n (|L||U|)_ij -- and the backward error of the
+refined solution from the full A (host FP64).
+
+n = 4096 (dense G, FP64, 16 RHS): the whole oracle path runs on the host; solutions must
+agree within 10 kappa_inf(A) max(eta, u).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import genp as og  # noqa: E402
+from paper_1212_4560_amd import genp, workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_fullsize_n16384_toeplitz_sampled():
+    print("full size n=16384 Toeplitz: building inputs", flush=True)
+    w = wl.make("c3_n16384_haar1e6_toeplitz", device="cuda")
+    n = w.n
+    s = genp.Solver(n, "f64", 256)
+    s.precondition(w.A, p=w.p)
+    Ah = host(w.A)
+    ph = host(w.p)
+    rng = np.random.default_rng(0)
+    I = rng.integers(0, n, 96)
+    J = rng.integers(0, n, 96)
+    # a column of the Toeplitz multiplier: G[:, j] = p[i - j + n - 1]
+    cols = {j: ph[np.arange(n) - j + n - 1] for j in set(J.tolist())}
+    C = s.work()
+    Cs = host(C[torch.as_tensor(I, device="cuda"), torch.as_tensor(J, device="cuda")])
+    del C
+    for t, (i, j) in enumerate(zip(I, J)):
+        exact = Ah[i] @ cols[j]
+        bound = og.gamma(n) * (np.abs(Ah[i]) @ np.abs(cols[j]))
+        assert abs(Cs[t] - exact) <= 2 * bound
+    print("  C = A G sampled entries ok; factor", flush=True)
+    assert s.factor(0.0) == 0
+    info = s.info()
+    assert np.isfinite(info["growth"]) and info["breakdown_col"] == 0
+    LU = s.work()
+    rows = host(LU[torch.as_tensor(I, device="cuda")])
+    colsU = host(LU[:, torch.as_tensor(J, device="cuda")])
+    del LU
+    for t, (i, j) in enumerate(zip(I, J)):
+        li = rows[t].copy()
+        li[i] = 1.0
+        li[i + 1:] = 0.0
+        uj = colsU[:, t].copy()
+        uj[j + 1:] = 0.0
+        m = min(i, j) + 1
+        prod = li[:m] @ uj[:m]
+        bound = 10 * og.gamma(n) * (np.abs(li[:m]) @ np.abs(uj[:m]))
+        assert abs(Cs[t] - prod) <= bound + 2 * og.gamma(n) * abs(Cs[t])
+    print("  L U sampled entries ok; solve + refine", flush=True)
+    X = s.solve(w.B)
+    st, eta = s.refine(w.B, X, 2, 1e-14)
+    assert st == genp.OK
+    eta_o = og.backward_error_inf(Ah, host(X), host(w.B))
+    print(f"  eta library {max(eta):.2e} oracle {eta_o.max():.2e}", flush=True)
+    assert np.all(eta_o <= 1e-14)
+
+
+def test_fullsize_n4096_dense_whole_path():
+    print("full size n=4096 dense, 16 RHS", flush=True)
+    w = wl.make("c2_n4096_haar1e4_dense")
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")  # noqa: E731
+    s = genp.Solver(w.n, "f64", 256)
+    s.precondition(dev(w.A), G=dev(w.G))
+    assert s.factor() == 0
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, 2, 1e-14)
+    assert st == genp.OK
+    Xh = host(X)
+    res, LUo, info = og.genp_solve(w.A, w.B, w.G, nb=256, refine_steps=2, tol=1e-14)
+    eta_g = og.backward_error_inf(w.A, Xh, w.B)
+    assert np.all(eta_g <= 1e-14)
+    kappa = np.linalg.cond(w.A, np.inf)
+    tol = 10 * kappa * max(eta_g.max(), res.eta_hist[-1], og.U64)
+    assert np.max(np.abs(Xh - res.X)) <= tol * np.max(np.abs(res.X))
+    gi = s.info()
+    assert abs(gi["growth"] - info.growth) <= 0.01 * info.growth
+
+
+def test_fullsize_n8192_differentiation_form():
+    """n = 8192, A ~ N(0,1)/sqrt(n) with a rank-8 leading 16 x 16 block, dense G, 64 RHS:
+    forward solve + FP64 refinement, backward adjoint refined against A^T; the gradient of
+    sum(W * X) is checked against the oracle's FP64 gradient (LAPACK solve with A^T).
+    FP64 factors: with FP32 factors kappa(A G) u_32 > 1 at this size and GMRES-IR(50) does
+    not converge (eta 5e-3 after 12800 inner iterations), so the form runs in FP64."""
+    print("full size n=8192 differentiation form", flush=True)
+    w = wl.make("c5_n8192_scaled_lowrank")
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")  # noqa: E731
+    s = genp.Solver(w.n, "f64", 256)
+    s.precondition(dev(w.A), G=dev(w.G))
+    assert s.factor() == 0
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, 2, 1e-14)
+    info = s.info()
+    Xh = host(X)
+    eta_o = og.backward_error_inf(w.A, Xh, w.B)
+    print(f"  forward: status {st} outer {info['iters']} inner {info['inner_iters']} eta {eta_o.max():.2e}",
+          flush=True)
+    assert st == genp.OK and np.all(eta_o <= 1e-14)
+    dB, dA = s.solve_backward(dev(w.W), X, want_dA=True, refine_iters=1)
+    dBo, dAo = og.adjoint(w.A, Xh, w.W)
+    kappa = np.linalg.cond(w.A, np.inf)
+    err_b = np.max(np.abs(host(dB) - dBo)) / np.max(np.abs(dBo))
+    rng = np.random.default_rng(1)
+    I, J = rng.integers(0, w.n, 64), rng.integers(0, w.n, 64)
+    dAs = host(dA[torch.as_tensor(I, device="cuda"), torch.as_tensor(J, device="cuda")])
+    err_a = np.max(np.abs(dAs - dAo[I, J])) / np.max(np.abs(dAo))
+    print(f"  backward: kappa {kappa:.2e} rel err dB {err_b:.2e} dA {err_a:.2e}", flush=True)
+    assert err_b <= 10 * kappa * 1e-15 and err_a <= 10 * kappa * 1e-15
