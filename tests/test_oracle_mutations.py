@@ -1,0 +1,258 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each mutant replaces one oracle function with a plausibly wrong version (a
+dropped term, a wrong sign, a wrong index, a transposed operand) and the test
+asserts that at least one of the independent checks below fails with it and
+that all of them pass without it.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact, genp as og
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+def _arr(x):
+    return np.array(x, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ checks ----
+
+def check_golden():
+    g = json.load(open(GOLDEN))
+    e = g["genp_3x3"]
+    LU, _ = og.genp_unblocked(_arr(e["C"]))
+    L, U = og.unpack(LU)
+    ok = np.array_equal(L, _arr(e["L"])) and np.array_equal(U, _arr(e["U"]))
+    ok &= np.allclose(og.lu_solve(LU, _arr(e["b"])), _arr(e["x"]))
+    r = g["right_multiplier_repairs_it"]
+    C = og.precondition(_arr(r["A"]), _arr(r["G"]))
+    ok &= np.array_equal(C, _arr(r["C"]))
+    LU, _ = og.genp_unblocked(_arr(r["C"]))
+    ok &= np.allclose(og.solve(LU, _arr(r["G"]), _arr(r["b"])), _arr(r["x"]))
+    t = g["toeplitz_3x3"]
+    ok &= np.array_equal(og.toeplitz_from_params(_arr(t["p"]), 3), _arr(t["T"]))
+    return bool(ok)
+
+
+def check_exact():
+    g = np.random.default_rng(5)
+    n = 5
+    A, G, b = g.standard_normal((n, n)), g.standard_normal((n, n)), g.standard_normal((n, 1))
+    C = og.precondition(A, G)
+    Ce = exact.to_float(exact.matmul(exact.to_frac(A), exact.to_frac(G)))
+    if not np.all(np.abs(C - Ce) <= og.gamma(n) * (np.abs(A) @ np.abs(G))):
+        return False
+    Le, Ue, _ = exact.genp(exact.to_frac(C))
+    LU, _ = og.genp_unblocked(C)
+    L, U = og.unpack(LU)
+    if np.max(np.abs(L - exact.to_float(Le))) > 1e-9 or np.max(np.abs(U - exact.to_float(Ue))) > 1e-9 * np.max(np.abs(U)):
+        return False
+    xc = exact.to_float(exact.cramer(exact.to_frac(A), exact.to_frac(b)))
+    res, _, _ = og.genp_solve(A, b, G, refine_steps=2)
+    return bool(res is not None and np.max(np.abs(res.X - xc)) <= 1e-10 * np.max(np.abs(xc)))
+
+
+def check_gepp_and_eta():
+    g = np.random.default_rng(7)
+    n = 64
+    A = g.standard_normal((n, n))
+    G = g.standard_normal((n, n))
+    B = g.standard_normal((n, 2))
+    res, _, info = og.genp_solve(A, B, G, nb=16, refine_steps=2)
+    if res is None:
+        return False
+    Xp = np.linalg.solve(A, B)
+    ok = np.max(np.abs(res.X - Xp)) <= 1e-10 * np.max(np.abs(Xp))
+    # eta against an independent computation with library norms
+    R = B - A @ res.X
+    eta = np.array([np.linalg.norm(R[:, j], np.inf) / (np.linalg.norm(A, np.inf) * np.linalg.norm(res.X[:, j], np.inf)
+                                                       + np.linalg.norm(B[:, j], np.inf)) for j in range(2)])
+    ok &= np.allclose(og.backward_error_inf(A, res.X, B), eta, rtol=1e-12, atol=0)
+    ok &= res.eta_hist[-1] <= 1e-14
+    return bool(ok)
+
+
+def check_toeplitz_scipy():
+    from scipy.linalg import toeplitz
+    n = 9
+    p = np.random.default_rng(2).standard_normal(2 * n - 1)
+    return bool(np.array_equal(og.toeplitz_from_params(p, n), toeplitz(p[n - 1:], p[n - 1::-1])))
+
+
+def check_blocked():
+    g = np.random.default_rng(4)
+    n = 37
+    C = g.standard_normal((n, n)) + 2 * n * np.eye(n)
+    a, _ = og.genp_unblocked(C)
+    b, _ = og.genp_blocked(C, 8)
+    L, U = og.unpack(b)
+    return bool(np.allclose(a, b, rtol=0, atol=1e-12) and np.allclose(L @ U, C, rtol=0, atol=1e-10))
+
+
+def check_adjoint_fd():
+    g = np.random.default_rng(6)
+    n, k = 12, 2
+    A = g.standard_normal((n, n)) + 3 * np.eye(n)
+    B, W = g.standard_normal((n, k)), g.standard_normal((n, k))
+    X = np.linalg.solve(A, B)
+    dB, dA = og.adjoint(A, X, W)
+
+    def L(Am, Bm):
+        return float(np.sum(W * np.linalg.solve(Am, Bm)))
+    h = 1e-6
+    E = np.zeros((n, n))
+    E[3, 7] = h
+    fa = (L(A + E, B) - L(A - E, B)) / (2 * h)
+    Eb = np.zeros((n, k))
+    Eb[5, 1] = h
+    fb = (L(A, B + Eb) - L(A, B - Eb)) / (2 * h)
+    return bool(abs(fa - dA[3, 7]) <= 1e-6 * max(1, abs(fa)) and abs(fb - dB[5, 1]) <= 1e-6 * max(1, abs(fb)))
+
+
+CHECKS = [check_golden, check_exact, check_gepp_and_eta, check_toeplitz_scipy, check_blocked, check_adjoint_fd]
+
+
+def run_checks():
+    out = []
+    for c in CHECKS:
+        try:
+            with np.errstate(all="ignore"):
+                out.append(c())
+        except Exception:
+            out.append(False)
+    return out
+
+
+# ----------------------------------------------------------------- mutants ----
+
+def _genp_sign(C, pivot_tol=0.0):
+    LU = np.array(C, dtype=np.float64, copy=True)
+    n = LU.shape[0]
+    for k in range(n):
+        LU[k + 1:, k] /= LU[k, k]
+        LU[k + 1:, k + 1:] += np.outer(LU[k + 1:, k], LU[k, k + 1:])      # wrong sign
+    return LU, og.FactorInfo(0, np.diag(LU), float(np.max(np.abs(C))), 1.0)
+
+
+def _genp_no_divide(C, pivot_tol=0.0):
+    LU = np.array(C, dtype=np.float64, copy=True)
+    n = LU.shape[0]
+    for k in range(n):
+        LU[k + 1:, k + 1:] -= np.outer(LU[k + 1:, k] / LU[k, k], LU[k, k + 1:])  # multipliers not stored
+    return LU, og.FactorInfo(0, np.diag(LU), float(np.max(np.abs(C))), 1.0)
+
+
+def _genp_index(C, pivot_tol=0.0):
+    LU = np.array(C, dtype=np.float64, copy=True)
+    n = LU.shape[0]
+    for k in range(n):
+        LU[k + 1:, k] /= LU[k, k]
+        LU[k + 1:, k + 1:] -= np.outer(LU[k + 1:, k], LU[k, k:-1])         # pivot row shifted by one
+    return LU, og.FactorInfo(0, np.diag(LU), float(np.max(np.abs(C))), 1.0)
+
+
+def _forward_transposed(LU, B):
+    B = np.asarray(B, dtype=np.float64)
+    Z = np.array(B, copy=True).reshape(B.shape[0], -1)
+    for i in range(LU.shape[0]):
+        if i:
+            Z[i] -= LU[:i, i] @ Z[:i]                                       # column instead of row
+    return Z.reshape(B.shape)
+
+
+def _backward_no_divide(LU, Z):
+    Z = np.asarray(Z, dtype=np.float64)
+    Y = np.array(Z, copy=True).reshape(Z.shape[0], -1)
+    n = LU.shape[0]
+    for i in range(n - 1, -1, -1):
+        if i < n - 1:
+            Y[i] -= LU[i, i + 1:] @ Y[i + 1:]                              # diagonal never divided
+    return Y.reshape(Z.shape)
+
+
+def _precondition_left(A, G):
+    return np.asarray(G) @ np.asarray(A)                                   # wrong side
+
+
+def _toeplitz_transposed(p, n):
+    p = np.asarray(p, dtype=np.float64)
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    return p[j - i + n - 1]                                                # t_{j-i}
+
+
+def _solve_no_recovery(LU, G, B):
+    return og.lu_solve(LU, B)                                              # forgets x = G y
+
+
+def _residual_sign(A, X, B):
+    return A @ X - B                                                       # wrong sign
+
+
+def _eta_onenorm(A, X, B):
+    X2 = np.asarray(X).reshape(X.shape[0], -1)
+    B2 = np.asarray(B).reshape(B.shape[0], -1)
+    R = B2 - A @ X2
+    a = np.max(np.sum(np.abs(A), axis=0))                                  # column sums (1-norm)
+    return np.max(np.abs(R), axis=0) / (a * np.max(np.abs(X2), axis=0) + np.max(np.abs(B2), axis=0))
+
+
+def _adjoint_no_transpose(A, X, W):
+    dB = np.linalg.solve(np.asarray(A), W)                                 # A instead of A^T
+    return dB, -dB @ np.asarray(X).T
+
+
+def _adjoint_sign(A, X, W):
+    dB = np.linalg.solve(np.asarray(A).T, W)
+    return dB, dB @ np.asarray(X).T                                        # lost minus sign
+
+
+def _blocked_transposed_l21(C, nb, pivot_tol=0.0):
+    from scipy.linalg import solve_triangular
+    LU = np.array(C, dtype=np.float64, copy=True)
+    n = LU.shape[0]
+    for k in range(0, n, nb):
+        e = min(k + nb, n)
+        D, _ = og.genp_unblocked(LU[k:e, k:e])
+        LU[k:e, k:e] = D
+        if e < n:
+            L11 = np.tril(D, -1) + np.eye(e - k)
+            U11 = np.triu(D)
+            LU[e:, k:e] = solve_triangular(U11, LU[e:, k:e].T, lower=False).T   # U11 instead of U11^T
+            LU[k:e, e:] = solve_triangular(L11, LU[k:e, e:], lower=True, unit_diagonal=True)
+            LU[e:, e:] -= LU[e:, k:e] @ LU[k:e, e:]
+    return LU, og.FactorInfo(0, np.diag(LU), float(np.max(np.abs(C))), 1.0)
+
+
+MUTANTS = {
+    "genp: wrong sign in the Schur update": ("genp_unblocked", _genp_sign),
+    "genp: multipliers not stored": ("genp_unblocked", _genp_no_divide),
+    "genp: pivot row off by one": ("genp_unblocked", _genp_index),
+    "forward substitution: transposed operand": ("forward_unit", _forward_transposed),
+    "back substitution: no division by u_ii": ("backward_upper", _backward_no_divide),
+    "precondition: multiplier on the left": ("precondition", _precondition_left),
+    "Toeplitz: transposed index": ("toeplitz_from_params", _toeplitz_transposed),
+    "solve: recovery x = G y dropped": ("solve", _solve_no_recovery),
+    "refinement: residual sign": ("residual", _residual_sign),
+    "backward error: 1-norm of A": ("backward_error_inf", _eta_onenorm),
+    "adjoint: A instead of A^T": ("adjoint", _adjoint_no_transpose),
+    "adjoint: lost minus sign on dA": ("adjoint", _adjoint_sign),
+    "block GE: L21 with U11 not transposed": ("genp_blocked", _blocked_transposed_l21),
+}
+
+
+def test_all_checks_pass_on_the_oracle():
+    assert all(run_checks())
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, monkeypatch):
+    attr, fn = MUTANTS[name]
+    monkeypatch.setattr(og, attr, fn)
+    res = run_checks()
+    assert not all(res), f"mutant not caught: {name}"
