@@ -112,6 +112,11 @@ enum TrsmKind : int {
 };
 hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long ldt, int nb, void* X,
                        long long ldx, int ncols, hipStream_t s);
+// The two block solves of an elimination step in one launch: A12 <- L11^{-1} A12
+// (nb x m) and A21 <- A21 U11^{-1} (m x nb), with L11 \ U11 the factored diagonal
+// block D.  nb in {64, 128, 256}; f32: D, A12 and A21 are FP32 (arithmetic in FP64).
+hipError_t launch_panel_trsm(int f32, const void* D, long long ldd, int nb, void* A12, void* A21, long long ldx,
+                             int m, hipStream_t s);
 // Whole triangular solve T X = B (T = the n_pad x n_pad factor as in launch_trsm's kinds,
 // except TRSM_RIGHT_U) for 1..4 right-hand sides, one launch per bs-row block.
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,

@@ -633,8 +633,7 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
         const int64_t m = np - k - nb;
         if (m > 0) {
-            HIPCK(launch_trsm(TRSM_L_UNIT, lp, lp, Dk, ldc, (int)nb, at(k, k + nb), ldc, (int)m, st));
-            HIPCK(launch_trsm(TRSM_RIGHT_U, lp, lp, Dk, ldc, (int)nb, at(k + nb, k), ldc, (int)m, st));
+            HIPCK(launch_panel_trsm(lp, Dk, ldc, (int)nb, at(k, k + nb), at(k + nb, k), ldc, (int)m, st));
         }
         HIPCK(hipEventRecord(ev(j, 3), st));
         return GENP_OK;

@@ -18,6 +18,12 @@
 // and two barriers per 16 rows; the footprint (256 threads, 37 KB LDS) lets it
 // run beside a Schur-GEMM workgroup.
 //
+// panel_trsm_kernel (the two block solves of an elimination step, one launch):
+// lower-triangular solves T Y = Z, 16 x 16 blocks, right-looking.  A wave owns
+// 16 right-hand sides and keeps all NB / 16 of its 16 x 16 tiles of Y in MFMA
+// accumulators; the diagonal block is solved by substitution (one lane per
+// right-hand side), the update of the blocks below by v_mfma_f64_16x16x4_f64.
+//
 // trsv_step_kernel (1..4 right-hand sides, whole triangular factor): see below.
 #include "common.h"
 
@@ -113,6 +119,151 @@ trsm_cols_kernel(const TF* __restrict__ T, long long ldt, int nb, TX* X, long lo
 #pragma unroll
         for (int i = 0; i < SB; ++i) X[xat(g * SB + i)] = (TX)x[i];
     }
+}
+
+// Lower-triangular solve T Y = Z by 16 x 16 blocks, T = L (unit, TT = false) or U^T
+// (TT = true, T(i, k) = U[k][i]).  Y(i, c): XT = false -> X[i * ldx + c] (the columns
+// of X are the right-hand sides), XT = true -> X[c * ldx + i] (its rows are).
+// The wave owning right-hand sides c0..c0+15 holds tile b of Y in acc[b]: lane l,
+// element r = Y(16 b + l / 16 + 4 r, c0 + l % 16).  With that layout, element q of
+// acc[b] is exactly the B operand of the 16x16x4 MFMA for rows 16 b + 4 q .. + 3 of
+// Y (lane l: k = l / 16, column l % 16), so the solved tiles feed the update of the
+// tiles below with no data movement.  The diagonal blocks are solved by
+// substitution in the same order as a column sweep, with division by the pivot.
+// T is staged through LDS one 16-column strip at a time (rows 16 b .. NB - 1),
+// prefetched two strips ahead through registers.  Only LDS traffic is fenced at the
+// barriers, so the prefetch stays in flight across them.
+template <int NBLK, bool TT, bool UNIT, bool XT, typename TF, typename TX>
+__device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], double (*Ys)[16][17],
+                                                const TF* __restrict__ T, long long ldt, TX* X, long long ldx,
+                                                int ncols, int wg) {
+    constexpr int NB = NBLK * 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int cc = wg * 64 + w * 16 + lr;
+    const bool cok = cc < ncols;
+    auto xidx = [&](int i) -> long long { return XT ? (long long)cc * ldx + i : (long long)i * ldx + cc; };
+    auto tload = [&](int i, int k) -> double {
+        return (double)(TT ? T[(long long)k * ldt + i] : T[(long long)i * ldt + k]);
+    };
+    // strip b: T(i, 16 b + k), i in [16 b, NB), k in [0, 16): NBLK - b elements per thread
+    auto strip_ik = [&](int b, int e, int& i, int& k) {
+        const int rows = NB - 16 * b;
+        if (TT) { k = e / rows; i = 16 * b + e % rows; }
+        else { i = 16 * b + e / 16; k = e % 16; }
+    };
+    auto lds_barrier = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    };
+    auto lds_wave_sync = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    };
+
+    f64x4 acc[NBLK];
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[b][r] = cok ? (double)X[xidx(16 * b + lq + 4 * r)] : 0.0;
+
+    double pfa[NBLK], pfb[NBLK];
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) {
+        int i, k;
+        strip_ik(0, tid + q * 256, i, k);
+        Ts[0][i][k] = tload(i, k);
+    }
+    if (NBLK > 1) {
+#pragma unroll
+        for (int q = 0; q < NBLK - 1; ++q) {
+            int i, k;
+            strip_ik(1, tid + q * 256, i, k);
+            pfb[q] = tload(i, 16 + k);
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        const int cur = b & 1;
+        // strip b + 2 -> register set b & 1 (strip b + 1, in set (b + 1) & 1, goes to LDS below)
+        if (b + 2 < NBLK) {
+#pragma unroll
+            for (int q = 0; q < NBLK - b - 2; ++q) {
+                int i, k;
+                strip_ik(b + 2, tid + q * 256, i, k);
+                const double v = tload(i, 16 * (b + 2) + k);
+                if (b & 1) pfb[q] = v;
+                else pfa[q] = v;
+            }
+        }
+        // diagonal block: lane c < 16 of each wave solves right-hand side c0 + c
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ys[w][lq + 4 * r][lr] = acc[b][r];
+        lds_wave_sync();
+        if (lane < 16) {
+            double y[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) y[i] = Ys[w][i][lane];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                if (!UNIT) y[s] /= Ts[cur][16 * b + s][s];
+#pragma unroll
+                for (int i = s + 1; i < 16; ++i) y[i] = fma(-Ts[cur][16 * b + i][s], y[s], y[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Ys[w][i][lane] = y[i];
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[b][r] = Ys[w][lq + 4 * r][lr];
+        // Y_bb -= T(bb, b) Y_b for the tiles below, the next one first
+#pragma unroll
+        for (int bb = b + 1; bb < NBLK; ++bb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double a = -Ts[cur][16 * bb + lr][4 * q + lq];
+                acc[bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, acc[b][q], acc[bb], 0, 0, 0);
+            }
+        if (b + 1 < NBLK) {
+#pragma unroll
+            for (int q = 0; q < NBLK - b - 1; ++q) {
+                int i, k;
+                strip_ik(b + 1, tid + q * 256, i, k);
+                Ts[cur ^ 1][i][k] = ((b + 1) & 1) ? pfb[q] : pfa[q];
+            }
+        }
+        lds_barrier();
+    }
+    if (cok) {
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[xidx(16 * b + lq + 4 * r)] = (TX)acc[b][r];
+    }
+}
+
+// Both block solves of step k in one launch (they depend only on the diagonal block):
+// workgroups [0, nwg) compute U12 = L11^{-1} A12 in place (the columns of A12 are the
+// right-hand sides), workgroups [nwg, 2 nwg) compute L21 = A21 U11^{-1}, i.e.
+// U11^T L21^T = A21^T (the rows of A21 are the right-hand sides).
+template <int NBLK, typename TF, typename TX>
+__global__ void __launch_bounds__(256, 1)
+panel_trsm_kernel(const TF* __restrict__ D, long long ldd, TX* A12, TX* A21, long long ldx, int m, int nwg) {
+    __shared__ double Ts[2][NBLK * 16][17];
+    __shared__ double Ys[4][16][17];
+    if ((int)blockIdx.x < nwg) blk_lower_solve<NBLK, false, true, false>(Ts, Ys, D, ldd, A12, ldx, m, blockIdx.x);
+    else blk_lower_solve<NBLK, true, false, true>(Ts, Ys, D, ldd, A21, ldx, m, blockIdx.x - nwg);
+}
+
+template <int NBLK, typename TF, typename TX>
+hipError_t panel_go(const void* D, long long ldd, void* A12, void* A21, long long ldx, int m, hipStream_t s) {
+    const int nwg = (m + 63) / 64;
+    hipLaunchKernelGGL((panel_trsm_kernel<NBLK, TF, TX>), dim3(2 * nwg), dim3(256), 0, s, (const TF*)D, ldd,
+                       (TX*)A12, (TX*)A21, ldx, m, nwg);
+    return hipGetLastError();
 }
 
 __device__ inline double readlane_d(double v, int lane) {
@@ -287,6 +438,20 @@ hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long 
     if (t_f32 && !x_f32) return dispatch<float, double>(kind, T, ldt, nb, X, ldx, ncols, s);
     if (t_f32 && x_f32) return dispatch<float, float>(kind, T, ldt, nb, X, ldx, ncols, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_panel_trsm(int f32, const void* D, long long ldd, int nb, void* A12, void* A21, long long ldx,
+                             int m, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    switch (nb) {
+        case 64: return f32 ? panel_go<4, float, float>(D, ldd, A12, A21, ldx, m, s)
+                            : panel_go<4, double, double>(D, ldd, A12, A21, ldx, m, s);
+        case 128: return f32 ? panel_go<8, float, float>(D, ldd, A12, A21, ldx, m, s)
+                             : panel_go<8, double, double>(D, ldd, A12, A21, ldx, m, s);
+        case 256: return f32 ? panel_go<16, float, float>(D, ldd, A12, A21, ldx, m, s)
+                             : panel_go<16, double, double>(D, ldd, A12, A21, ldx, m, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 namespace {
