@@ -218,6 +218,16 @@ def relative_residual(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> np.ndarray
     return np.linalg.norm(A @ X2 - B2, axis=0) / np.linalg.norm(B2, axis=0)
 
 
+def backward_error_2(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Normwise backward error per column in the 2-norm (Rigal-Gaches):
+    eta_j = ||b_j - A x_j||_2 / (||A||_2 ||x_j||_2 + ||b_j||_2), ||A||_2 from the SVD."""
+    X2 = np.asarray(X).reshape(X.shape[0], -1)
+    B2 = np.asarray(B).reshape(B.shape[0], -1)
+    R = residual(A, X2, B2)
+    a = np.linalg.norm(A, 2)
+    return np.linalg.norm(R, axis=0) / (a * np.linalg.norm(X2, axis=0) + np.linalg.norm(B2, axis=0))
+
+
 @dataclasses.dataclass
 class SolveResult:
     X: np.ndarray
@@ -252,6 +262,99 @@ def genp_solve(A, B, G, nb: Optional[int] = None, refine_steps: int = 2, tol: fl
     X = solve(LU, G, B)
     res = refine(A, G, LU, B, X, refine_steps, tol)
     return res, LU, info
+
+
+# ---------------------------------------------------------------------------
+# GMRES-based refinement (the correction equation A d = r solved by GMRES,
+# right-preconditioned with M^{-1} = G (LU)^{-1}, since A G (LU)^{-1} = I when
+# the factors are exact).  The paper refines with the factors directly
+# (section 7.1); GMRES on the correction equation is what the low-precision
+# form needs when kappa(C) u_low is not small.
+# ---------------------------------------------------------------------------
+
+def gmres(matvec, precond, r: np.ndarray, restart: int, max_iter: int, rtol: float):
+    """Right-preconditioned restarted GMRES for A d = r, from d = 0.
+
+    Arnoldi on A M^{-1} with modified Gram-Schmidt, Givens rotations on the
+    Hessenberg matrix, least-squares update at the end of each cycle.  Stops
+    when the (rotated) residual norm is <= rtol ||r||_2 or after max_iter inner
+    iterations.  Returns (d, inner iterations, residual-norm history)."""
+    r = np.asarray(r, dtype=np.float64)
+    n = r.shape[0]
+    d = np.zeros(n)
+    beta0 = np.linalg.norm(r)
+    hist = [beta0]
+    if beta0 == 0.0:
+        return d, 0, hist
+    its = 0
+    while its < max_iter:
+        res = r - matvec(d)
+        beta = np.linalg.norm(res)
+        if beta <= rtol * beta0:
+            break
+        m = min(restart, max_iter - its)
+        V = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[:, 0] = res / beta
+        k = 0
+        for j in range(m):
+            w = matvec(precond(V[:, j]))
+            for i in range(j + 1):                      # modified Gram-Schmidt
+                H[i, j] = w @ V[:, i]
+                w = w - H[i, j] * V[:, i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[:, j + 1] = w / H[j + 1, j]
+            for i in range(j):                          # earlier rotations
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])        # new rotation zeroing H[j+1, j]
+            cs[j], sn[j] = (1.0, 0.0) if den == 0.0 else (H[j, j] / den, H[j + 1, j] / den)
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            its += 1
+            hist.append(abs(g[j + 1]))
+            if abs(g[j + 1]) <= rtol * beta0 or H[j, j] == 0.0:
+                break
+        y = np.zeros(k)                                 # back substitution with the k x k triangle
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:]) / H[i, i]
+        d = d + precond(V[:, :k] @ y)
+        if hist[-1] <= rtol * beta0:
+            break
+    return d, its, hist
+
+
+def gmres_ir(A, G, LU, B, X, restart: int = 50, max_outer: int = 10, max_inner: int = 1000,
+             tol: float = 0.0, inner_rtol: float = 1e-10) -> SolveResult:
+    """Refinement whose correction d solves A d = r by preconditioned GMRES:
+    r = b - A x (FP64), d = GMRES(A, r; M^{-1} = G (LU)^{-1}), x += d, per column,
+    until eta_inf <= tol or max_outer steps."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    X2 = X.reshape(X.shape[0], -1)
+    B2 = np.asarray(B, dtype=np.float64).reshape(B.shape[0], -1)
+    hist = [float(np.max(backward_error_inf(A, X2, B2)))]
+    steps = 0
+    inner = 0
+    while steps < max_outer and hist[-1] > tol:
+        for c in range(X2.shape[1]):
+            r = B2[:, c] - A @ X2[:, c]
+            d, its, _ = gmres(lambda v: A @ v, lambda v: solve(LU, G, v), r, restart, max_inner, inner_rtol)
+            inner += its
+            X2[:, c] += d
+        steps += 1
+        hist.append(float(np.max(backward_error_inf(A, X2, B2))))
+    res = SolveResult(X2.reshape(X.shape), hist, steps)
+    res.inner = inner
+    return res
 
 
 # ---------------------------------------------------------------------------

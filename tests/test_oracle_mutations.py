@@ -5,8 +5,10 @@ dropped term, a wrong sign, a wrong index, a transposed operand) and the test
 asserts that at least one of the independent checks below fails with it and
 that all of them pass without it.
 """
+import inspect
 import json
 import os
+import textwrap
 
 import numpy as np
 import pytest
@@ -114,7 +116,40 @@ def check_adjoint_fd():
     return bool(abs(fa - dA[3, 7]) <= 1e-6 * max(1, abs(fa)) and abs(fb - dB[5, 1]) <= 1e-6 * max(1, abs(fb)))
 
 
-CHECKS = [check_golden, check_exact, check_gepp_and_eta, check_toeplitz_scipy, check_blocked, check_adjoint_fd]
+def check_eta2():
+    c, s_ = np.cos(np.pi / 6), np.sin(np.pi / 6)
+    A = np.array([[c, -s_], [s_, c]]) @ np.diag([3.0, 1.0])
+    x = np.array([[0.25], [0.0]])
+    b = np.array([[1.0], [0.0]])
+    r = np.array([1.0 - 0.75 * c, -0.75 * s_])
+    return bool(abs(og.backward_error_2(A, x, b)[0] - np.sqrt(r @ r) / 1.75) <= 1e-15)
+
+
+def check_gmres():
+    g = np.random.default_rng(4)
+    n = 30
+    A = g.standard_normal((n, n)) + 6 * np.eye(n)
+    r = g.standard_normal(n)
+    for k in (2, 3):
+        d, _, _ = og.gmres(lambda v: A @ v, lambda v: v, r, restart=n, max_iter=k, rtol=0.0)
+        K = np.stack([np.linalg.matrix_power(A, j) @ r for j in range(k)], axis=1)
+        c, *_ = np.linalg.lstsq(A @ K, r, rcond=None)
+        if abs(np.linalg.norm(r - A @ d) - np.linalg.norm(r - A @ K @ c)) > 1e-10 * np.linalg.norm(r):
+            return False
+    # preconditioned refinement with perturbed factors must reach eta <= 1e-14
+    g = np.random.default_rng(6)
+    n = 32
+    A = g.standard_normal((n, n))
+    G = g.standard_normal((n, n))
+    B = g.standard_normal((n, 1))
+    LU, _ = og.genp_unblocked(og.precondition(A, G))
+    LUp = LU * (1 + 1e-4 * g.standard_normal(LU.shape))
+    res = og.gmres_ir(A, G, LUp, B, og.solve(LUp, G, B), restart=10, max_outer=4, tol=1e-14)
+    return bool(res.eta_hist[-1] <= 1e-14)
+
+
+CHECKS = [check_golden, check_exact, check_gepp_and_eta, check_toeplitz_scipy, check_blocked, check_adjoint_fd,
+          check_eta2, check_gmres]
 
 
 def run_checks():
@@ -229,6 +264,34 @@ def _blocked_transposed_l21(C, nb, pivot_tol=0.0):
     return LU, og.FactorInfo(0, np.diag(LU), float(np.max(np.abs(C))), 1.0)
 
 
+def _from_source(fn, old, new):
+    """A copy of oracle function fn with one source line changed (the planted mistake)."""
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert old in src, old
+    ns = dict(vars(og))
+    exec(compile(src.replace(old, new, 1), "<mutant>", "exec"), ns)
+    return ns[fn.__name__]
+
+
+SOURCE_MUTANTS = {
+    "gmres: Gram-Schmidt adds the projection": (
+        "gmres", "w = w - H[i, j] * V[:, i]", "w = w + H[i, j] * V[:, i]"),
+    "gmres: rotated right-hand side loses its sign": (
+        "gmres", "g[j + 1] = -sn[j] * g[j]", "g[j + 1] = sn[j] * g[j]"),
+    "gmres: back substitution adds instead of subtracting": (
+        "gmres", "y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:]) / H[i, i]",
+        "y[i] = (g[i] + H[i, i + 1:k] @ y[i + 1:]) / H[i, i]"),
+    "gmres: preconditioner not applied to the correction": (
+        "gmres", "d = d + precond(V[:, :k] @ y)", "d = d + V[:, :k] @ y"),
+    "gmres: earlier rotation applied with the wrong sign": (
+        "gmres", "H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]",
+        "H[i + 1, j] = sn[i] * H[i, j] + cs[i] * H[i + 1, j]"),
+    "eta_2: Frobenius norm of A": (
+        "backward_error_2", "a = np.linalg.norm(A, 2)", "a = np.linalg.norm(A)"),
+    "gmres_ir: residual with the wrong sign": (
+        "gmres_ir", "r = B2[:, c] - A @ X2[:, c]", "r = A @ X2[:, c] - B2[:, c]"),
+}
+
 MUTANTS = {
     "genp: wrong sign in the Schur update": ("genp_unblocked", _genp_sign),
     "genp: multipliers not stored": ("genp_unblocked", _genp_no_divide),
@@ -254,5 +317,13 @@ def test_all_checks_pass_on_the_oracle():
 def test_mutant_is_caught(name, monkeypatch):
     attr, fn = MUTANTS[name]
     monkeypatch.setattr(og, attr, fn)
+    res = run_checks()
+    assert not all(res), f"mutant not caught: {name}"
+
+
+@pytest.mark.parametrize("name", sorted(SOURCE_MUTANTS))
+def test_source_mutant_is_caught(name, monkeypatch):
+    attr, old, new = SOURCE_MUTANTS[name]
+    monkeypatch.setattr(og, attr, _from_source(getattr(og, attr), old, new))
     res = run_checks()
     assert not all(res), f"mutant not caught: {name}"

@@ -349,3 +349,102 @@ def test_bf16_products_exact_in_fp64():
     eb = exact.to_frac(b)
     for i in range(0, 1000, 37):
         assert float(ea[i][0] * eb[i][0]) == a[i] * b[i]
+
+
+# ---------------------------------------------------------------------------
+# 2-norm backward error and the GMRES refinement reference
+# ---------------------------------------------------------------------------
+
+def test_backward_error_2_closed_form():
+    """A = Q diag(3, 1) (Q a rotation by 30 degrees) has ||A||_2 = 3 while its infinity-
+    and Frobenius norms differ, so a wrong norm changes eta_2.  With x = (t, 0) and
+    b = (1, 0): eta_2 = ||b - A x||_2 / (3 |t| + 1), written out by hand below."""
+    c, s_ = np.cos(np.pi / 6), np.sin(np.pi / 6)
+    Q = np.array([[c, -s_], [s_, c]])
+    A = Q @ np.diag([3.0, 1.0])
+    t = 0.25
+    x = np.array([[t], [0.0]])
+    b = np.array([[1.0], [0.0]])
+    r = np.array([1.0 - 3 * c * t, -3 * s_ * t])     # b - A x, with A e_1 = 3 Q e_1
+    expect = np.sqrt(r @ r) / (3 * abs(t) + 1.0)
+    assert abs(og.backward_error_2(A, x, b)[0] - expect) <= 1e-15
+    assert og.backward_error_2(A, np.zeros((2, 1)), b)[0] == 1.0
+
+
+def test_backward_error_2_rigal_gaches_perturbation():
+    """eta_2 is attained: dA = eta ||A||_2 r x^T / (||r|| ||x||), db = -eta ||b|| r / ||r||
+    satisfy (A + dA) x = b + db, with ||dA||_2 = eta ||A||_2 and ||db|| = eta ||b||."""
+    g = np.random.default_rng(3)
+    A = g.standard_normal((9, 9))
+    x = g.standard_normal((9, 1))
+    b = g.standard_normal((9, 1))
+    eta = og.backward_error_2(A, x, b)[0]
+    r = (b - A @ x)[:, 0]
+    a2 = np.linalg.svd(A, compute_uv=False)[0]
+    xn, rn, bn = np.linalg.norm(x), np.linalg.norm(r), np.linalg.norm(b)
+    dA = eta * a2 * np.outer(r, x[:, 0]) / (rn * xn)
+    db = -eta * bn * r / rn
+    assert np.allclose((A + dA) @ x[:, 0], b[:, 0] + db, atol=1e-12)
+    assert abs(np.linalg.svd(dA, compute_uv=False)[0] - eta * a2) <= 1e-12 * eta * a2
+
+
+def _identity_precond(v):
+    return v
+
+
+def test_gmres_minimal_residual_over_krylov_space():
+    """After k < n inner iterations (no restart), GMRES's correction minimizes
+    ||r - A d|| over d in K_k(A, r) = span{r, A r, ..., A^{k-1} r}: compare with the
+    least-squares solution on the explicit Krylov basis."""
+    g = np.random.default_rng(4)
+    n = 30
+    A = g.standard_normal((n, n)) + 6 * np.eye(n)
+    r = g.standard_normal(n)
+    for k in (1, 2, 3, 5):
+        d, its, _ = og.gmres(lambda v: A @ v, _identity_precond, r, restart=n, max_iter=k, rtol=0.0)
+        assert its == k
+        K = np.empty((n, k))
+        K[:, 0] = r
+        for j in range(1, k):
+            K[:, j] = A @ K[:, j - 1]
+        c, *_ = np.linalg.lstsq(A @ K, r, rcond=None)
+        best = np.linalg.norm(r - A @ K @ c)
+        assert abs(np.linalg.norm(r - A @ d) - best) <= 1e-10 * np.linalg.norm(r)
+        assert np.linalg.norm(d - K @ c) <= 1e-8 * np.linalg.norm(K @ c)
+
+
+def test_gmres_finite_termination_and_scipy():
+    """Without restarts GMRES solves an n x n system in at most n iterations; with
+    restarts it agrees with scipy's GMRES on a well-conditioned system."""
+    from scipy.sparse.linalg import gmres as sp_gmres
+    g = np.random.default_rng(5)
+    n = 16
+    A = g.standard_normal((n, n))
+    r = g.standard_normal(n)
+    d, its, _ = og.gmres(lambda v: A @ v, _identity_precond, r, restart=n, max_iter=n, rtol=1e-14)
+    assert its <= n
+    assert np.linalg.norm(r - A @ d) <= 1e-10 * np.linalg.norm(r)
+    B = g.standard_normal((60, 60)) + 12 * np.eye(60)
+    q = g.standard_normal(60)
+    d1, _, _ = og.gmres(lambda v: B @ v, _identity_precond, q, restart=8, max_iter=200, rtol=1e-12)
+    d2, info = sp_gmres(B, q, rtol=1e-12, atol=0.0, restart=8, maxiter=200)
+    assert info == 0
+    assert np.linalg.norm(d1 - d2) <= 1e-9 * np.linalg.norm(d2)
+    assert np.allclose(d1, np.linalg.solve(B, q), rtol=0, atol=1e-10)
+
+
+def test_gmres_ir_repairs_perturbed_factors():
+    """Factors of A G perturbed by 1e-4 relative (as low-precision factors would be):
+    plain refinement contracts slowly; GMRES-IR reaches eta_inf <= 1e-14."""
+    g = np.random.default_rng(6)
+    n = 48
+    A = g.standard_normal((n, n))
+    G = g.standard_normal((n, n))
+    B = g.standard_normal((n, 2))
+    LU, info = og.genp_unblocked(og.precondition(A, G))
+    LUp = LU * (1 + 1e-4 * g.standard_normal(LU.shape))
+    X0 = og.solve(LUp, G, B)
+    res = og.gmres_ir(A, G, LUp, B, X0, restart=10, max_outer=4, tol=1e-14)
+    assert res.eta_hist[-1] <= 1e-14
+    assert res.steps <= 3
+    assert np.allclose(res.X, np.linalg.solve(A, B), rtol=0, atol=1e-10 * np.max(np.abs(res.X)))
