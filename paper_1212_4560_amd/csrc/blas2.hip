@@ -48,47 +48,72 @@ __global__ void pad_identity_kernel(T* C, long long ldc, int n, int n_pad) {
     C[(long long)i * ldc + j] = (i == j) ? T(1) : T(0);
 }
 
+__device__ inline double nanmax(double m, double a) { return (a > m || isnan(a)) ? a : m; }
+
+// max |X(i, j)| (upper: j >= i only): one wave per row at a time, lanes across the
+// row (coalesced), four independent partial maxima per lane, one atomic per wave.
 template <typename T>
 __global__ void max_abs_kernel(const T* __restrict__ X, long long ldx, int rows, int cols, int upper,
                                unsigned long long* out) {
-    double m = 0.0;
-    const long long tot = (long long)rows * cols;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(e / cols), j = (int)(e % cols);
-        if (upper && j < i) continue;
-        const double a = fabs((double)X[(long long)i * ldx + j]);
-        m = (a > m || isnan(a)) ? a : m;
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int nw = (int)(((long long)gridDim.x * blockDim.x) >> 6);
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    for (int i = wave; i < rows; i += nw) {
+        const T* r = X + (long long)i * ldx;
+        int j = (upper ? i : 0) + lane;
+        for (; j + 192 < cols; j += 256) {
+            m0 = nanmax(m0, fabs((double)r[j]));
+            m1 = nanmax(m1, fabs((double)r[j + 64]));
+            m2 = nanmax(m2, fabs((double)r[j + 128]));
+            m3 = nanmax(m3, fabs((double)r[j + 192]));
+        }
+        for (; j < cols; j += 64) m0 = nanmax(m0, fabs((double)r[j]));
     }
+    double m = nanmax(nanmax(m0, m1), nanmax(m2, m3));
     m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+    if (lane == 0) atomic_max_nonneg(out, m);
 }
 
+// max_i sum_j |A(i, j)| (the infinity norm): one wave per row, one atomic per row.
 __global__ void row_abs_sum_max_kernel(const double* __restrict__ A, long long lda, int n,
                                        unsigned long long* out) {
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= n) return;
     const double* r = A + (long long)row * lda;
-    double s = 0.0;
-    for (int k = lane; k < n; k += 64) s += fabs(r[k]);
-    s = wave_sum(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = lane;
+    for (; k + 192 < n; k += 256) {
+        s0 += fabs(r[k]);
+        s1 += fabs(r[k + 64]);
+        s2 += fabs(r[k + 128]);
+        s3 += fabs(r[k + 192]);
+    }
+    for (; k < n; k += 64) s0 += fabs(r[k]);
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) atomic_max_nonneg(out, s);
 }
 
+// out[c] = max_i |X(i, c)| for cols <= 256 columns: threads stride over rows, the
+// block combines its partial maxima in LDS, one atomic per column per block.
 __global__ void col_abs_max_kernel(const double* __restrict__ X, long long ldx, int rows, int cols,
                                    unsigned long long* out) {
-    // block: 256 threads = cols-strided over a chunk of rows
+    __shared__ double red[256];
+    const int per = blockDim.x / cols;
     const int c = threadIdx.x % cols;
-    const int rstart = blockIdx.x * (blockDim.x / cols) + threadIdx.x / cols;
-    const int rstep = gridDim.x * (blockDim.x / cols);
-    if (threadIdx.x >= (blockDim.x / cols) * cols) return;
+    const int rr = threadIdx.x / cols;
     double m = 0.0;
-    for (int i = rstart; i < rows; i += rstep) {
-        const double a = fabs(X[(long long)i * ldx + c]);
-        m = (a > m || isnan(a)) ? a : m;
+    if (rr < per) {
+        for (int i = blockIdx.x * per + rr; i < rows; i += gridDim.x * per) m = nanmax(m, fabs(X[(long long)i * ldx + c]));
     }
-    atomic_max_nonneg(out + c, m);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    if ((int)threadIdx.x < cols) {
+        double v = 0.0;
+        for (int t = 0; t < per; ++t) v = nanmax(v, red[t * cols + threadIdx.x]);
+        atomic_max_nonneg(out + threadIdx.x, v);
+    }
 }
 
 template <typename T>
@@ -264,7 +289,7 @@ hipError_t launch_max_abs(int prec, const void* X, long long ldx, int rows, int 
                           unsigned long long* out, hipStream_t s) {
     const long long tot = (long long)rows * cols;
     if (tot <= 0) return hipSuccess;
-    const unsigned g = (unsigned)std::min<long long>(blocks_for(tot, 256), 4096);
+    const unsigned g = (unsigned)std::min<long long>((rows + 3) / 4, 2048);
     if (prec == PREC_F64)
         hipLaunchKernelGGL(max_abs_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)X, ldx,
                            rows, cols, upper, out);
@@ -284,7 +309,7 @@ hipError_t launch_col_abs_max(const double* X, long long ldx, int rows, int cols
                               unsigned long long* out, hipStream_t s) {
     if (cols <= 0 || cols > 256 || rows <= 0) return cols > 256 ? hipErrorInvalidValue : hipSuccess;
     const int per = 256 / cols;
-    const unsigned g = (unsigned)std::min<long long>((rows + per - 1) / per, 1024);
+    const unsigned g = (unsigned)std::min<long long>((rows + per - 1) / per, 256);
     hipLaunchKernelGGL(col_abs_max_kernel, dim3(g), dim3(256), 0, s, X, ldx, rows, cols, out);
     return hipGetLastError();
 }

@@ -73,6 +73,9 @@ struct genp_ctx {
     std::vector<hipEvent_t> ev_step;
     hipStream_t side = nullptr;        // look-ahead stream for the next panel (default priority)
     bool lookahead = true;
+    // chained triangular solves (<= 4 right-hand sides): ticket, sticky error word, one flag per 64 rows
+    unsigned* tsync = nullptr;
+    bool trsv_chain = true;
     double anorm = 0.0;
 };
 
@@ -177,7 +180,12 @@ int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const size_t es = esize(c->prec);
     const char* Cb = (const char*)c->C;
     if (k <= 4) {
-        // few right-hand sides: one fused launch per 128-row block (update + triangle)
+        // few right-hand sides: one chained launch per triangle (or one launch per 128-row block)
+        if (c->trsv_chain) {
+            HIPCK(launch_trsv_chain(TRSM_L_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->stream));
+            HIPCK(launch_trsv_chain(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->stream));
+            return GENP_OK;
+        }
         const int bs = nb >= 128 ? 128 : 64;
         HIPCK(launch_trsv_full(TRSM_L_UNIT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
         HIPCK(launch_trsv_full(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
@@ -214,6 +222,12 @@ int lu_solve_trans_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const size_t es = esize(c->prec);
     const char* Cb = (const char*)c->C;
     if (k <= 4) {
+        if (c->trsv_chain) {
+            HIPCK(launch_trsv_chain(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->stream));
+            HIPCK(launch_trsv_chain(TRSM_LT_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync,
+                                    c->stream));
+            return GENP_OK;
+        }
         const int bs = nb >= 128 ? 128 : 64;
         HIPCK(launch_trsv_full(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
         HIPCK(launch_trsv_full(TRSM_LT_UNIT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
@@ -462,7 +476,9 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
     const size_t nblk = c->n_pad / nb;
     bool ok = hipMalloc(&c->C, (size_t)c->n_pad * c->ldc * esize(prec)) == hipSuccess &&
               hipMalloc(&c->stats, nblk * sizeof(PanelStats)) == hipSuccess &&
-              hipMalloc(&c->red, (R_COLS + 3 * 256) * sizeof(unsigned long long)) == hipSuccess;
+              hipMalloc(&c->red, (R_COLS + 3 * 256) * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&c->tsync, (c->n_pad / 64 + 2) * sizeof(unsigned)) == hipSuccess &&
+              hipMemset(c->tsync, 0, (c->n_pad / 64 + 2) * sizeof(unsigned)) == hipSuccess;
     for (int e = 0; ok && e < EV_N; ++e)
         ok = hipEventCreate(&c->ev0[e]) == hipSuccess && hipEventCreate(&c->ev1[e]) == hipSuccess;
     for (int e = 0; ok && e < 2; ++e) ok = hipEventCreate(&c->ev_ag[e]) == hipSuccess;
@@ -476,6 +492,8 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
     if (ok) {
         const char* la = getenv("GENP_LOOKAHEAD");
         c->lookahead = !(la && la[0] == '0');
+        const char* tv = getenv("GENP_TRSV");   // "step": one launch per block instead of the chained solve
+        c->trsv_chain = !(tv && strcmp(tv, "step") == 0);
     }
     if (ok) ok = ensure_rhs(c, 4) == GENP_OK;
     if (!ok) {
@@ -497,6 +515,7 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->C);
     hipFree(c->stats);
     hipFree(c->red);
+    hipFree(c->tsync);
     hipFree(c->p);
     hipFree(c->p_rev);
     hipFree(c->Z);
@@ -766,6 +785,16 @@ int genp_solve(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* 
     return GENP_OK;
 }
 
+// The chained solves record a wait that exceeded its safety limit in a sticky word;
+// the synchronizing calls report it (the solutions computed since are invalid).
+static int chain_status(genp_ctx* c) {
+    if (!c->trsv_chain) return GENP_OK;
+    unsigned err = 0;
+    HIPCK(hipMemcpyAsync(&err, c->tsync + 1, sizeof err, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return err ? GENP_EDEVICE : GENP_OK;
+}
+
 int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, int max_iter,
                 double tol, int solver, double* eta_out) {
     CK(check_ctx(c));
@@ -825,6 +854,7 @@ int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double*
     }
     ev_end(c, EV_REF);
     HIPCK(hipStreamSynchronize(c->stream));
+    CK(chain_status(c));
     c->info.iters = it;
     c->info.inner_iters = inner_total;
     c->info.eta = max_of(eta);
@@ -887,6 +917,7 @@ int genp_get_info(const genp_ctx* cc, genp_info* out) {
     CK(check_ctx(c));
     if (!out) return GENP_EINVAL;
     HIPCK(hipStreamSynchronize(c->stream));
+    CK(chain_status(c));
     float ms;
     double* slots[EV_N] = {&c->info.ms_precond, &c->info.ms_factor, &c->info.ms_solve, &c->info.ms_refine,
                            &c->info.ms_backward};

@@ -310,10 +310,11 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
             for (int s = 0; s < NS; ++s)
                 a[q][s] = (r < r_end) ? (double)T[tat<TT>(r, pc0 + s * 64 + lane, ldt)] : 0.0;
         }
+        // all RPW dot products first; then the read-modify-write of X as one batch of
+        // loads followed by the stores (a load of X cannot move above an earlier store to X)
+        double res[RPW];
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
-            const int r = rf + q * rstep;
-            if (r >= r_end) break;
             double acc[NR];
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
@@ -323,12 +324,23 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
             }
-            if (lane < NR) {
-                double v = 0.0;
+            double v = 0.0;
 #pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    if (c == lane) v = acc[c];
-                X[(long long)r * ldx + lane] -= v;
+            for (int c = 0; c < NR; ++c)
+                if (c == lane) v = acc[c];
+            res[q] = v;
+        }
+        if (lane < NR) {
+            double old[RPW];
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int r = rf + q * rstep;
+                old[q] = (r < r_end) ? X[(long long)r * ldx + lane] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int r = rf + q * rstep;
+                if (r < r_end) X[(long long)r * ldx + lane] = old[q] - res[q];
             }
         }
     };
@@ -342,12 +354,13 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
     __shared__ double Ts[BS][BS + 1];
     __shared__ double rdiag[BS];
     const int r0 = t * BS;
-    constexpr int LPT = BS * BS / 256;   // staged elements per thread, loaded in batches of 16
+    constexpr int LPT = BS * BS / 256;   // staged elements per thread, all loads issued together
+    constexpr int LB = LPT < 64 ? LPT : 64;
 #pragma unroll
-    for (int q0 = 0; q0 < LPT; q0 += 16) {
-        double v[16];
+    for (int q0 = 0; q0 < LPT; q0 += LB) {
+        double v[LB];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < LB; ++q) {
             const int e = tid + (q0 + q) * 256;
             int r, c;
             if (TT) { c = e / BS; r = e % BS; }
@@ -355,7 +368,7 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
             v[q] = (double)T[tat<TT>(r0 + r, r0 + c, ldt)];
         }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < LB; ++q) {
             const int e = tid + (q0 + q) * 256;
             int r, c;
             if (TT) { c = e / BS; r = e % BS; }
@@ -406,6 +419,135 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
     for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int c = 0; c < NR; ++c) X[(long long)(r0 + s * 64 + lane) * ldx + c] = x[s][c];
+}
+
+// Whole triangular solve T x = b for 1..4 right-hand sides in ONE launch, 64-row
+// blocks.  Workgroups take their position in the elimination order from an atomic
+// ticket, so a workgroup only ever waits for blocks owned by workgroups that started
+// before it: the chain always progresses, whether or not every workgroup is resident.
+// Block t: stage the diagonal block in LDS; for every earlier block p (in solve
+// order) wait for its published solution x_p, accumulate T(t, p) x_p (the 64 x 64
+// block is prefetched one step ahead through registers into LDS); then substitute
+// with the diagonal block (one wave, readlane broadcast), store x_t, and publish it.
+// Publication: the writer's release fence at device scope, then a flag; the reader
+// polls the flag, then acquires.  sync[0]: ticket, sync[1]: sticky error word (a
+// wait exceeded spin_limit polls: the result is invalid), sync[2 + b]: flag of
+// block b.  The caller clears sync[0] and the flags before every launch.
+template <bool LOWER, bool UNIT, bool TT, int NR, typename TF>
+__global__ void __launch_bounds__(256)
+trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, long long ldx,
+                  unsigned* sync, unsigned spin_limit) {
+    constexpr int BS = 64;
+    __shared__ double Td[BS][BS + 1];
+    __shared__ double To[2][BS][BS + 1];
+    __shared__ double xs[BS][NR];
+    __shared__ double zs[BS][NR];
+    __shared__ int s_q;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_q = (int)atomicAdd(&sync[0], 1u);
+    __syncthreads();
+    const int q = s_q;
+    const int t = LOWER ? q : nblk - 1 - q;
+    const long long r0 = (long long)t * BS;
+    // 64 x 64 block (rb, cb) of the operator, 16 elements per thread, coalesced for either access
+    auto load_blk = [&](int rb, int cb, double (&v)[16]) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
+            const int i = TT ? (e & 63) : (e >> 6), j = TT ? (e >> 6) : (e & 63);
+            v[k] = (double)T[tat<TT>((long long)rb * BS + i, (long long)cb * BS + j, ldt)];
+        }
+    };
+    auto store_blk = [&](double (*dst)[BS + 1], const double (&v)[16]) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
+            const int i = TT ? (e & 63) : (e >> 6), j = TT ? (e >> 6) : (e & 63);
+            dst[i][j] = v[k];
+        }
+    };
+    auto order = [&](int s_) { return LOWER ? s_ : nblk - 1 - s_; };
+    {
+        double v[16];
+        load_blk(t, t, v);
+        store_blk(Td, v);
+    }
+    double vn[16];
+    if (q > 0) {
+        load_blk(t, order(0), vn);
+        store_blk(To[0], vn);
+    }
+    const int ri = tid >> 2, part = tid & 3;   // row and column quarter of the block products
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    for (int s_ = 0; s_ < q; ++s_) {
+        const int p = order(s_);
+        const int buf = s_ & 1;
+        if (s_ + 1 < q) load_blk(t, order(s_ + 1), vn);
+        if (tid == 0) {
+            unsigned it = 0;
+            while (__hip_atomic_load(&sync[2 + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                if (++it > spin_limit) {
+                    __hip_atomic_fetch_or(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (tid < BS * NR) xs[tid / NR][tid % NR] = X[((long long)p * BS + tid / NR) * ldx + tid % NR];
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = part * 16 + jj;
+            const double a = To[buf][ri][j];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(a, xs[j][c], acc[c]);
+        }
+        if (s_ + 1 < q) store_blk(To[buf ^ 1], vn);
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        acc[c] += __shfl_xor(acc[c], 1, 64);
+        acc[c] += __shfl_xor(acc[c], 2, 64);
+    }
+    if (part == 0) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) zs[ri][c] = X[(r0 + ri) * ldx + c] - acc[c];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double z[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) z[c] = zs[lane][c];
+        const double rd = UNIT ? 1.0 : 1.0 / Td[lane][lane];
+        for (int u = 0; u < BS; ++u) {
+            const int i = LOWER ? u : BS - 1 - u;
+            const double ri_ = UNIT ? 1.0 : readlane_d(rd, i);
+            const double m = Td[lane][i];
+            const bool upd = LOWER ? lane > i : lane < i;
+            const bool own = lane == i;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const double xi = readlane_d(z[c], i) * ri_;
+                const double nv = fma(-m, xi, z[c]);
+                z[c] = own ? xi : (upd ? nv : z[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) X[(r0 + lane) * ldx + c] = z[c];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&sync[2 + t], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void trsv_chain_reset_kernel(unsigned* sync, int nblk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) sync[0] = 0u;
+    if (i < nblk) sync[2 + i] = 0u;
 }
 
 template <bool LOWER, bool UNIT, bool TT, bool XT, typename TF, typename TX>
@@ -496,6 +638,51 @@ hipError_t trsv_kind(int kind, const void* T, long long ldt, int n_pad, double* 
 }
 
 }  // namespace
+
+namespace {
+
+template <bool LOWER, bool UNIT, bool TT, typename TF>
+hipError_t chain_go(const void* T, long long ldt, int nblk, double* X, long long ldx, int nr, unsigned* sync,
+                    hipStream_t s) {
+    constexpr unsigned kSpin = 1u << 20;   // polls (about 1 s in all): a safety limit a running chain never reaches
+    hipLaunchKernelGGL(trsv_chain_reset_kernel, dim3((nblk + 255) / 256), dim3(256), 0, s, sync, nblk);
+    switch (nr) {
+#define GENP_CHAIN_CASE(NR)                                                                                      \
+    case NR:                                                                                                     \
+        hipLaunchKernelGGL((trsv_chain_kernel<LOWER, UNIT, TT, NR, TF>), dim3(nblk), dim3(256), 0, s, (const TF*)T, \
+                           ldt, nblk, X, ldx, sync, kSpin);                                                      \
+        break;
+        GENP_CHAIN_CASE(1)
+        GENP_CHAIN_CASE(2)
+        GENP_CHAIN_CASE(3)
+        GENP_CHAIN_CASE(4)
+#undef GENP_CHAIN_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t chain_kind(int kind, const void* T, long long ldt, int nblk, double* X, long long ldx, int nr,
+                      unsigned* sync, hipStream_t s) {
+    switch (kind) {
+        case TRSM_L_UNIT: return chain_go<true, true, false, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
+        case TRSM_U: return chain_go<false, false, false, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
+        case TRSM_UT: return chain_go<true, false, true, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
+        case TRSM_LT_UNIT: return chain_go<false, true, true, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_trsv_chain(int kind, int t_f32, const void* T, long long ldt, int n_pad, double* X, long long ldx,
+                             int nr, unsigned* sync, hipStream_t s) {
+    if (nr < 1 || nr > 4 || n_pad % 64) return hipErrorInvalidValue;
+    const int nblk = n_pad / 64;
+    return t_f32 ? chain_kind<float>(kind, T, ldt, nblk, X, ldx, nr, sync, s)
+                 : chain_kind<double>(kind, T, ldt, nblk, X, ldx, nr, sync, s);
+}
 
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
                             long long ldx, int nr, hipStream_t s) {
