@@ -226,7 +226,7 @@ def main() -> int:
 
     ag_avg = sum(ag_ms) / len(ag_ms)
     achieved = 2.0 * n ** 3 / (ag_avg * 1e-3) / 1e12
-    roof = {"kernel": "gemm_f64_kernel (C = A G, Toeplitz G generated in-kernel)", "bound": "mfma",
+    roof = {"kernel": "gemm_ag_toep_kernel (C = A G, Toeplitz G generated in-kernel)", "bound": "mfma",
             "achieved": round(achieved, 2), "peak": PEAK[args.prec], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[args.prec], 4), "traffic": None,
             "avg_ms": round(ag_avg, 3), "algorithmic_flop_per_launch": 2.0 * n ** 3}

@@ -233,6 +233,81 @@ gemm_f64_kernel(GemmF64Args g) {
     }
 }
 
+// C = A G with G the Toeplitz matrix of parameters p (G(k, j) = p[k - j + K - 1]):
+// the plain product on interior tiles only (M, N multiples of 128, K of 32), with no
+// bounds checks and a 32-deep K chunk per barrier (the generated operand needs only a
+// window of BNt + 31 parameters in LDS, so two blocks still fit on a CU).  Same tile
+// layout and tile order as gemm_f64_kernel with one tile-row per group.
+__global__ void __launch_bounds__(256, 2)
+gemm_ag_toep_kernel(int M, int N, int K, const double* __restrict__ A, long long lda,
+                    const double* __restrict__ p, double* __restrict__ D, long long ldd) {
+    constexpr int BKT = 32, BMt = 128, BNt = 128, T = 256;
+    constexpr int LA = BMt * BKT / T, PB = BNt + BKT - 1;
+    __shared__ double As[2][BKT][BMt + 1];
+    __shared__ double Bs[2][PB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int ntn = N / BNt, total = (M / BMt) * ntn;
+    const int pid = xcd_remap(blockIdx.x, total);
+    const int m0 = (pid / ntn) * BMt, n0 = (pid % ntn) * BNt;
+    const int nk = K / BKT;
+    const int lr = lane & 15, lq = lane >> 4;
+    double ra[LA], rb;
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int e = tid + r * T;
+            ra[r] = A[(long long)(m0 + e / BKT) * lda + k0 + e % BKT];
+        }
+        // window of p over k - j in [k0 - n0 - BNt + 1, k0 + BKT - 1 - n0]
+        const long long idx = (long long)k0 - n0 - (BNt - 1) + K - 1 + tid;
+        rb = (tid < PB && idx >= 0 && idx < 2LL * K - 1) ? p[idx] : 0.0;
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int e = tid + r * T;
+            As[buf][e % BKT][e / BKT] = ra[r];
+        }
+        if (tid < PB) Bs[buf][tid] = rb;
+    };
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * BKT);
+#pragma unroll
+        for (int kk = 0; kk < BKT; kk += 4) {
+            double af[4], bf[4];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) af[mi] = As[cur][kk + lq][wm * 64 + mi * 16 + lr];
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[cur][(kk + lq) - (wn * 64 + ni * 16 + lr) + BNt - 1];
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                D[(long long)(m0 + wm * 64 + mi * 16 + lq + 4 * r) * ldd + n0 + wn * 64 + ni * 16 + lr] =
+                    acc[mi][ni][r];
+}
+
 __global__ void splitk_reduce_kernel(int M, int N, int ks, const double* __restrict__ P, long long ldp,
                                      long long ss, double alpha, double beta, const double* Cin,
                                      long long ldci, double* D, long long ldd) {
@@ -276,6 +351,13 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
         if (a.amode == OP_N) return launch_t<2, 1, OP_N, OP_N, true>(a, s);
         if (a.amode == OP_T) return launch_t<2, 1, OP_T, OP_N, true>(a, s);
         return hipErrorInvalidValue;
+    }
+    if (tile == 0 && a.amode == OP_N && a.bmode == OP_TOEP && a.ksplit <= 1 && a.alpha == 1.0 && a.beta == 0.0 &&
+        a.M % 128 == 0 && a.N % 128 == 0 && a.K % 32 == 0 && a.K == a.ldb) {
+        // the multiplier product on full tiles (ldb carries the Toeplitz order, which is K)
+        hipLaunchKernelGGL(gemm_ag_toep_kernel, dim3((a.M / 128) * (a.N / 128)), dim3(256), 0, s, a.M, a.N, a.K, a.A,
+                           a.lda, a.B, a.D, a.ldd);
+        return hipGetLastError();
     }
     switch (tile) {
         case 0: return dispatch_modes<2, 2>(a, s);

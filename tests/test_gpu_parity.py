@@ -39,9 +39,10 @@ def _say(*a):
 
 # ------------------------------------------------------------------ C = A G ----
 
-@pytest.mark.parametrize("n", [1, 7, 64, 200, 256, 517])
+@pytest.mark.parametrize("n", [1, 7, 64, 200, 256, 517, 640])
 @pytest.mark.parametrize("mult", ["dense", "toeplitz"])
 def test_precondition_entrywise(n, mult):
+    """Sizes on both sides of the full-tile Toeplitz product (n a multiple of 128: 256, 640)."""
     _say(f"precondition n={n} mult={mult}")
     g = np.random.default_rng(n)
     A = g.standard_normal((n, n))
