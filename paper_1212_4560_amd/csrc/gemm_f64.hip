@@ -279,11 +279,9 @@ gemm_ag_toep_kernel(int M, int N, int K, const double* __restrict__ A, long long
     gload(0);
     sstore(0);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * BKT);
+    auto mfma_chunk = [&](int cur, int kk0, int kk1) {
 #pragma unroll
-        for (int kk = 0; kk < BKT; kk += 4) {
+        for (int kk = kk0; kk < kk1; kk += 4) {
             double af[4], bf[4];
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi) af[mi] = As[cur][kk + lq][wm * 64 + mi * 16 + lr];
@@ -295,7 +293,18 @@ gemm_ag_toep_kernel(int M, int N, int K, const double* __restrict__ A, long long
                 for (int ni = 0; ni < 4; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
         }
+    };
+    // Per chunk: issue the next chunk's loads, run half the MFMAs, write the next chunk to
+    // LDS (its loads have had half a chunk to land), run the other half.  The wave runs
+    // at raised priority through the MFMA stream and drops it before the barrier.
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * BKT);
+        __builtin_amdgcn_s_setprio(1);
+        mfma_chunk(cur, 0, BKT / 2);
         if (kt + 1 < nk) sstore(cur ^ 1);
+        mfma_chunk(cur, BKT / 2, BKT);
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
 #pragma unroll
