@@ -644,28 +644,37 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     hipStream_t S = c->stream, P = c->side;
     auto ev = [&](int64_t b, int i) { return c->ev_step[6 * b + i]; };
     // panel j: diagonal block LU, then U12 = L11^{-1} A12 and L21 = A21 U11^{-1} by substitution
-    auto panel = [&](int64_t j, hipStream_t st) -> int {
+    auto diag = [&](int64_t j, hipStream_t st) -> int {
         const int64_t k = j * nb;
-        void* Dk = at(k, k);
         const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
         HIPCK(hipEventRecord(ev(j, 2), st));
-        HIPCK(launch_diag_lu(c->prec, Dk, ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+        HIPCK(launch_diag_lu(c->prec, at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+        return GENP_OK;
+    };
+    auto solves = [&](int64_t j, hipStream_t st) -> int {
+        const int64_t k = j * nb;
         const int64_t m = np - k - nb;
-        if (m > 0) {
-            HIPCK(launch_panel_trsm(lp, Dk, ldc, (int)nb, at(k, k + nb), at(k + nb, k), ldc, (int)m, st));
-        }
+        if (m > 0)
+            HIPCK(launch_panel_trsm(lp, at(k, k), ldc, (int)nb, at(k, k + nb), at(k + nb, k), ldc, (int)m, st));
         HIPCK(hipEventRecord(ev(j, 3), st));
         return GENP_OK;
     };
-    // Schur update of step j restricted to rows [r0, r0 + M) x cols [c0, c0 + N) of the trailing block
-    auto schur = [&](int64_t j, int64_t r0, int64_t c0, int64_t M, int64_t N, hipStream_t st) -> int {
+    auto panel = [&](int64_t j, hipStream_t st) -> int {
+        CK(diag(j, st));
+        return solves(j, st);
+    };
+    // Schur update of steps j .. j+kb-1 (kb = 1 or 2: their L21 columns and U12 rows are
+    // adjacent, so both updates are one product with K = kb nb), restricted to rows
+    // [r0, r0 + M) x cols [c0, c0 + N) of the trailing block
+    auto schur = [&](int64_t j, int64_t r0, int64_t c0, int64_t M, int64_t N, hipStream_t st, int kb = 1) -> int {
         if (M <= 0 || N <= 0) return GENP_OK;
         const int64_t k = j * nb;
+        const int KK = (int)(kb * nb);
         if (lp) {
             GemmLpArgs g{};
             g.M = (int)M;
             g.N = (int)N;
-            g.K = (int)nb;
+            g.K = KK;
             g.A = at(r0, k);             // L21 rows r0..
             g.lda = ldc;
             g.amode = OP_N;
@@ -687,7 +696,7 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         g.ksplit = 1;
         g.M = (int)M;
         g.N = (int)N;
-        g.K = (int)nb;
+        g.K = KK;
         g.A = C + r0 * ldc + k;          // L21 rows r0..
         g.lda = ldc;
         g.amode = OP_N;
@@ -704,26 +713,62 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         return GENP_OK;
     };
     ev_begin(c, EV_FAC);
-    CK(panel(0, S));
-    for (int64_t j = 0; j + 1 < K; ++j) {
-        const int64_t r1 = (j + 1) * nb, m = np - r1;
-        HIPCK(hipEventRecord(ev(j, 0), S));
-        if (c->lookahead) {
-            // cross: block column j+1 and block row j+1 first, so panel j+1 can start
-            CK(schur(j, r1, r1, m, nb, S));
-            CK(schur(j, r1, r1 + nb, nb, m - nb, S));
-            HIPCK(hipEventRecord(ev(j, 4), S));
-            HIPCK(hipStreamWaitEvent(P, ev(j, 4), 0));
-            CK(panel(j + 1, P));
-            HIPCK(hipEventRecord(ev(j + 1, 5), P));
-            CK(schur(j, r1 + nb, r1 + nb, m - nb, m - nb, S));
-            HIPCK(hipEventRecord(ev(j, 1), S));
-            HIPCK(hipStreamWaitEvent(S, ev(j + 1, 5), 0));
-        } else {
-            CK(schur(j, r1, r1, m, m, S));
-            HIPCK(hipEventRecord(ev(j, 1), S));
-            CK(panel(j + 1, S));
+    // Steps go in pairs (a, a+1) so that the bulk of the trailing matrix takes both
+    // Schur updates as one product with K = 2 nb.  Invariant at the top of the loop:
+    // panels a and a+1 are factored, and the trailing block from row/column (a+2) nb
+    // has every update before step a.  Per pair, on the main stream: updates a, a+1 on
+    // the next two block columns and rows; the first half of the bulk update; the block
+    // solves of panel a+2; update a+2 on block a+3; the second half of the bulk; the
+    // block solves of panel a+3.  The two diagonal-block factorizations (one workgroup
+    // each) run on the side stream, each under one half of the bulk.  The block solves
+    // need the whole GPU for a short time, so they run between the halves rather than
+    // beside them.  Without look-ahead the same products run in the same order on one
+    // stream (identical values).
+    hipStream_t PS = c->lookahead ? P : S;
+    auto diag_async = [&](int64_t j, int e_after) -> int {
+        // diagonal block j on the side stream once the main stream reaches this point
+        if (PS != S) {
+            HIPCK(hipEventRecord(ev(j, e_after), S));
+            HIPCK(hipStreamWaitEvent(PS, ev(j, e_after), 0));
         }
+        CK(diag(j, PS));
+        if (PS != S) HIPCK(hipEventRecord(ev(j, 5), PS));
+        return GENP_OK;
+    };
+    auto wait_diag = [&](int64_t j) -> int {
+        if (PS != S) HIPCK(hipStreamWaitEvent(S, ev(j, 5), 0));
+        return GENP_OK;
+    };
+    CK(panel(0, S));
+    if (K > 1) {
+        CK(schur(0, nb, nb, np - nb, nb, S));
+        CK(schur(0, nb, 2 * nb, nb, np - 2 * nb, S));
+        CK(panel(1, S));
+    }
+    for (int64_t a = 0; a + 2 < K; a += 2) {
+        const int64_t r2 = (a + 2) * nb, m = np - r2;
+        const int64_t nb2 = std::min<int64_t>(2, K - (a + 2));   // panels in the next pair
+        const int64_t w = nb2 * nb;
+        const int64_t rb = r2 + w, mb = m - w;                   // the bulk: rows/cols rb.. (mb of them)
+        const int64_t n1 = (mb / 2 + nb - 1) / nb * nb;          // its first column half
+        HIPCK(hipEventRecord(ev(a, 0), S));
+        CK(schur(a, r2, r2, m, w, S, 2));
+        CK(schur(a, r2, r2 + w, w, m - w, S, 2));
+        CK(diag_async(a + 2, 4));
+        CK(schur(a, rb, rb, mb, n1, S, 2));
+        CK(wait_diag(a + 2));
+        CK(solves(a + 2, S));
+        if (nb2 == 2) {
+            CK(schur(a + 2, r2 + nb, r2 + nb, m - nb, nb, S));
+            CK(schur(a + 2, r2 + nb, r2 + 2 * nb, nb, m - 2 * nb, S));
+            CK(diag_async(a + 3, 4));
+        }
+        CK(schur(a, rb, rb + n1, mb, mb - n1, S, 2));
+        if (nb2 == 2) {
+            CK(wait_diag(a + 3));
+            CK(solves(a + 3, S));
+        }
+        HIPCK(hipEventRecord(ev(a, 1), S));
     }
     HIPCK(launch_max_abs(c->prec, c->C, ldc, (int)c->n, (int)c->n, 1, c->red + R_MAXU, c->stream));
     ev_end(c, EV_FAC);
@@ -735,10 +780,15 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     HIPCK(hipStreamSynchronize(c->stream));
     double ms_s = 0.0, ms_p = 0.0;
     int ns = 0;
+    // query only events recorded by this schedule: an unrecorded one would leave an error
+    // behind for the next launch check
     for (int64_t b = 0; b < nblk; ++b) {
-        float t0 = 0.f, t1 = 0.f;
+        float t0 = 0.f;
         if (hipEventElapsedTime(&t0, c->ev_step[6 * b + 2], c->ev_step[6 * b + 3]) == hipSuccess) ms_p += t0;
-        if (b + 1 < nblk && hipEventElapsedTime(&t1, c->ev_step[6 * b], c->ev_step[6 * b + 1]) == hipSuccess) {
+    }
+    for (int64_t a = 0; a + 2 < nblk; a += 2) {
+        float t1 = 0.f;
+        if (hipEventElapsedTime(&t1, c->ev_step[6 * a], c->ev_step[6 * a + 1]) == hipSuccess) {
             ms_s += t1;
             ++ns;
         }

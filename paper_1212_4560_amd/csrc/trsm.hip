@@ -129,20 +129,24 @@ trsm_cols_kernel(const TF* __restrict__ T, long long ldt, int nb, TX* X, long lo
 // acc[b] is exactly the B operand of the 16x16x4 MFMA for rows 16 b + 4 q .. + 3 of
 // Y (lane l: k = l / 16, column l % 16), so the solved tiles feed the update of the
 // tiles below with no data movement.  The diagonal blocks are solved by
-// substitution in the same order as a column sweep, with division by the pivot.
+// substitution in the same order as a column sweep, with division by the pivot,
+// in place in the accumulators (cross-lane broadcast of each solved row).
 // T is staged through LDS one 16-column strip at a time (rows 16 b .. NB - 1),
-// prefetched two strips ahead through registers.  Only LDS traffic is fenced at the
+// prefetched one strip ahead through registers.  Only LDS traffic is fenced at the
 // barriers, so the prefetch stays in flight across them.
 template <int NBLK, bool TT, bool UNIT, bool XT, typename TF, typename TX>
-__device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], double (*Ys)[16][17],
-                                                const TF* __restrict__ T, long long ldt, TX* X, long long ldx,
-                                                int ncols, int wg) {
+__device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], const TF* __restrict__ T,
+                                                long long ldt, TX* X, long long ldx, int ncols, int wg) {
     constexpr int NB = NBLK * 16;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
     const int cc = wg * 64 + w * 16 + lr;
     const bool cok = cc < ncols;
-    auto xidx = [&](int i) -> long long { return XT ? (long long)cc * ldx + i : (long long)i * ldx + cc; };
+    // Y(i, cc) with i = 16 b + lq + 4 r: one per-lane base pointer plus a uniform offset
+    // (an immediate when the rows of X are the right-hand sides)
+    TX* const xb = XT ? X + (long long)(cok ? cc : 0) * ldx + lq : X + (long long)lq * ldx + (cok ? cc : 0);
+    const long long xs = XT ? 1 : ldx;
+    auto xat = [&](int b, int r) -> TX& { return xb[(long long)(16 * b + 4 * r) * xs]; };
     auto tload = [&](int i, int k) -> double {
         return (double)(TT ? T[(long long)k * ldt + i] : T[(long long)i * ldt + k]);
     };
@@ -157,68 +161,50 @@ __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], dou
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     };
-    auto lds_wave_sync = []() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-    };
 
     f64x4 acc[NBLK];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[b][r] = cok ? (double)X[xidx(16 * b + lq + 4 * r)] : 0.0;
+        for (int r = 0; r < 4; ++r) acc[b][r] = cok ? (double)xat(b, r) : 0.0;
 
-    double pfa[NBLK], pfb[NBLK];
 #pragma unroll
     for (int q = 0; q < NBLK; ++q) {
         int i, k;
         strip_ik(0, tid + q * 256, i, k);
         Ts[0][i][k] = tload(i, k);
     }
-    if (NBLK > 1) {
-#pragma unroll
-        for (int q = 0; q < NBLK - 1; ++q) {
-            int i, k;
-            strip_ik(1, tid + q * 256, i, k);
-            pfb[q] = tload(i, 16 + k);
-        }
-    }
     lds_barrier();
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
         const int cur = b & 1;
-        // strip b + 2 -> register set b & 1 (strip b + 1, in set (b + 1) & 1, goes to LDS below)
-        if (b + 2 < NBLK) {
+        // strip b + 1 -> registers now, -> LDS at the end of this step
+        double pf[NBLK];
+        if (b + 1 < NBLK) {
 #pragma unroll
-            for (int q = 0; q < NBLK - b - 2; ++q) {
+            for (int q = 0; q < NBLK - b - 1; ++q) {
                 int i, k;
-                strip_ik(b + 2, tid + q * 256, i, k);
-                const double v = tload(i, 16 * (b + 2) + k);
-                if (b & 1) pfb[q] = v;
-                else pfa[q] = v;
+                strip_ik(b + 1, tid + q * 256, i, k);
+                pf[q] = tload(i, 16 * (b + 1) + k);
             }
         }
-        // diagonal block: lane c < 16 of each wave solves right-hand side c0 + c
+        // diagonal block, in place in the accumulator layout: row s of every right-hand
+        // side sits in lane group s % 4, element s / 4; the owner divides by the pivot,
+        // the value is broadcast to the other three lane groups of the same column, and
+        // each lane updates its rows below s (a column sweep: the operations and their
+        // order per element are those of substitution)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Ys[w][lq + 4 * r][lr] = acc[b][r];
-        lds_wave_sync();
-        if (lane < 16) {
-            double y[16];
+        for (int s_ = 0; s_ < 16; ++s_) {
+            double v = acc[b][s_ >> 2];
+            if (!UNIT) v = v / Ts[cur][16 * b + s_][s_];
+            const double ys = __shfl(v, (s_ & 3) * 16 + lr, 64);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) y[i] = Ys[w][i][lane];
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                if (!UNIT) y[s] /= Ts[cur][16 * b + s][s];
-#pragma unroll
-                for (int i = s + 1; i < 16; ++i) y[i] = fma(-Ts[cur][16 * b + i][s], y[s], y[i]);
+            for (int r = 0; r < 4; ++r) {
+                const int i = lq + 4 * r;
+                const double nv = fma(-Ts[cur][16 * b + i][s_], ys, acc[b][r]);
+                acc[b][r] = (i > s_) ? nv : ((i == s_) ? ys : acc[b][r]);
             }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) Ys[w][i][lane] = y[i];
         }
-        lds_wave_sync();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[b][r] = Ys[w][lq + 4 * r][lr];
         // Y_bb -= T(bb, b) Y_b for the tiles below, the next one first
 #pragma unroll
         for (int bb = b + 1; bb < NBLK; ++bb)
@@ -232,7 +218,7 @@ __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], dou
             for (int q = 0; q < NBLK - b - 1; ++q) {
                 int i, k;
                 strip_ik(b + 1, tid + q * 256, i, k);
-                Ts[cur ^ 1][i][k] = ((b + 1) & 1) ? pfb[q] : pfa[q];
+                Ts[cur ^ 1][i][k] = pf[q];
             }
         }
         lds_barrier();
@@ -241,7 +227,7 @@ __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], dou
 #pragma unroll
         for (int b = 0; b < NBLK; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) X[xidx(16 * b + lq + 4 * r)] = (TX)acc[b][r];
+            for (int r = 0; r < 4; ++r) xat(b, r) = (TX)acc[b][r];
     }
 }
 
@@ -250,12 +236,11 @@ __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], dou
 // right-hand sides), workgroups [nwg, 2 nwg) compute L21 = A21 U11^{-1}, i.e.
 // U11^T L21^T = A21^T (the rows of A21 are the right-hand sides).
 template <int NBLK, typename TF, typename TX>
-__global__ void __launch_bounds__(256, 1)
+__global__ void __launch_bounds__(256, 2)
 panel_trsm_kernel(const TF* __restrict__ D, long long ldd, TX* A12, TX* A21, long long ldx, int m, int nwg) {
     __shared__ double Ts[2][NBLK * 16][17];
-    __shared__ double Ys[4][16][17];
-    if ((int)blockIdx.x < nwg) blk_lower_solve<NBLK, false, true, false>(Ts, Ys, D, ldd, A12, ldx, m, blockIdx.x);
-    else blk_lower_solve<NBLK, true, false, true>(Ts, Ys, D, ldd, A21, ldx, m, blockIdx.x - nwg);
+    if ((int)blockIdx.x < nwg) blk_lower_solve<NBLK, false, true, false>(Ts, D, ldd, A12, ldx, m, blockIdx.x);
+    else blk_lower_solve<NBLK, true, false, true>(Ts, D, ldd, A21, ldx, m, blockIdx.x - nwg);
 }
 
 template <int NBLK, typename TF, typename TX>
