@@ -51,6 +51,10 @@ struct GemmF64Args {
     long long split_stride;              //      at D + s * split_stride (beta ignored)
     int a_f32;                           // A operand stored as FP32 (widened on load)
     int group_m;                         // tile-rows per group of the tile order (0 = 8)
+    // optional second product in the same launch (same K, modes, leading dimensions,
+    // alpha, beta; no split-K): M2 x N2 into D2 from A2, B2, Cin2 (M2 = 0: none)
+    int M2, N2;
+    const double* A2; const double* B2; const double* Cin2; double* D2;
 };
 // tile: 0 = 128x128 (2x2 waves), 1 = 256x64 (4x1), 2 = 64x256 (1x4), 3 = 64x64,
 //       4 = 128x64 (2x1), 5 = 64x128 (1x2)

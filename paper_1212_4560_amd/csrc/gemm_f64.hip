@@ -47,9 +47,28 @@ gemm_f64_kernel(GemmF64Args g) {
     const int wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
 
-    const int ntm = (g.M + BMt - 1) / BMt, ntn = (g.N + BNt - 1) / BNt;
+    // which product this block computes (the optional second one follows the first's tiles)
+    int bid = blockIdx.x;
+    int gM = g.M, gN = g.N;
+    const double* gA = g.A;
+    const double* gB = g.B;
+    const double* gCin = g.Cin;
+    double* gD = g.D;
+    {
+        const int t1 = ((g.M + BMt - 1) / BMt) * ((g.N + BNt - 1) / BNt);
+        if (g.M2 > 0 && bid >= t1) {
+            bid -= t1;
+            gM = g.M2;
+            gN = g.N2;
+            gA = g.A2;
+            gB = g.B2;
+            gCin = g.Cin2;
+            gD = g.D2;
+        }
+    }
+    const int ntm = (gM + BMt - 1) / BMt, ntn = (gN + BNt - 1) / BNt;
     const int total = ntm * ntn;
-    const int pid = xcd_remap(blockIdx.x, total);
+    const int pid = xcd_remap(bid, total);
     // tile order: groups of GROUP tile-rows, column-major inside a group.  With a generated
     // (Toeplitz) B the only streamed operand is A, so GROUP = 1 lets all concurrent blocks of
     // an XCD share each chunk of one A row-panel in its L2.
@@ -81,7 +100,7 @@ gemm_f64_kernel(GemmF64Args g) {
             for (int r = 0; r < LPA; ++r) {
                 const int e = tid + r * T;
                 const long long idx = base + e;
-                ra[r] = (e < PA && idx >= 0 && idx < 2 * g.lda - 1) ? g.A[idx] : 0.0;
+                ra[r] = (e < PA && idx >= 0 && idx < 2 * g.lda - 1) ? gA[idx] : 0.0;
             }
         } else {
 #pragma unroll
@@ -90,8 +109,8 @@ gemm_f64_kernel(GemmF64Args g) {
                 int i, k;
                 if constexpr (AMODE == OP_N) { i = e / BK; k = e % BK; }
                 else { k = e / BMt; i = e % BMt; }
-                if constexpr (AF32) ra[r] = load_op<AMODE>((const float*)g.A, g.lda, m0 + i, k0 + k, g.M, kend);
-                else ra[r] = load_op<AMODE>(g.A, g.lda, m0 + i, k0 + k, g.M, kend);
+                if constexpr (AF32) ra[r] = load_op<AMODE>((const float*)gA, g.lda, m0 + i, k0 + k, gM, kend);
+                else ra[r] = load_op<AMODE>(gA, g.lda, m0 + i, k0 + k, gM, kend);
             }
         }
         if constexpr (BMODE == OP_TOEP) {
@@ -101,7 +120,7 @@ gemm_f64_kernel(GemmF64Args g) {
             for (int r = 0; r < LPB; ++r) {
                 const int e = tid + r * T;
                 const long long idx = base + e;
-                rb[r] = (e < PB && idx >= 0 && idx < 2 * g.ldb - 1) ? g.B[idx] : 0.0;
+                rb[r] = (e < PB && idx >= 0 && idx < 2 * g.ldb - 1) ? gB[idx] : 0.0;
             }
         } else {
 #pragma unroll
@@ -112,9 +131,9 @@ gemm_f64_kernel(GemmF64Args g) {
                 else { j = e / BK; k = e % BK; }
                 // B(k, j): OP_N -> B[k*ld + j]; OP_T -> B[j*ld + k]
                 double v = 0.0;
-                if (k0 + k < kend && n0 + j < g.N)
-                    v = (BMODE == OP_N) ? g.B[(long long)(k0 + k) * g.ldb + n0 + j]
-                                        : g.B[(long long)(n0 + j) * g.ldb + k0 + k];
+                if (k0 + k < kend && n0 + j < gN)
+                    v = (BMODE == OP_N) ? gB[(long long)(k0 + k) * g.ldb + n0 + j]
+                                        : gB[(long long)(n0 + j) * g.ldb + k0 + k];
                 rb[r] = v;
             }
         }
@@ -199,7 +218,7 @@ gemm_f64_kernel(GemmF64Args g) {
     // epilogue.  Cin may alias D (in-place Schur update), so the compiler cannot move
     // a load above an earlier store: the loads of each 16-row strip are issued as a
     // batch before its stores.
-    double* D = g.D;
+    double* D = gD;
     const bool split = g.ksplit > 1;
     if (split) D += (long long)blockIdx.y * g.split_stride;
     const bool rd = !split && g.beta != 0.0;
@@ -213,7 +232,7 @@ gemm_f64_kernel(GemmF64Args g) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = m0 + wm * 64 + mi * 16 + lq + 4 * r;
-                    cv[ni][r] = (row < g.M && col < g.N) ? g.Cin[(long long)row * g.ldci + col] : 0.0;
+                    cv[ni][r] = (row < gM && col < gN) ? gCin[(long long)row * g.ldci + col] : 0.0;
                 }
             }
         }
@@ -223,7 +242,7 @@ gemm_f64_kernel(GemmF64Args g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * 64 + mi * 16 + lq + 4 * r;
-                if (row < g.M && col < g.N) {
+                if (row < gM && col < gN) {
                     double v = g.alpha * acc[mi][ni][r];
                     if (rd) v = fma(g.beta, cv[ni][r], v);
                     D[(long long)row * g.ldd + col] = v;
@@ -333,7 +352,9 @@ __global__ void splitk_reduce_kernel(int M, int N, int ks, const double* __restr
 template <int WM, int WN, int AM, int BMd, bool AF32 = false>
 hipError_t launch_t(const GemmF64Args& a, hipStream_t s) {
     const int ntm = (a.M + 64 * WM - 1) / (64 * WM), ntn = (a.N + 64 * WN - 1) / (64 * WN);
-    dim3 grid(ntm * ntn, a.ksplit > 1 ? a.ksplit : 1);
+    int tiles = ntm * ntn;
+    if (a.M2 > 0) tiles += ((a.M2 + 64 * WM - 1) / (64 * WM)) * ((a.N2 + 64 * WN - 1) / (64 * WN));
+    dim3 grid(tiles, a.ksplit > 1 ? a.ksplit : 1);
     hipLaunchKernelGGL((gemm_f64_kernel<WM, WN, AM, BMd, AF32>), grid, dim3(64 * WM * WN), 0, s, a);
     return hipGetLastError();
 }
@@ -353,7 +374,20 @@ hipError_t dispatch_modes(const GemmF64Args& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
-    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    if (a.M2 > 0 && (a.N2 <= 0 || a.ksplit > 1 || a.a_f32)) return hipErrorInvalidValue;
+    if (a.M <= 0 || a.N <= 0) {
+        if (a.M2 <= 0) return hipSuccess;
+        // only the second product is non-empty
+        GemmF64Args b = a;
+        b.M = a.M2;
+        b.N = a.N2;
+        b.A = a.A2;
+        b.B = a.B2;
+        b.Cin = a.Cin2;
+        b.D = a.D2;
+        b.M2 = 0;
+        return launch_gemm_f64(b, tile, s);
+    }
     if (a.a_f32) {
         // FP32 factors times FP64 right-hand sides (the correction solves of the precision form)
         if (tile != 4 || a.bmode != OP_N) return hipErrorInvalidValue;
@@ -361,7 +395,8 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
         if (a.amode == OP_T) return launch_t<2, 1, OP_T, OP_N, true>(a, s);
         return hipErrorInvalidValue;
     }
-    if (tile == 0 && a.amode == OP_N && a.bmode == OP_TOEP && a.ksplit <= 1 && a.alpha == 1.0 && a.beta == 0.0 &&
+    if (tile == 0 && a.M2 <= 0 && a.amode == OP_N && a.bmode == OP_TOEP && a.ksplit <= 1 && a.alpha == 1.0 &&
+        a.beta == 0.0 &&
         a.M % 128 == 0 && a.N % 128 == 0 && a.K % 32 == 0 && a.K == a.ldb) {
         // the multiplier product on full tiles (ldb carries the Toeplitz order, which is K)
         hipLaunchKernelGGL(gemm_ag_toep_kernel, dim3((a.M / 128) * (a.N / 128)), dim3(256), 0, s, a.M, a.N, a.K, a.A,

@@ -712,6 +712,35 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         HIPCK(launch_gemm_f64(g, 0, st));
         return GENP_OK;
     };
+    // two blocks of the same update in one launch (FP64; the precision form launches twice)
+    auto schur_two = [&](int64_t j, int64_t r0, int64_t c0, int64_t M, int64_t N, int64_t r1_, int64_t c1_,
+                         int64_t M1, int64_t N1, hipStream_t st, int kb = 1) -> int {
+        if (lp || M <= 0 || N <= 0 || M1 <= 0 || N1 <= 0) {
+            CK(schur(j, r0, c0, M, N, st, kb));
+            return schur(j, r1_, c1_, M1, N1, st, kb);
+        }
+        double* C = (double*)c->C;
+        const int64_t k = j * nb;
+        GemmF64Args g{};
+        g.ksplit = 1;
+        g.K = (int)(kb * nb);
+        g.lda = g.ldb = g.ldci = g.ldd = ldc;
+        g.amode = g.bmode = OP_N;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        g.M = (int)M;
+        g.N = (int)N;
+        g.A = C + r0 * ldc + k;
+        g.B = C + k * ldc + c0;
+        g.Cin = g.D = C + r0 * ldc + c0;
+        g.M2 = (int)M1;
+        g.N2 = (int)N1;
+        g.A2 = C + r1_ * ldc + k;
+        g.B2 = C + k * ldc + c1_;
+        g.Cin2 = g.D2 = C + r1_ * ldc + c1_;
+        HIPCK(launch_gemm_f64(g, 0, st));
+        return GENP_OK;
+    };
     ev_begin(c, EV_FAC);
     // Steps go in pairs (a, a+1) so that the bulk of the trailing matrix takes both
     // Schur updates as one product with K = 2 nb.  Invariant at the top of the loop:
@@ -741,8 +770,7 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
     };
     CK(panel(0, S));
     if (K > 1) {
-        CK(schur(0, nb, nb, np - nb, nb, S));
-        CK(schur(0, nb, 2 * nb, nb, np - 2 * nb, S));
+        CK(schur_two(0, nb, nb, np - nb, nb, nb, 2 * nb, nb, np - 2 * nb, S));
         CK(panel(1, S));
     }
     for (int64_t a = 0; a + 2 < K; a += 2) {
@@ -752,15 +780,13 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         const int64_t rb = r2 + w, mb = m - w;                   // the bulk: rows/cols rb.. (mb of them)
         const int64_t n1 = (mb / 2 + nb - 1) / nb * nb;          // its first column half
         HIPCK(hipEventRecord(ev(a, 0), S));
-        CK(schur(a, r2, r2, m, w, S, 2));
-        CK(schur(a, r2, r2 + w, w, m - w, S, 2));
+        CK(schur_two(a, r2, r2, m, w, r2, r2 + w, w, m - w, S, 2));
         CK(diag_async(a + 2, 4));
         CK(schur(a, rb, rb, mb, n1, S, 2));
         CK(wait_diag(a + 2));
         CK(solves(a + 2, S));
         if (nb2 == 2) {
-            CK(schur(a + 2, r2 + nb, r2 + nb, m - nb, nb, S));
-            CK(schur(a + 2, r2 + nb, r2 + 2 * nb, nb, m - 2 * nb, S));
+            CK(schur_two(a + 2, r2 + nb, r2 + nb, m - nb, nb, r2 + nb, r2 + 2 * nb, nb, m - 2 * nb, S));
             CK(diag_async(a + 3, 4));
         }
         CK(schur(a, rb, rb + n1, mb, mb - n1, S, 2));
