@@ -31,12 +31,6 @@ def method_flops(n: int, k: int, it: int) -> float:
     return 2.0 * n ** 3 + lu + 4.0 * n * n * k + it * 6.0 * n * n * k
 
 
-def schur_flops(n: int, nb: int) -> float:
-    """Flops of the Schur-update GEMMs: 2 m^2 nb per step, m = trailing size."""
-    n_pad = (n + nb - 1) // nb * nb
-    return sum(2.0 * (n_pad - (b + 1) * nb) ** 2 * nb for b in range(n_pad // nb))
-
-
 def traffic_if_current(n: int):
     """HBM bytes per launch of the A*G kernel from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy kernel), or
@@ -203,7 +197,7 @@ def main() -> int:
         infos.append(inf)
         ag_ms.append(inf["ms_ag"])
         log(f"[bench] step {i}: precond {inf['ms_precond']:.1f} (A*G {inf['ms_ag']:.1f}) factor "
-            f"{inf['ms_factor']:.1f} (schur {inf['ms_schur']:.1f}, panel {inf['ms_panel']:.1f}) solve "
+            f"{inf['ms_factor']:.1f} (update pairs {inf['ms_schur']:.1f}, panels {inf['ms_panel']:.1f}) solve "
             f"{inf['ms_solve']:.1f} refine {inf['ms_refine']:.1f} ms; it={inf['iters']} inner={inf['inner_iters']} "
             f"eta={inf['eta']:.2e}")
     ev1.record(stream)
@@ -240,11 +234,9 @@ def main() -> int:
                    "multiplier": w.mult, "smax": w.smax, "refine_tol": args.tol},
         "eta_lib": eta_lib, "eta_oracle": eta_orc, "refine_steps": its,
         "stage_ms": {"precondition": round(last["ms_precond"], 3), "ag_gemm": round(last["ms_ag"], 3),
-                     "factor": round(last["ms_factor"], 3), "schur_gemms": round(last["ms_schur"], 3),
+                     "factor": round(last["ms_factor"], 3), "update_pairs": round(last["ms_schur"], 3),
                      "panels": round(last["ms_panel"], 3), "solve": round(last["ms_solve"], 3),
                      "refine": round(last["ms_refine"], 3)},
-        "schur_tflops": round(schur_flops(n, args.nb) / (last["ms_schur"] * 1e-3) / 1e12, 2)
-        if last["ms_schur"] > 0 else None,
         "growth": last["growth"], "wall_s": round(wall, 2),
         "roofline": roof,
     }

@@ -305,3 +305,58 @@ def test_gradient_does_not_depend_on_multiplier():
         grads.append(host(A.grad))
     kappa = np.linalg.cond(w.A, np.inf)
     assert np.max(np.abs(grads[0] - grads[1])) <= 10 * kappa * 1e-15 * np.max(np.abs(grads[0]))
+
+
+# -------------------------------------------------- schedule and solve variants ----
+
+def _factor_with_env(monkeypatch, var, value, A, G, n, nb, prec="f64"):
+    monkeypatch.setenv(var, value)
+    s = genp.Solver(n, prec, nb)       # the library reads the switch when the context is created
+    s.precondition(dev(A), G=dev(G))
+    assert s.factor() == 0
+    return s, host(s.work())
+
+
+@pytest.mark.parametrize("n,nb,prec", [(1280, 256, "f64"), (1100, 128, "f64"), (900, 64, "f32")])
+def test_lookahead_does_not_change_the_factors(monkeypatch, n, nb, prec):
+    """Look-ahead only moves the diagonal-block factorizations to a second stream: the
+    products, their grouping and their order are the same, so the factors are bit-identical."""
+    g = np.random.default_rng(n)
+    A, G = g.standard_normal((n, n)), g.standard_normal((n, n))
+    _, on = _factor_with_env(monkeypatch, "GENP_LOOKAHEAD", "1", A, G, n, nb, prec)
+    _, off = _factor_with_env(monkeypatch, "GENP_LOOKAHEAD", "0", A, G, n, nb, prec)
+    assert np.array_equal(on, off)
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4])
+def test_chained_triangular_solves_match_per_block_solves(monkeypatch, nrhs):
+    """The single-launch solves (forward/backward for the solution, transposed for the
+    adjoint) against the one-launch-per-block solves, for 1..4 right-hand sides.  Both are
+    substitution with the sums accumulated in a different order, so both must be backward
+    stable: eta_inf of X for A X = B and of dB for A^T dB = W small (no refinement here) and
+    within 10x of each other; the solutions themselves differ by the factors' conditioning
+    times u (GENP factors of A G can be much worse conditioned than A).  No error word may
+    be left behind."""
+    n, nb = 1000, 128
+    g = np.random.default_rng(40 + nrhs)
+    A = g.standard_normal((n, n)) + 3 * np.sqrt(n) * np.eye(n)
+    G = g.standard_normal((n, n))
+    B = g.standard_normal((n, nrhs))
+    W = g.standard_normal((n, nrhs))
+    res = {}
+    for mode in ("chain", "step"):
+        s, _ = _factor_with_env(monkeypatch, "GENP_TRSV", mode, A, G, n, nb)
+        X = s.solve(dev(B))
+        dB, _ = s.solve_backward(dev(W), X, want_dA=False, refine_iters=0)
+        s.info()                        # raises if a chained solve reported an error
+        res[mode] = (host(X), host(dB))
+    eta = {m: (og.backward_error_inf(A, res[m][0], B).max(), og.backward_error_inf(A.T, res[m][1], W).max())
+           for m in res}
+    _say(f"  nrhs={nrhs}: eta chain {eta['chain']} step {eta['step']}")
+    for k in range(2):
+        a, b = eta["chain"][k], eta["step"][k]
+        # unrefined GENP solves: growth puts eta near 1e-10 here (refinement takes it to u)
+        assert a <= 1e-8 and b <= 1e-8
+        assert a <= 10 * b + 1e-16 and b <= 10 * a + 1e-16
+        x, y = res["chain"][k], res["step"][k]
+        assert np.max(np.abs(x - y)) <= 1e-6 * np.max(np.abs(y))
