@@ -57,7 +57,9 @@ enum {
 enum {
     GENP_G_DENSE = 0,     /* G: n x n dense, row-major, leading dimension ldg        */
     GENP_G_TOEPLITZ = 1,  /* G: 2n-1 parameters p, G[i][j] = p[i - j + n - 1]        */
-    GENP_G_NONE = 2       /* no multiplier: C = A (plain GENP, for tests)            */
+    GENP_G_NONE = 2,      /* no multiplier: C = A (plain GENP, for tests)            */
+    GENP_G_CIRCULANT = 3  /* G: n parameters c, G[i][j] = c[(i - j) mod n]; applied by
+                             FFT; n a power of two, 4 <= n <= 16384                    */
 };
 
 /* Refinement solvers for genp_refine. */
@@ -123,8 +125,11 @@ int genp_destroy(genp_ctx* ctx);
  * C = A G (section 1.1; right multiplier per Corollary 4.1(ii)), in the
  * context's working precision.  A: n x n FP64 (lda >= n).  mult selects G:
  * dense (G n x n FP64, ldg >= n), Toeplitz (G = the 2n-1 FP64 parameters,
- * ldg ignored, copied), or none (G ignored).  Also computes ||A||_inf.
- * Resets the context to the "preconditioned" state.
+ * ldg ignored, copied), circulant (G = the n FP64 parameters c, ldg ignored;
+ * the multiplier's spectrum is kept, and every product with G or G^T runs as
+ * FFTs of length n, Theorem 2.1 -- n must be a power of two with
+ * 4 <= n <= 16384, else GENP_ENOTSUP), or none (G ignored).  Also computes
+ * ||A||_inf.  Resets the context to the "preconditioned" state.
  */
 int genp_precondition(genp_ctx* ctx, const double* A, int64_t lda, int mult,
                       const double* G, int64_t ldg);

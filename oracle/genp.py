@@ -49,11 +49,26 @@ def toeplitz_from_params(p: np.ndarray, n: int) -> np.ndarray:
     return p[i - j + n - 1]
 
 
+def circulant_from_params(c: np.ndarray, n: int) -> np.ndarray:
+    """Dense n x n circulant matrix with first column c: G[i, j] = c[(i - j) mod n]
+    (the circulant class of Definition 3.2; section 2.3).  Every circulant is
+    diagonalized by the DFT (Theorem 2.1), which is what makes it cheap to apply."""
+    c = np.asarray(c, dtype=np.float64)
+    if c.shape != (n,):
+        raise ValueError("need n parameters")
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    return c[(i - j) % n]
+
+
 def dense_multiplier(G: Optional[np.ndarray], p: Optional[np.ndarray], n: int) -> np.ndarray:
+    """The multiplier as a dense matrix: G itself, or built from its parameters
+    (2n - 1 Toeplitz parameters, or n circulant parameters)."""
     if G is not None:
         return np.asarray(G, dtype=np.float64)
     if p is not None:
-        return toeplitz_from_params(p, n)
+        p = np.asarray(p)
+        return circulant_from_params(p, n) if p.shape[0] == n and n > 1 else toeplitz_from_params(p, n)
     raise ValueError("need G or p")
 
 

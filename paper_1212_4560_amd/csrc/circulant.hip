@@ -1,0 +1,185 @@
+// Circulant multipliers applied by FFT (the DFT diagonalizes every circulant matrix,
+// Theorem 2.1; circulant multipliers, Definition 3.2).
+//
+// G[i][j] = c[(i - j) mod n], n = 2N a power of two, 4 <= n <= 16384.
+//   row correlation   (x^T G)[j] = sum_k x[k] c[(k - j) mod n]  <->  X conj(C)   (A G, G^T y)
+//   column convolution  (G y)[i] = sum_j c[(i - j) mod n] y[j]  <->  Y C         (G y)
+// with X, Y, C the DFTs of length n.
+//
+// One workgroup per vector.  The real vector of length n = 2N is packed as N complex
+// numbers z[k] = x[2k] + i x[2k+1] and transformed in place in LDS (radix 2, length N:
+// decimation in time from bit-reversed order, so the spectrum comes out in natural
+// order).  The spectrum of the real vector follows from Z[f] and Z[N-f]:
+//   E[f] = (Z[f] + conj Z[N-f]) / 2,  O[f] = (Z[f] - conj Z[N-f]) / (2i),
+//   X[f] = E[f] + W^f O[f]  (W = e^{-2 pi i / n}),  f = 0..N.
+// After the product R = X S (S = C or conj C), the inverse runs the same relations
+// backwards:
+//   E'[f] = (R[f] + conj R[N-f]) / 2,  O'[f] = (R[f] - conj R[N-f]) W^{-f} / 2,
+//   Z'[f] = E'[f] + i O'[f],
+// an inverse FFT of length N (decimation in frequency: natural order in, bit-reversed
+// order out), and the unpacking r[2k] = Re z'[k] / N, r[2k+1] = Im z'[k] / N.
+// Each pair (f, N - f) is handled by one thread, so the unpack, product and repack need
+// no barrier between them.
+#include "common.h"
+
+namespace {
+
+constexpr int CIRC_MAXN2 = 8192;   // largest N = n / 2: N complex doubles = 128 KB of LDS
+constexpr int CIRC_THREADS = 512;
+
+struct cplx {
+    double re, im;
+};
+__device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cplx cconj(cplx a) { return {a.re, -a.im}; }
+__device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
+
+// MODE 0: y = alpha * (x correlated / convolved with c) + beta * yin.
+// MODE 1: the spectrum X[0..N] of x itself (the multiplier's spectrum, once per multiplier).
+template <int MODE, bool CONJ, typename TO>
+__global__ void __launch_bounds__(CIRC_THREADS)
+circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long long bx,
+            const double2* __restrict__ spec, const double2* __restrict__ tw, const double2* __restrict__ wp,
+            double alpha, double beta, const double* yin, long long syi, long long byi, TO* y, long long sy,
+            long long by, double2* __restrict__ spec_out) {
+    __shared__ cplx L[CIRC_MAXN2];
+    const int N = n >> 1;
+    const int tid = threadIdx.x;
+    const long long b = blockIdx.x;
+    const double* xv = x + b * bx;
+    // packed, bit-reversed load
+    for (int k = tid; k < N; k += CIRC_THREADS) {
+        const int r = (int)(__brev((unsigned)k) >> (32 - logN));
+        L[r] = {xv[(2LL * k) * sx], xv[(2LL * k + 1) * sx]};
+    }
+    __syncthreads();
+    // forward FFT of length N, decimation in time
+    for (int len = 2; len <= N; len <<= 1) {
+        const int half = len >> 1, step = N / len;
+        for (int j = tid; j < (N >> 1); j += CIRC_THREADS) {
+            const int pos = j & (half - 1);
+            const int i0 = (j - pos) * 2 + pos, i1 = i0 + half;
+            const double2 w2 = tw[pos * step];
+            const cplx t = cmul({w2.x, w2.y}, L[i1]);
+            const cplx a = L[i0];
+            L[i0] = cadd(a, t);
+            L[i1] = csub(a, t);
+        }
+        __syncthreads();
+    }
+    // spectrum of the real vector, product with the multiplier's spectrum, repack
+    for (int f = tid; f <= (N >> 1); f += CIRC_THREADS) {
+        if (f == 0) {
+            const cplx z0 = L[0];
+            const double x0 = z0.re + z0.im, xN = z0.re - z0.im;   // X[0], X[N] (real)
+            if (MODE == 1) {
+                spec_out[0] = make_double2(x0, 0.0);
+                spec_out[N] = make_double2(xN, 0.0);
+                continue;
+            }
+            const cplx r0 = cmul({x0, 0.0}, CONJ ? cconj({spec[0].x, spec[0].y}) : cplx{spec[0].x, spec[0].y});
+            const cplx rN = cmul({xN, 0.0}, CONJ ? cconj({spec[N].x, spec[N].y}) : cplx{spec[N].x, spec[N].y});
+            // E'[0] = (R[0] + conj R[N]) / 2, O'[0] = (R[0] - conj R[N]) / 2
+            const cplx e = cscale(cadd(r0, cconj(rN)), 0.5), o = cscale(csub(r0, cconj(rN)), 0.5);
+            L[0] = {e.re - o.im, e.im + o.re};
+            continue;
+        }
+        const int g = N - f;
+        const cplx zf = L[f], zg = L[g];
+        const double2 wf2 = wp[f], wg2 = wp[g];
+        const cplx wf = {wf2.x, wf2.y}, wg = {wg2.x, wg2.y};
+        // E = (Z[f] + conj Z[N-f]) / 2; O = (Z[f] - conj Z[N-f]) / (2i) = -i (Z[f] - conj Z[N-f]) / 2
+        const cplx ef = cscale(cadd(zf, cconj(zg)), 0.5), df = cscale(csub(zf, cconj(zg)), 0.5);
+        const cplx of = {df.im, -df.re};
+        const cplx eg = cscale(cadd(zg, cconj(zf)), 0.5), dg = cscale(csub(zg, cconj(zf)), 0.5);
+        const cplx og = {dg.im, -dg.re};
+        const cplx xf = cadd(ef, cmul(wf, of)), xg = cadd(eg, cmul(wg, og));
+        if (MODE == 1) {
+            spec_out[f] = make_double2(xf.re, xf.im);
+            spec_out[g] = make_double2(xg.re, xg.im);
+            continue;
+        }
+        const cplx sf = {spec[f].x, spec[f].y}, sg = {spec[g].x, spec[g].y};
+        const cplx rf = cmul(xf, CONJ ? cconj(sf) : sf), rg = cmul(xg, CONJ ? cconj(sg) : sg);
+        // E' = (R[f] + conj R[N-f]) / 2, O' = (R[f] - conj R[N-f]) W^{-f} / 2, Z' = E' + i O'
+        const cplx ef2 = cscale(cadd(rf, cconj(rg)), 0.5);
+        const cplx of2 = cmul(cscale(csub(rf, cconj(rg)), 0.5), cconj(wf));
+        const cplx eg2 = cscale(cadd(rg, cconj(rf)), 0.5);
+        const cplx og2 = cmul(cscale(csub(rg, cconj(rf)), 0.5), cconj(wg));
+        L[f] = {ef2.re - of2.im, ef2.im + of2.re};
+        if (g != f) L[g] = {eg2.re - og2.im, eg2.im + og2.re};
+    }
+    if (MODE == 1) return;
+    __syncthreads();
+    // inverse FFT of length N, decimation in frequency (bit-reversed output)
+    for (int len = N; len >= 2; len >>= 1) {
+        const int half = len >> 1, step = N / len;
+        for (int j = tid; j < (N >> 1); j += CIRC_THREADS) {
+            const int pos = j & (half - 1);
+            const int i0 = (j - pos) * 2 + pos, i1 = i0 + half;
+            const double2 w2 = tw[pos * step];
+            const cplx a = L[i0], c = L[i1];
+            L[i0] = cadd(a, c);
+            L[i1] = cmul(csub(a, c), {w2.x, -w2.y});
+        }
+        __syncthreads();
+    }
+    const double s = alpha / (double)N;
+    TO* yv = y + b * by;
+    const double* yiv = (beta != 0.0) ? yin + b * byi : nullptr;
+    for (int k = tid; k < N; k += CIRC_THREADS) {
+        const int r = (int)(__brev((unsigned)k) >> (32 - logN));
+        const cplx z = L[r];
+        double v0 = s * z.re, v1 = s * z.im;
+        if (yiv) {
+            v0 = fma(beta, yiv[(2LL * k) * syi], v0);
+            v1 = fma(beta, yiv[(2LL * k + 1) * syi], v1);
+        }
+        yv[(2LL * k) * sy] = (TO)v0;
+        yv[(2LL * k + 1) * sy] = (TO)v1;
+    }
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+bool circ_size_ok(long long n) {
+    return n >= 4 && n <= 2LL * CIRC_MAXN2 && (n & (n - 1)) == 0;
+}
+
+hipError_t launch_circ_spectrum(int n, const double* c, const double2* tw, const double2* wp, double2* spec,
+                                hipStream_t s) {
+    if (!circ_size_ok(n)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((circ_kernel<1, false, double>), dim3(1), dim3(CIRC_THREADS), 0, s, n, ilog2(n / 2), c, 1LL,
+                       0LL, (const double2*)nullptr, tw, wp, 1.0, 0.0, (const double*)nullptr, 0LL, 0LL,
+                       (double*)nullptr, 0LL, 0LL, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_circ_apply(int n, int nvec, int conj, const double* x, long long sx, long long bx, const double2* spec,
+                             const double2* tw, const double2* wp, double alpha, double beta, const double* yin,
+                             long long syi, long long byi, void* y, int y_f32, long long sy, long long by,
+                             hipStream_t s) {
+    if (!circ_size_ok(n)) return hipErrorInvalidValue;
+    if (nvec <= 0) return hipSuccess;
+    const int lg = ilog2(n / 2);
+#define GENP_CIRC_GO(CJ, TO)                                                                                   \
+    hipLaunchKernelGGL((circ_kernel<0, CJ, TO>), dim3(nvec), dim3(CIRC_THREADS), 0, s, n, lg, x, sx, bx, spec, \
+                       tw, wp, alpha, beta, yin, syi, byi, (TO*)y, sy, by, (double2*)nullptr)
+    if (conj) {
+        if (y_f32) GENP_CIRC_GO(true, float);
+        else GENP_CIRC_GO(true, double);
+    } else {
+        if (y_f32) GENP_CIRC_GO(false, float);
+        else GENP_CIRC_GO(false, double);
+    }
+#undef GENP_CIRC_GO
+    return hipGetLastError();
+}

@@ -51,6 +51,10 @@ struct genp_ctx {
     int64_t ldg = 0;
     double* p = nullptr;       // Toeplitz parameters (owned copy)
     double* p_rev = nullptr;   // reversed: the parameters of G^T
+    // circulant multiplier: its spectrum and the FFT twiddles (n / 2 + 1, n / 4, n / 2 + 1)
+    double2* circ_spec = nullptr;
+    double2* circ_tw = nullptr;
+    double2* circ_wp = nullptr;
     // right-hand-side scratch, capacity kcap columns
     int64_t kcap = 0;
     double* Z = nullptr;       // n_pad x kcap
@@ -273,6 +277,12 @@ int apply_g(genp_ctx* c, int trans, int k, double alpha, const double* Zin, int6
     if (c->mult == GENP_G_TOEPLITZ)
         return skinny(c, n, n, k, alpha, trans ? c->p_rev : c->p, n, OP_TOEP, 0, Zin, ldz, beta, Yin, ldyi,
                       Y, ldy);
+    if (c->mult == GENP_G_CIRCULANT) {
+        // the k columns as k vectors: element t of column b at Z[t * ldz + b]
+        HIPCK(launch_circ_apply(n, k, trans, Zin, ldz, 1, c->circ_spec, c->circ_tw, c->circ_wp, alpha, beta, Yin,
+                                ldyi, 1, Y, 0, ldy, 1, c->stream));
+        return GENP_OK;
+    }
     return skinny(c, n, n, k, alpha, c->G, c->ldg, trans ? OP_T : OP_N, 0, Zin, ldz, beta, Yin, ldyi, Y,
                   ldy);
 }
@@ -518,6 +528,9 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->tsync);
     hipFree(c->p);
     hipFree(c->p_rev);
+    hipFree(c->circ_spec);
+    hipFree(c->circ_tw);
+    hipFree(c->circ_wp);
     hipFree(c->Z);
     hipFree(c->R);
     hipFree(c->Dx);
@@ -543,7 +556,9 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
     CK(check_ctx(c));
     const int64_t n = c->n;
     if (!A || lda < n) return GENP_EINVAL;
-    if (mult != GENP_G_DENSE && mult != GENP_G_TOEPLITZ && mult != GENP_G_NONE) return GENP_EINVAL;
+    if (mult != GENP_G_DENSE && mult != GENP_G_TOEPLITZ && mult != GENP_G_NONE && mult != GENP_G_CIRCULANT)
+        return GENP_EINVAL;
+    if (mult == GENP_G_CIRCULANT && !circ_size_ok(n)) return GENP_ENOTSUP;
     if (mult != GENP_G_NONE && !G) return GENP_EINVAL;
     if (mult == GENP_G_DENSE && ldg < n) return GENP_EINVAL;
     c->state = ST_CREATED;
@@ -563,8 +578,33 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
         // G^T(i, k) = G(k, i) = p[k - i + n - 1] = p_rev[i - k + n - 1] with p_rev[t] = p[2n - 2 - t]
         HIPCK(launch_copy2d(G, 1, c->p_rev + (2 * n - 2), -1, (int)(2 * n - 1), 1, c->stream));
     }
+    if (mult == GENP_G_CIRCULANT) {
+        const int64_t N = n / 2;
+        if (!c->circ_spec) {
+            // twiddles of the length-N complex FFT and of the real-spectrum packing, in FP64 on the host
+            std::vector<double2> tw(N / 2), wp(N + 1);
+            const double pi = 3.14159265358979323846264338327950288;
+            for (int64_t k = 0; k < N / 2; ++k)
+                tw[k] = make_double2(cos(2.0 * pi * (double)k / (double)N), -sin(2.0 * pi * (double)k / (double)N));
+            for (int64_t f = 0; f <= N; ++f)
+                wp[f] = make_double2(cos(2.0 * pi * (double)f / (double)n), -sin(2.0 * pi * (double)f / (double)n));
+            if (hipMalloc(&c->circ_spec, (N + 1) * sizeof(double2)) != hipSuccess ||
+                hipMalloc(&c->circ_tw, std::max<int64_t>(1, N / 2) * sizeof(double2)) != hipSuccess ||
+                hipMalloc(&c->circ_wp, (N + 1) * sizeof(double2)) != hipSuccess)
+                return GENP_ENOMEM;
+            HIPCK(hipMemcpy(c->circ_tw, tw.data(), (N / 2) * sizeof(double2), hipMemcpyHostToDevice));
+            HIPCK(hipMemcpy(c->circ_wp, wp.data(), (N + 1) * sizeof(double2), hipMemcpyHostToDevice));
+        }
+        HIPCK(launch_circ_spectrum((int)n, G, c->circ_tw, c->circ_wp, c->circ_spec, c->stream));
+    }
     HIPCK(hipMemsetAsync(c->red, 0, sizeof(unsigned long long) * R_COLS, c->stream));
-    if (mult == GENP_G_NONE) {
+    if (mult == GENP_G_CIRCULANT) {
+        // C = A G: each row of A correlated with c, by FFT
+        HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
+        HIPCK(launch_circ_apply((int)n, (int)n, 1, A, 1, lda, c->circ_spec, c->circ_tw, c->circ_wp, 1.0, 0.0,
+                                nullptr, 0, 0, c->C, c->prec != GENP_F64, 1, c->ldc, c->stream));
+        HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
+    } else if (mult == GENP_G_NONE) {
         if (c->prec == GENP_F64) HIPCK(launch_copy2d(A, lda, (double*)c->C, c->ldc, (int)n, (int)n, c->stream));
         else HIPCK(launch_convert_f64_f32(A, lda, (float*)c->C, c->ldc, (int)n, (int)n, c->stream));
     } else if (c->prec == GENP_F64) {

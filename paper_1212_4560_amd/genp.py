@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgenp.so")
 
 F64, F32, BF16 = 0, 1, 2
-G_DENSE, G_TOEPLITZ, G_NONE = 0, 1, 2
+G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT = 0, 1, 2, 3
 SOLVER_LUIR, SOLVER_GMRES = 0, 1
 OK, BREAKDOWN, ENOCONV = 0, 1, 2
 EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP = -1, -2, -3, -4, -5
@@ -154,8 +154,9 @@ class Solver:
         except Exception:
             pass
 
-    def precondition(self, A, G=None, p=None):
-        """C = A G (dense G, or Toeplitz with parameters p, or no multiplier)."""
+    def precondition(self, A, G=None, p=None, c=None):
+        """C = A G (dense G, Toeplitz with parameters p, circulant with first column c,
+        or no multiplier)."""
         n = self.n
         a, lda = _mat(A, "A", n, n)
         if G is not None:
@@ -165,10 +166,14 @@ class Solver:
             g, ldg = _mat(p, "p", 2 * n - 1)
             mult = G_TOEPLITZ
             ldg = n
+        elif c is not None:
+            g, ldg = _mat(c, "c", n)
+            mult = G_CIRCULANT
+            ldg = n
         else:
             g, ldg, mult = 0, n, G_NONE
         _check(load().genp_precondition(self._h, a, lda, mult, g, ldg), "genp_precondition")
-        self._keep = (A, G, p)
+        self._keep = (A, G, p, c)
         return self
 
     def factor(self, pivot_tol: float = 0.0) -> int:
@@ -229,13 +234,14 @@ class Solver:
 
 
 def solve(A, B, G=None, p=None, prec: str = "f64", nb: int = 256, refine: int = 2,
-          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir"):
+          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir", c=None):
     """The whole path: C = A G, GENP, substitutions, X = G Y, refinement.
+    The multiplier: dense G, Toeplitz parameters p, or circulant first column c.
 
     Returns (X, info dict, solver object).  Raises GenpError on breakdown.
     """
     s = Solver(A.shape[0], prec, nb)
-    s.precondition(A, G=G, p=p)
+    s.precondition(A, G=G, p=p, c=c)
     bk = s.factor(pivot_tol)
     if bk:
         raise GenpError(BREAKDOWN, f"genp_factor (column {bk})")

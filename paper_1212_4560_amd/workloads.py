@@ -41,14 +41,15 @@ import numpy as np
 
 MULT_DENSE = "dense"
 MULT_TOEPLITZ = "toeplitz"
+MULT_CIRCULANT = "circulant"
 
 
 @dataclasses.dataclass
 class Workload:
     """One seeded instance.  Arrays are float64, C-contiguous (row-major).
 
-    ``G`` is the dense n x n multiplier (None for Toeplitz), ``p`` the 2n-1
-    Toeplitz parameters (None for dense).  ``W`` is only set for the
+    ``G`` is the dense n x n multiplier (None for Toeplitz and circulant), ``p`` the
+    2n-1 Toeplitz parameters or the n circulant parameters (None for dense).  ``W`` is only set for the
     differentiation workload.  On the ``cuda`` device the arrays are torch
     tensors instead of numpy arrays.
     """
@@ -89,6 +90,8 @@ def _multiplier_draw(g: np.random.Generator, n: int, mult: str):
         return g.standard_normal((n, n)), None
     if mult == MULT_TOEPLITZ:
         return None, g.standard_normal(2 * n - 1)
+    if mult == MULT_CIRCULANT:
+        return None, g.standard_normal(n)
     raise ValueError(f"unknown multiplier kind {mult!r}")
 
 
@@ -186,6 +189,9 @@ NAMED = {
                                      mult=MULT_DENSE, nrhs=64, seed=2),
     "c5_n8192_scaled_lowrank": dict(kind="scaled_gaussian_lowrank_lead", n=8192, seed=5,
                                     nrhs=64),
+    # the benchmark's A with a Gaussian circulant multiplier (n parameters), applied by FFT
+    "c3c_n16384_haar1e6_circulant": dict(kind="haar_logspaced", n=16384, smax=1e6,
+                                         mult=MULT_CIRCULANT, nrhs=1, seed=3),
 }
 
 

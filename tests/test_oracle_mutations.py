@@ -148,8 +148,17 @@ def check_gmres():
     return bool(res.eta_hist[-1] <= 1e-14)
 
 
+def check_circulant():
+    from scipy.linalg import circulant
+    n = 10
+    c = np.random.default_rng(3).standard_normal(n)
+    G = og.circulant_from_params(c, n)
+    v = np.exp(2j * np.pi * np.arange(n) * 2 / n)
+    return bool(np.array_equal(G, circulant(c)) and np.allclose(G @ v, np.fft.fft(c)[2] * v, atol=1e-12))
+
+
 CHECKS = [check_golden, check_exact, check_gepp_and_eta, check_toeplitz_scipy, check_blocked, check_adjoint_fd,
-          check_eta2, check_gmres]
+          check_eta2, check_gmres, check_circulant]
 
 
 def run_checks():
@@ -288,6 +297,8 @@ SOURCE_MUTANTS = {
         "H[i + 1, j] = sn[i] * H[i, j] + cs[i] * H[i + 1, j]"),
     "eta_2: Frobenius norm of A": (
         "backward_error_2", "a = np.linalg.norm(A, 2)", "a = np.linalg.norm(A)"),
+    "circulant: transposed index": (
+        "circulant_from_params", "return c[(i - j) % n]", "return c[(j - i) % n]"),
     "gmres_ir: residual with the wrong sign": (
         "gmres_ir", "r = B2[:, c] - A @ X2[:, c]", "r = A @ X2[:, c] - B2[:, c]"),
 }

@@ -448,3 +448,40 @@ def test_gmres_ir_repairs_perturbed_factors():
     assert res.eta_hist[-1] <= 1e-14
     assert res.steps <= 3
     assert np.allclose(res.X, np.linalg.solve(A, B), rtol=0, atol=1e-10 * np.max(np.abs(res.X)))
+
+
+# ---------------------------------------------------------------------------
+# circulant multipliers (Definition 3.2; Theorem 2.1)
+# ---------------------------------------------------------------------------
+
+def test_circulant_against_scipy_and_its_dft_eigenvectors():
+    """Index convention G[i, j] = c[(i - j) mod n] against scipy.linalg.circulant (first
+    column c), and the DFT diagonalization of Theorem 2.1: the Fourier vectors
+    v_k[j] = exp(2 pi i j k / n) are eigenvectors with eigenvalue (DFT c)[k] -- a
+    transposed index (c[(j - i) mod n]) would give the conjugate eigenvalues instead."""
+    from scipy.linalg import circulant
+    n = 12
+    c = np.random.default_rng(8).standard_normal(n)
+    G = og.circulant_from_params(c, n)
+    assert np.array_equal(G, circulant(c))
+    lam = np.fft.fft(c)
+    for k in (1, 3, 5):
+        v = np.exp(2j * np.pi * np.arange(n) * k / n)
+        assert np.allclose(G @ v, lam[k] * v, rtol=0, atol=1e-12)
+        assert not np.allclose(G.T @ v, lam[k] * v, rtol=0, atol=1e-6)
+
+
+def test_circulant_multiplier_repairs_genp():
+    """GENP fails on the rank-deficient leading block and succeeds on A G with a
+    Gaussian circulant G (the circulant class of Definition 3.2, used in Table 7.1);
+    the refined solution reaches eta <= 1e-14."""
+    w = wl.make("c1_n256_rankdef")
+    A, B = w.A, w.B
+    n = A.shape[0]
+    _, info_a = og.genp_unblocked(A, pivot_tol=n * og.U64)
+    assert info_a.breakdown_col == 5
+    c = np.random.default_rng(21).standard_normal(n)
+    G = og.circulant_from_params(c, n)
+    res, LU, info = og.genp_solve(A, B, G, refine_steps=2, tol=1e-14, pivot_tol=n * og.U64)
+    assert info.breakdown_col == 0
+    assert res.eta_hist[-1] <= 1e-14
