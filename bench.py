@@ -10,6 +10,10 @@ on the GPU before the timed region.
 
 Prints ONE JSON line.  GFLOP/s counts the method's algorithmic flops
 2n^3 + (2/3 n^3 - n^2/2 - n/6) + 4 n^2 k + it * 6 n^2 k.
+Beside the headline it reports, as context, the precision form (FP32 / BF16
+factors with FP64 GMRES refinement) and the same recipe with a Gaussian
+circulant multiplier applied by FFT (time to solution, not GFLOP/s: the FFT
+path does O(n^2 log n) work for the product instead of 2n^3).
 """
 from __future__ import annotations
 
@@ -85,6 +89,111 @@ def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
     return res
 
 
+def circulant_comparison(args, n: int, f64_ms: float) -> dict:
+    """The same recipe with a Gaussian circulant multiplier (Definition 3.2) applied by FFT
+    instead of the Toeplitz product: one warm-up, then `steps` timed whole-path steps."""
+    import numpy as np
+    import torch
+    from paper_1212_4560_amd import genp, workloads as wl
+    name = "c3c_n16384_haar1e6_circulant"
+    w = wl.make(name, n=n, device="cuda")
+    k = w.nrhs
+    stream = torch.cuda.current_stream()
+    s = genp.Solver(n, "f64", args.nb, stream=stream)
+    X = torch.empty((n, k), dtype=torch.float64, device="cuda")
+
+    def step():
+        s.precondition(w.A, c=w.p)
+        if s.factor(0.0):
+            raise RuntimeError("circulant multiplier: breakdown")
+        s.solve(w.B, X)
+        st, eta = s.refine(w.B, X, args.max_refine, args.tol, args.solver)
+        return s.info()
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    e0.record(stream)
+    for _ in range(args.steps):
+        infos.append(step())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    last = infos[-1]
+    eta_orc = None
+    if not args.no_host_check:
+        from oracle import genp as og
+        eta_orc = float(np.max(og.backward_error_inf(w.A.cpu().numpy(), X.cpu().numpy(), w.B.cpu().numpy())))
+    res = {"workload": name, "n": n, "nrhs": k, "ms_per_step": round(ms, 3),
+           "stage_ms": {"precondition_fft": round(last["ms_precond"], 3), "factor": round(last["ms_factor"], 3),
+                        "solve": round(last["ms_solve"], 3), "refine": round(last["ms_refine"], 3)},
+           "refine_steps": [i["iters"] for i in infos], "eta_lib": max(i["eta"] for i in infos),
+           "eta_oracle": eta_orc, "growth": last["growth"],
+           "speedup_vs_toeplitz_gemm_path": round(f64_ms / ms, 3)}
+    log(f"[bench] circulant: {ms:.1f} ms per step (FFT product {last['ms_precond']:.2f} ms, factor "
+        f"{last['ms_factor']:.1f} ms), eta {res['eta_lib']:.2e}")
+    del s, X, w
+    torch.cuda.empty_cache()
+    return res
+
+
+def table_7_1(trials: int, sizes=(64, 256, 1024)) -> dict:
+    """Table 7.1's experiment through the library: relative residuals ||A y - b||_2 / ||b||_2
+    of GENP with a +-1 circulant multiplier, before and after one refinement step, on
+    well conditioned systems whose n/2 x n/2 leading block is ill conditioned (the paper's
+    generator is not given; here the CS-decomposition recipe of
+    workloads.cs_illcond_lead).  Signs are drawn again when the library reports the
+    multiplier singular.  Plain GENP on A is reported beside them."""
+    import numpy as np
+    import torch
+    from paper_1212_4560_amd import genp, workloads as wl
+
+    def rel(A, x, b):
+        return float(np.linalg.norm(A @ x - b) / np.linalg.norm(b))
+
+    def stats(v):
+        v = np.asarray(v)
+        return {"min": float(v.min()), "max": float(v.max()), "mean": float(v.mean()), "std": float(v.std())}
+
+    out = {}
+    for n in sizes:
+        plain, r0, r1, redraws = [], [], [], 0
+        s = genp.Solver(n, "f64", 64)
+        for seed in range(trials):
+            w = wl.cs_illcond_lead(n, seed)
+            A = torch.from_numpy(w.A).cuda()
+            b = torch.from_numpy(w.B).cuda()
+            s.precondition(A)
+            if s.factor() == 0:
+                plain.append(rel(w.A, s.solve(b).cpu().numpy(), w.B))
+            else:
+                plain.append(float("inf"))
+            c, attempt = w.p, 0
+            while True:
+                try:
+                    s.precondition(A, c=torch.from_numpy(c).cuda())
+                    break
+                except genp.GenpError as e:
+                    if e.status != genp.ESINGULAR:
+                        raise
+                    attempt += 1
+                    c = wl.pm1_redraw(n, seed, attempt)
+            redraws += attempt
+            if s.factor():
+                raise RuntimeError(f"breakdown with the +-1 circulant, n={n} seed={seed}")
+            X = s.solve(b)
+            r0.append(rel(w.A, X.cpu().numpy(), w.B))
+            s.refine(b, X, 1, 0.0)
+            r1.append(rel(w.A, X.cpu().numpy(), w.B))
+        out[str(n)] = {"plain_genp": stats(plain), "iter0": stats(r0), "iter1": stats(r1),
+                       "singular_draws_redrawn": redraws, "trials": trials}
+        log(f"[table 7.1] n={n}: iter0 max {max(r0):.2e} mean {np.mean(r0):.2e}; iter1 max {max(r1):.2e}; "
+            f"plain GENP min {min(plain):.2e}; singular draws {redraws}")
+        del s
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -134,6 +243,11 @@ def main() -> int:
                          "(no QR; the kernels' memory traffic does not depend on the values)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain copy kernel of the n x n working matrix (PMC calibration)")
+    ap.add_argument("--no-circulant", action="store_true",
+                    help="skip the circulant-multiplier (FFT) comparison")
+    ap.add_argument("--table-7-1", type=int, default=0, metavar="TRIALS",
+                    help="only run Table 7.1's experiment (n = 64, 256, 1024; TRIALS systems each) "
+                         "and print its statistics as one JSON line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-check", action="store_true",
                     help="skip the oracle's backward-error check of the final X")
@@ -150,6 +264,10 @@ def main() -> int:
     from paper_1212_4560_amd import genp, workloads as wl
 
     torch.cuda.set_device(0)
+    if args.table_7_1:
+        print(json.dumps({"experiment": "Table 7.1: relative residuals, +-1 circulant GENP",
+                          "data": "synthetic", "results": table_7_1(args.table_7_1)}), flush=True)
+        return 0
     t0 = time.perf_counter()
     if args.gaussian_inputs:
         spec = dict(wl.NAMED[args.workload])
@@ -246,6 +364,10 @@ def main() -> int:
     roof["traffic"] = traffic_if_current(n)
     if not args.no_mixed and args.prec == "f64":
         out["mixed"] = mixed_comparison(w, args, ms_per_step, value)
+    if not args.no_circulant and args.prec == "f64" and n >= 4 and n <= 16384 and n & (n - 1) == 0:
+        del w
+        torch.cuda.empty_cache()
+        out["circulant"] = circulant_comparison(args, n, ms_per_step)
     if not args.no_cpu_baseline:
         del s
         torch.cuda.empty_cache()

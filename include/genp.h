@@ -76,7 +76,8 @@ enum {
     GENP_EDEVICE = -2,    /* no usable gfx950 device, or a HIP call failed             */
     GENP_ENOMEM = -3,     /* device allocation failed                                  */
     GENP_ESTATE = -4,     /* call out of order                                         */
-    GENP_ENOTSUP = -5     /* combination not supported by this build                   */
+    GENP_ENOTSUP = -5,    /* combination not supported by this build                   */
+    GENP_ESINGULAR = -6   /* the multiplier is singular to working precision           */
 };
 
 #define GENP_ETA_HIST 64
@@ -105,6 +106,10 @@ typedef struct {
     double ms_panel;            /* sum over panels of diagonal-block LU start to block-solve
                                    end (overlaps the updates)                                 */
     int32_t n_schur;            /* number of step pairs summed in ms_schur                   */
+    double cond_g;              /* 2-norm condition number of G when it is known cheaply:
+                                   circulant: max_f |DFT(c)[f]| / min_f |DFT(c)[f]| (exact, the
+                                   circulant being normal, Theorem 2.1); none: 1; dense and
+                                   Toeplitz: NaN (not computed)                              */
 } genp_info;
 
 /*
@@ -130,6 +135,12 @@ int genp_destroy(genp_ctx* ctx);
  * FFTs of length n, Theorem 2.1 -- n must be a power of two with
  * 4 <= n <= 16384, else GENP_ENOTSUP), or none (G ignored).  Also computes
  * ||A||_inf.  Resets the context to the "preconditioned" state.
+ * A circulant multiplier whose spectrum has min |DFT(c)| <= n 2^-53 max |DFT(c)|,
+ * or a non-finite one, is rejected with GENP_ESINGULAR (the context is then left
+ * unpreconditioned): C = A G would be singular to working precision.  Draws with
+ * entries +-1 hit this with probability about 2 sqrt(2 / (pi n)), whenever the
+ * signs balance (DFT(c)[0] = 0) or balance over the even and odd positions
+ * (DFT(c)[n/2] = 0); the caller draws new signs.
  */
 int genp_precondition(genp_ctx* ctx, const double* A, int64_t lda, int mult,
                       const double* G, int64_t ldg);

@@ -61,6 +61,18 @@ def circulant_from_params(c: np.ndarray, n: int) -> np.ndarray:
     return c[(i - j) % n]
 
 
+def circulant_cond(c: np.ndarray) -> float:
+    """2-norm condition number of the circulant with first column c.
+
+    Theorem 2.1: the DFT diagonalizes every circulant, whose eigenvalues are
+    the DFT of its first column.  A circulant is normal, so its singular values
+    are the moduli of those eigenvalues and kappa_2 = max |DFT(c)| / min |DFT(c)|
+    (infinite when some DFT coefficient vanishes).  The FFT is a library step."""
+    lam = np.abs(np.fft.fft(np.asarray(c, dtype=np.float64)))
+    lo = lam.min()
+    return float(lam.max() / lo) if lo > 0 else float("inf")
+
+
 def dense_multiplier(G: Optional[np.ndarray], p: Optional[np.ndarray], n: int) -> np.ndarray:
     """The multiplier as a dense matrix: G itself, or built from its parameters
     (2n - 1 Toeplitz parameters, or n circulant parameters)."""

@@ -37,7 +37,9 @@ __device__ inline cplx cconj(cplx a) { return {a.re, -a.im}; }
 __device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
 
 // MODE 0: y = alpha * (x correlated / convolved with c) + beta * yin.
-// MODE 1: the spectrum X[0..N] of x itself (the multiplier's spectrum, once per multiplier).
+// MODE 1: the spectrum X[0..N] of x itself (the multiplier's spectrum, once per multiplier),
+// and in spec_out[N + 1] the pair (max_f |X[f]|, min_f |X[f]|): the extreme singular values
+// of the circulant, which is normal (Theorem 2.1).  A NaN modulus makes both NaN.
 template <int MODE, bool CONJ, typename TO>
 __global__ void __launch_bounds__(CIRC_THREADS)
 circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long long bx,
@@ -70,6 +72,13 @@ circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long lo
         __syncthreads();
     }
     // spectrum of the real vector, product with the multiplier's spectrum, repack
+    double smax = 0.0, smin = __builtin_inf();   // MODE 1: extreme moduli (NaN sticks)
+    auto upd_max = [&](double v) { smax = (v != v || v > smax) ? v : smax; };
+    auto upd_min = [&](double v) { smin = (v != v || v < smin) ? v : smin; };
+    auto track = [&](double v) {
+        upd_max(v);
+        upd_min(v);
+    };
     for (int f = tid; f <= (N >> 1); f += CIRC_THREADS) {
         if (f == 0) {
             const cplx z0 = L[0];
@@ -77,6 +86,8 @@ circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long lo
             if (MODE == 1) {
                 spec_out[0] = make_double2(x0, 0.0);
                 spec_out[N] = make_double2(xN, 0.0);
+                track(fabs(x0));
+                track(fabs(xN));
                 continue;
             }
             const cplx r0 = cmul({x0, 0.0}, CONJ ? cconj({spec[0].x, spec[0].y}) : cplx{spec[0].x, spec[0].y});
@@ -99,6 +110,8 @@ circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long lo
         if (MODE == 1) {
             spec_out[f] = make_double2(xf.re, xf.im);
             spec_out[g] = make_double2(xg.re, xg.im);
+            track(hypot(xf.re, xf.im));
+            track(hypot(xg.re, xg.im));
             continue;
         }
         const cplx sf = {spec[f].x, spec[f].y}, sg = {spec[g].x, spec[g].y};
@@ -111,7 +124,29 @@ circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long lo
         L[f] = {ef2.re - of2.im, ef2.im + of2.re};
         if (g != f) L[g] = {eg2.re - og2.im, eg2.im + og2.re};
     }
-    if (MODE == 1) return;
+    if constexpr (MODE == 1) {
+        // block reduction of the extreme moduli: within each wave, then across the 8 waves
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double a = __shfl_xor(smax, o, 64), b = __shfl_xor(smin, o, 64);
+            upd_max(a);
+            upd_min(b);
+        }
+        __shared__ double red[2][CIRC_THREADS / 64];
+        const int wv = tid >> 6;
+        if ((tid & 63) == 0) {
+            red[0][wv] = smax;
+            red[1][wv] = smin;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 0; w < CIRC_THREADS / 64; ++w) {
+                upd_max(red[0][w]);
+                upd_min(red[1][w]);
+            }
+            spec_out[N + 1] = make_double2(smax, smin);
+        }
+        return;
+    }
     __syncthreads();
     // inverse FFT of length N, decimation in frequency (bit-reversed output)
     for (int len = N; len >= 2; len >>= 1) {

@@ -11,6 +11,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <limits>
 #include <vector>
 
 #define HIPCK(x)                                      \
@@ -457,6 +459,7 @@ const char* genp_strerror(int s) {
         case GENP_ENOMEM: return "device allocation failed";
         case GENP_ESTATE: return "call out of order";
         case GENP_ENOTSUP: return "combination not supported";
+        case GENP_ESINGULAR: return "the multiplier is singular to working precision";
         default: return "unknown status";
     }
 }
@@ -588,7 +591,7 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
                 tw[k] = make_double2(cos(2.0 * pi * (double)k / (double)N), -sin(2.0 * pi * (double)k / (double)N));
             for (int64_t f = 0; f <= N; ++f)
                 wp[f] = make_double2(cos(2.0 * pi * (double)f / (double)n), -sin(2.0 * pi * (double)f / (double)n));
-            if (hipMalloc(&c->circ_spec, (N + 1) * sizeof(double2)) != hipSuccess ||
+            if (hipMalloc(&c->circ_spec, (N + 2) * sizeof(double2)) != hipSuccess ||
                 hipMalloc(&c->circ_tw, std::max<int64_t>(1, N / 2) * sizeof(double2)) != hipSuccess ||
                 hipMalloc(&c->circ_wp, (N + 1) * sizeof(double2)) != hipSuccess)
                 return GENP_ENOMEM;
@@ -657,7 +660,10 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
     HIPCK(launch_row_abs_sum_max(A, lda, (int)n, c->red + R_ANORM, c->stream));
     ev_end(c, EV_PRE);
     unsigned long long h[3];
+    double2 sv = make_double2(0.0, 0.0);   // circulant: (max, min) modulus of the spectrum
     HIPCK(hipMemcpyAsync(h, c->red, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    if (mult == GENP_G_CIRCULANT)
+        HIPCK(hipMemcpyAsync(&sv, c->circ_spec + n / 2 + 1, sizeof sv, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
     float ms_ag = 0.f;
     c->info.ms_ag = (mult != GENP_G_NONE && hipEventElapsedTime(&ms_ag, c->ev_ag[0], c->ev_ag[1]) == hipSuccess)
@@ -666,6 +672,15 @@ int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const
     c->info.max_abs_c = bits_to_double(h[R_MAXC]);
     c->info.anorm_inf = c->anorm;
     c->info.mult = mult;
+    c->info.cond_g = std::numeric_limits<double>::quiet_NaN();
+    if (mult == GENP_G_NONE) c->info.cond_g = 1.0;
+    if (mult == GENP_G_CIRCULANT) {
+        // the circulant is normal: its singular values are the moduli of its spectrum (Theorem 2.1)
+        c->info.cond_g = (sv.y > 0.0) ? sv.x / sv.y : std::numeric_limits<double>::infinity();
+        if (sv.x != sv.x || sv.y != sv.y) c->info.cond_g = std::numeric_limits<double>::quiet_NaN();
+        // singular to working precision (or non-finite): C = A G would be singular too
+        if (!(sv.y > (double)n * 0x1p-53 * sv.x) || !std::isfinite(sv.x)) return GENP_ESINGULAR;
+    }
     c->state = ST_PRECOND;
     return GENP_OK;
 }

@@ -26,7 +26,7 @@ F64, F32, BF16 = 0, 1, 2
 G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT = 0, 1, 2, 3
 SOLVER_LUIR, SOLVER_GMRES = 0, 1
 OK, BREAKDOWN, ENOCONV = 0, 1, 2
-EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP = -1, -2, -3, -4, -5
+EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP, ESINGULAR = -1, -2, -3, -4, -5, -6
 ETA_HIST = 64
 
 PRECS = {"f64": F64, "f32": F32, "bf16": BF16}
@@ -53,6 +53,7 @@ class GenpInfo(ctypes.Structure):
         ("ms_backward", ctypes.c_double),
         ("ms_ag", ctypes.c_double), ("ms_schur", ctypes.c_double), ("ms_panel", ctypes.c_double),
         ("n_schur", ctypes.c_int32),
+        ("cond_g", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -262,8 +263,8 @@ def _autograd_function():
         """
 
         @staticmethod
-        def forward(ctx, A, B, G=None, p=None, prec="f64", nb=256, refine=2, refine_bwd=1):
-            X, _, s = solve(A.detach(), B.detach(), G=G, p=p, prec=prec, nb=nb, refine=refine)
+        def forward(ctx, A, B, G=None, p=None, prec="f64", nb=256, refine=2, refine_bwd=1, c=None):
+            X, _, s = solve(A.detach(), B.detach(), G=G, p=p, prec=prec, nb=nb, refine=refine, c=c)
             ctx.solver = s
             ctx.refine_bwd = refine_bwd
             ctx.save_for_backward(X)
@@ -274,7 +275,7 @@ def _autograd_function():
             (X,) = ctx.saved_tensors
             dB, dA = ctx.solver.solve_backward(gX.contiguous(), X, want_dA=ctx.needs_input_grad[0],
                                                refine_iters=ctx.refine_bwd)
-            return dA, dB, None, None, None, None, None, None
+            return dA, dB, None, None, None, None, None, None, None
 
     return GenpSolve
 

@@ -42,6 +42,7 @@ import numpy as np
 MULT_DENSE = "dense"
 MULT_TOEPLITZ = "toeplitz"
 MULT_CIRCULANT = "circulant"
+MULT_CIRCULANT_PM1 = "circulant_pm1"   # circulant whose n entries are random signs +-1
 
 
 @dataclasses.dataclass
@@ -92,7 +93,44 @@ def _multiplier_draw(g: np.random.Generator, n: int, mult: str):
         return None, g.standard_normal(2 * n - 1)
     if mult == MULT_CIRCULANT:
         return None, g.standard_normal(n)
+    if mult == MULT_CIRCULANT_PM1:
+        return None, pm1_signs(g, n)
     raise ValueError(f"unknown multiplier kind {mult!r}")
+
+
+def pm1_signs(g: np.random.Generator, n: int) -> np.ndarray:
+    """n independent fair signs +-1 (FP64)."""
+    return g.integers(0, 2, n).astype(np.float64) * 2.0 - 1.0
+
+
+def pm1_redraw(n: int, seed: int, attempt: int) -> np.ndarray:
+    """A fresh sign vector for attempt number `attempt` of the draw with this seed
+    (independent stream per (seed, attempt); used when a draw is singular)."""
+    return pm1_signs(np.random.default_rng([seed, 7919, attempt]), n)
+
+
+def cs_illcond_lead(n: int, seed: int = 0, nrhs: int = 1, smallest_cos: float = 0.0) -> Workload:
+    """A well conditioned (orthogonal) A whose n/2 x n/2 leading block is ill conditioned,
+    with a +-1 circulant multiplier and b uniform in [-1, 1).
+
+    The CS decomposition gives A = diag(U1, U2) [[C, -S], [S, C]] diag(V1, V2)^T with
+    Haar U1, U2, V1, V2 of order n/2, C = diag(cos t_i), S = diag(sin t_i): A is
+    orthogonal (kappa_2 = 1) and its leading block U1 C V1^T has singular values
+    cos t_i.  The cosines are uniform in [0.5, 1) except the last, `smallest_cos`
+    (0: the leading block has rank n/2 - 1 in exact arithmetic)."""
+    if n < 2 or n % 2:
+        raise ValueError("n must be even and >= 2")
+    g = np.random.default_rng(seed)
+    h = n // 2
+    U1, U2, V1, V2 = (_q_positive_r_numpy(g.standard_normal((h, h))) for _ in range(4))
+    cosv = g.uniform(0.5, 1.0, h)
+    cosv[-1] = smallest_cos
+    sinv = np.sqrt(1.0 - cosv * cosv)
+    A = np.block([[(U1 * cosv) @ V1.T, -(U1 * sinv) @ V2.T],
+                  [(U2 * sinv) @ V1.T, (U2 * cosv) @ V2.T]])
+    B = g.uniform(-1.0, 1.0, (n, nrhs))
+    c = pm1_signs(g, n)
+    return Workload("cs_illcond_lead", n, seed, np.ascontiguousarray(A), B, MULT_CIRCULANT_PM1, p=c)
 
 
 def rank_deficient_lead(n: int = 256, seed: int = 1, nrhs: int = 1,

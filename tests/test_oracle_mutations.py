@@ -157,8 +157,14 @@ def check_circulant():
     return bool(np.array_equal(G, circulant(c)) and np.allclose(G @ v, np.fft.fft(c)[2] * v, atol=1e-12))
 
 
+def check_circulant_cond():
+    n = 9
+    c = np.random.default_rng(5).standard_normal(n)
+    return bool(np.isclose(og.circulant_cond(c), np.linalg.cond(og.circulant_from_params(c, n)), rtol=1e-9))
+
+
 CHECKS = [check_golden, check_exact, check_gepp_and_eta, check_toeplitz_scipy, check_blocked, check_adjoint_fd,
-          check_eta2, check_gmres, check_circulant]
+          check_eta2, check_gmres, check_circulant, check_circulant_cond]
 
 
 def run_checks():
@@ -297,6 +303,10 @@ SOURCE_MUTANTS = {
         "H[i + 1, j] = sn[i] * H[i, j] + cs[i] * H[i + 1, j]"),
     "eta_2: Frobenius norm of A": (
         "backward_error_2", "a = np.linalg.norm(A, 2)", "a = np.linalg.norm(A)"),
+    "circulant_cond: real part of the spectrum instead of its modulus": (
+        "circulant_cond", "lam = np.abs(np.fft.fft(", "lam = np.real(np.fft.fft("),
+    "circulant_cond: ratio upside down": (
+        "circulant_cond", "return float(lam.max() / lo)", "return float(lo / lam.max())"),
     "circulant: transposed index": (
         "circulant_from_params", "return c[(i - j) % n]", "return c[(j - i) % n]"),
     "gmres_ir: residual with the wrong sign": (

@@ -485,3 +485,64 @@ def test_circulant_multiplier_repairs_genp():
     res, LU, info = og.genp_solve(A, B, G, refine_steps=2, tol=1e-14, pivot_tol=n * og.U64)
     assert info.breakdown_col == 0
     assert res.eta_hist[-1] <= 1e-14
+
+
+def test_circulant_cond_against_svd_and_closed_forms():
+    """kappa_2 of a circulant from its spectrum (normality, Theorem 2.1) against the SVD of
+    the dense matrix, and closed forms: the identity (c = e_0) has kappa 1; a +-1 vector with
+    balanced signs has DFT(c)[0] = 0, one balanced over even and odd positions has
+    DFT(c)[n/2] = 0, both singular."""
+    g = np.random.default_rng(4)
+    for n in (5, 8, 33):
+        c = g.standard_normal(n)
+        assert np.isclose(og.circulant_cond(c), np.linalg.cond(og.circulant_from_params(c, n)), rtol=1e-9)
+        s = wl.pm1_signs(g, n)
+        k = og.circulant_cond(s)
+        if np.isfinite(k):
+            assert np.isclose(k, np.linalg.cond(og.circulant_from_params(s, n)), rtol=1e-9)
+    e0 = np.zeros(16)
+    e0[0] = 1.0
+    assert og.circulant_cond(e0) == 1.0
+    alt = (-1.0) ** np.arange(6)
+    u = np.array([1.0, -1.0, -1.0, 1.0, -1.0, 1.0])
+    assert u.sum() == 0 and u @ alt != 0 and og.circulant_cond(u) > 1e15
+    v = np.array([1.0, 1.0, 1.0, 1.0, -1.0, -1.0])
+    assert v.sum() != 0 and v @ alt == 0 and og.circulant_cond(v) > 1e15
+    assert np.isfinite(og.circulant_cond(np.array([1.0, 1.0, 1.0, -1.0])))   # spectrum 2, 2i, -2, -2i
+
+
+def test_pm1_circulant_singular_probability():
+    """A +-1 circulant is singular whenever its signs balance (probability C(n, n/2) / 2^n)
+    or balance between even and odd positions: over 4000 draws at n = 64 the singular
+    fraction lies between the first probability alone (0.099) and the sum of both plus
+    sampling slack."""
+    from math import comb
+    n = 64
+    g = np.random.default_rng(10)
+    sing = sum(not np.isfinite(og.circulant_cond(wl.pm1_signs(g, n))) for _ in range(4000))
+    p0 = comb(n, n // 2) / 2.0 ** n
+    assert 0.8 * p0 <= sing / 4000 <= 2 * p0 + 0.03
+
+
+def test_table_7_1_claims_with_pm1_circulant():
+    """Table 7.1's setting (well conditioned A, ill conditioned n/2 x n/2 leading block, +-1
+    circulant multiplier, b uniform in [-1, 1)): GENP on A itself gives a corrupted solution;
+    with a nonsingular +-1 circulant the relative residual stays below the table's worst value
+    at n = 64 (8.0e-11, zero refinement steps) and one refinement step takes it to the
+    rounding level (table: at most 5.3e-13)."""
+    n = 64
+    for seed in range(12):
+        w = wl.cs_illcond_lead(n, seed)
+        A, b = w.A, w.B
+        assert np.linalg.cond(A) < 1 + 1e-10 and np.linalg.cond(A[:n // 2, :n // 2]) > 1e12
+        LU0, _ = og.genp_unblocked(A)
+        assert og.relative_residual(A, og.lu_solve(LU0, b), b)[0] > 1e-6
+        c, attempt = w.p, 0
+        while not np.isfinite(og.circulant_cond(c)) or og.circulant_cond(c) > 1e8:
+            attempt += 1
+            c = wl.pm1_redraw(n, seed, attempt)
+        G = og.circulant_from_params(c, n)
+        res, LU, info = og.genp_solve(A, b, G, refine_steps=0)
+        r0 = og.relative_residual(A, res.X, b)[0]
+        r1 = og.relative_residual(A, og.refine(A, G, LU, b, res.X, 1).X, b)[0]
+        assert r0 <= 8.0e-11 and r1 <= 5.3e-13, (seed, r0, r1)
