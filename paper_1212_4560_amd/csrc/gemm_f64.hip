@@ -1,4 +1,5 @@
-// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4_f64), LDS double-buffered.
+// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4_f64): an LDS double-buffered
+// kernel for every shape, and a register-operand kernel for the two dominant products.
 //
 // D = alpha * op(A) op(B) + beta * Cin with M x N output, K reduction.  Used for
 // the multiplier product C = A G (section 1.1; G dense or generated from its
@@ -252,89 +253,146 @@ gemm_f64_kernel(GemmF64Args g) {
     }
 }
 
-// C = A G with G the Toeplitz matrix of parameters p (G(k, j) = p[k - j + K - 1]):
-// the plain product on interior tiles only (M, N multiples of 128, K of 32), with no
-// bounds checks and a 32-deep K chunk per barrier (the generated operand needs only a
-// window of BNt + 31 parameters in LDS, so two blocks still fit on a CU).  Same tile
-// layout and tile order as gemm_f64_kernel with one tile-row per group.
-__global__ void __launch_bounds__(256, 2)
-gemm_ag_toep_kernel(int M, int N, int K, const double* __restrict__ A, long long lda,
-                    const double* __restrict__ p, double* __restrict__ D, long long ldd) {
-    constexpr int BKT = 32, BMt = 128, BNt = 128, T = 256;
-    constexpr int LA = BMt * BKT / T, PB = BNt + BKT - 1;
-    __shared__ double As[2][BKT][BMt + 1];
-    __shared__ double Bs[2][PB];
+// Operands loaded straight into MFMA registers (no LDS, no barriers), for the two
+// products that dominate the solve: the multiplier product C = A G with a Toeplitz G
+// generated from its parameters, and the Schur complement updates A22 -= L21 U12.
+//
+// A workgroup of 4 waves covers 128 x 128 outputs, each wave an independent 64 x 64
+// tile (4 x 4 MFMA tiles).  The 16x16x4 MFMA sums over its 4 k-slots, and any fixed
+// assignment of actual k indices to the slots gives the same sum, so lane group q
+// (lanes 16q .. 16q+15) takes the k pair k0 + 2q, k0 + 2q + 1 of each 8-deep chunk:
+// its A fragment of a row is one 16-byte load, its B fragment two 8-byte loads from rows
+// of B, 16 consecutive columns per lane group.  Two register buffers alternate: the next
+// chunk's loads are issued before the current chunk's 32 MFMAs.  An FP64 MFMA of this
+// shape occupies the matrix unit for 64 cycles, so a chunk is about 2k cycles of MFMA per
+// wave and about 4k with two waves per SIMD: enough to cover the load latency from L2
+// without staging through LDS.  The loop body has no branches, so the waits the compiler
+// places before each MFMA only cover the buffer that MFMA reads.
+//
+// Requirements (checked by the launcher): M, N multiples of 64 (a wave whose quadrant lies
+// outside the output returns at once; there is no barrier to miss), K a multiple of 16,
+// A 16-byte aligned with an even leading dimension.  Toeplitz B: G(k, j) = p[k - j + ldb - 1],
+// K = ldb, N <= K.
+typedef const double __attribute__((address_space(1)))* gcd_ptr;   // global (not flat) loads
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef const f64x2 __attribute__((address_space(1)))* gcd2_ptr;
+
+template <bool TOEP>
+__device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
+    constexpr int KS = 2;   // k values per lane group per chunk; chunk depth 4 * KS = 8
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int ntn = N / BNt, total = (M / BMt) * ntn;
-    const int pid = xcd_remap(blockIdx.x, total);
-    const int m0 = (pid / ntn) * BMt, n0 = (pid % ntn) * BNt;
-    const int nk = K / BKT;
+    int bid = blockIdx.x;
+    int gM = g.M, gN = g.N;
+    const double* gA = g.A;
+    const double* gB = g.B;
+    const double* gCin = g.Cin;
+    double* gD = g.D;
+    {
+        const int t1 = ((g.M + 127) / 128) * ((g.N + 127) / 128);
+        if (g.M2 > 0 && bid >= t1) {
+            bid -= t1;
+            gM = g.M2;
+            gN = g.N2;
+            gA = g.A2;
+            gB = g.B2;
+            gCin = g.Cin2;
+            gD = g.D2;
+        }
+    }
+    const int ntm = (gM + 127) / 128, ntn = (gN + 127) / 128;
+    const int pid = xcd_remap(bid, ntm * ntn);
+    const int GROUP = g.group_m > 0 ? g.group_m : 8;
+    const int first_m = (pid / (GROUP * ntn)) * GROUP;
+    const int gsz = min(ntm - first_m, GROUP);
+    const int tm = first_m + (pid % (GROUP * ntn)) % gsz;
+    const int tn = (pid % (GROUP * ntn)) / gsz;
+    const int m0 = tm * 128 + wm * 64, n0 = tn * 128 + wn * 64;
+    if (m0 >= gM || n0 >= gN) return;
     const int lr = lane & 15, lq = lane >> 4;
-    double ra[LA], rb;
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int r = 0; r < LA; ++r) {
-            const int e = tid + r * T;
-            ra[r] = A[(long long)(m0 + e / BKT) * lda + k0 + e % BKT];
-        }
-        // window of p over k - j in [k0 - n0 - BNt + 1, k0 + BKT - 1 - n0]
-        const long long idx = (long long)k0 - n0 - (BNt - 1) + K - 1 + tid;
-        rb = (tid < PB && idx >= 0 && idx < 2LL * K - 1) ? p[idx] : 0.0;
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int r = 0; r < LA; ++r) {
-            const int e = tid + r * T;
-            As[buf][e % BKT][e / BKT] = ra[r];
-        }
-        if (tid < PB) Bs[buf][tid] = rb;
-    };
+    const long long lda = g.lda, ldb = g.ldb;
+    const gcd_ptr Ab = (gcd_ptr)(gA + (long long)(m0 + lr) * lda + lq * KS);
+    const gcd_ptr Bb = (gcd_ptr)(TOEP ? gB + (long long)lq * KS - (n0 + lr) + ldb - 1
+                                      : gB + (long long)lq * KS * ldb + n0 + lr);
     f64x4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    auto mfma_chunk = [&](int cur, int kk0, int kk1) {
+    double ra[2][4][KS], rb[2][4][KS];
+    auto load = [&](int buf, int k0) {
 #pragma unroll
-        for (int kk = kk0; kk < kk1; kk += 4) {
-            double af[4], bf[4];
+        for (int mi = 0; mi < 4; ++mi) {
+            const f64x2 v = *(gcd2_ptr)(Ab + (long long)mi * 16 * lda + k0);
+            ra[buf][mi][0] = v.x;
+            ra[buf][mi][1] = v.y;
+        }
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi) af[mi] = As[cur][kk + lq][wm * 64 + mi * 16 + lr];
+        for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[cur][(kk + lq) - (wn * 64 + ni * 16 + lr) + BNt - 1];
+            for (int s = 0; s < KS; ++s)
+                rb[buf][ni][s] = TOEP ? Bb[k0 + s - ni * 16] : Bb[(long long)(k0 + s) * ldb + ni * 16];
+    };
+    auto mma = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
-        }
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[buf][mi][s], rb[buf][ni][s], acc[mi][ni], 0, 0, 0);
     };
-    // Per chunk: issue the next chunk's loads, run half the MFMAs, write the next chunk to
-    // LDS (its loads have had half a chunk to land), run the other half.  The wave runs
-    // at raised priority through the MFMA stream and drops it before the barrier.
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * BKT);
-        __builtin_amdgcn_s_setprio(1);
-        mfma_chunk(cur, 0, BKT / 2);
-        if (kt + 1 < nk) sstore(cur ^ 1);
-        mfma_chunk(cur, BKT / 2, BKT);
-        __builtin_amdgcn_s_setprio(0);
-        __syncthreads();
+    // The empty asm statements keep the compiler from sinking each batch of loads down to
+    // its first use; the scheduling barriers keep the MFMAs from moving above the loads.
+    const int nk = g.K / (4 * KS);   // even
+    load(0, 0);
+    for (int c = 0; c < nk - 2; c += 2) {
+        load(1, (c + 1) * 4 * KS);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        mma(0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(0, (c + 2) * 4 * KS);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        mma(1);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    load(1, (nk - 1) * 4 * KS);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    mma(0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(1);
+    // epilogue: D = alpha acc + beta Cin; Cin may alias D, so each 16-row strip's loads are
+    // issued as a batch before its stores
+    const bool rd = g.beta != 0.0;
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < 4; ++mi) {
+        double cv[4][4];
+        if (rd) {
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cv[ni][r] = ((gcd_ptr)gCin)[(long long)(m0 + mi * 16 + lq + 4 * r) * g.ldci + n0 + ni * 16 + lr];
+        }
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                D[(long long)(m0 + wm * 64 + mi * 16 + lq + 4 * r) * ldd + n0 + wn * 64 + ni * 16 + lr] =
-                    acc[mi][ni][r];
+            for (int r = 0; r < 4; ++r) {
+                double v = g.alpha * acc[mi][ni][r];
+                if (rd) v = fma(g.beta, cv[ni][r], v);
+                ((double __attribute__((address_space(1)))*)gD)[(long long)(m0 + mi * 16 + lq + 4 * r) * g.ldd + n0 + ni * 16 + lr] = v;
+            }
+    }
 }
+
+// C = A G with the Toeplitz G generated from its parameters
+__global__ void __launch_bounds__(256, 2) gemm_ag_toep_kernel(GemmF64Args g) { gemm_regs_body<true>(g); }
+
+// D = alpha A B + beta Cin, A and B row-major (the Schur complement updates)
+__global__ void __launch_bounds__(256, 2) gemm_regs_kernel(GemmF64Args g) { gemm_regs_body<false>(g); }
 
 __global__ void splitk_reduce_kernel(int M, int N, int ks, const double* __restrict__ P, long long ldp,
                                      long long ss, double alpha, double beta, const double* Cin,
@@ -373,6 +431,15 @@ hipError_t dispatch_modes(const GemmF64Args& a, hipStream_t s) {
 
 }  // namespace
 
+// shapes the register-operand kernels take (see gemm_regs_body)
+static bool regs_ok(const GemmF64Args& a) {
+    auto al = [](const double* p, long long ld) { return ((uintptr_t)p & 15) == 0 && (ld & 1) == 0; };
+    if (a.ksplit > 1 || a.a_f32 || a.K <= 0 || a.K % 16) return false;
+    if (a.M % 64 || a.N % 64 || !al(a.A, a.lda)) return false;
+    if (a.M2 > 0 && (a.M2 % 64 || a.N2 % 64 || !al(a.A2, a.lda))) return false;
+    return true;
+}
+
 hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
     if (a.M2 > 0 && (a.N2 <= 0 || a.ksplit > 1 || a.a_f32)) return hipErrorInvalidValue;
     if (a.M <= 0 || a.N <= 0) {
@@ -395,13 +462,15 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
         if (a.amode == OP_T) return launch_t<2, 1, OP_T, OP_N, true>(a, s);
         return hipErrorInvalidValue;
     }
-    if (tile == 0 && a.M2 <= 0 && a.amode == OP_N && a.bmode == OP_TOEP && a.ksplit <= 1 && a.alpha == 1.0 &&
-        a.beta == 0.0 &&
-        a.M % 128 == 0 && a.N % 128 == 0 && a.K % 32 == 0 && a.K == a.ldb) {
-        // the multiplier product on full tiles (ldb carries the Toeplitz order, which is K)
-        hipLaunchKernelGGL(gemm_ag_toep_kernel, dim3((a.M / 128) * (a.N / 128)), dim3(256), 0, s, a.M, a.N, a.K, a.A,
-                           a.lda, a.B, a.D, a.ldd);
-        return hipGetLastError();
+    if (tile == 0 && regs_ok(a) && a.amode == OP_N && (a.bmode == OP_N || a.bmode == OP_TOEP)) {
+        const bool toep = a.bmode == OP_TOEP;
+        if (!toep || (a.M2 <= 0 && a.K == a.ldb && a.N <= a.K)) {
+            int tiles = ((a.M + 127) / 128) * ((a.N + 127) / 128);
+            if (a.M2 > 0) tiles += ((a.M2 + 127) / 128) * ((a.N2 + 127) / 128);
+            if (toep) hipLaunchKernelGGL(gemm_ag_toep_kernel, dim3(tiles), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL(gemm_regs_kernel, dim3(tiles), dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
     }
     switch (tile) {
         case 0: return dispatch_modes<2, 2>(a, s);
