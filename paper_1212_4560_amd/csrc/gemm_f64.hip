@@ -257,8 +257,8 @@ gemm_f64_kernel(GemmF64Args g) {
 // products that dominate the solve: the multiplier product C = A G with a Toeplitz G
 // generated from its parameters, and the Schur complement updates A22 -= L21 U12.
 //
-// A workgroup of 4 waves covers 128 x 128 outputs, each wave an independent 64 x 64
-// tile (4 x 4 MFMA tiles).  The 16x16x4 MFMA sums over its 4 k-slots, and any fixed
+// A workgroup of 2 x WMW waves covers (64 WMW) x 128 outputs, each wave an independent
+// 64 x 64 tile (4 x 4 MFMA tiles).  The 16x16x4 MFMA sums over its 4 k-slots, and any fixed
 // assignment of actual k indices to the slots gives the same sum, so lane group q
 // (lanes 16q .. 16q+15) takes the k pair k0 + 2q, k0 + 2q + 1 of each 8-deep chunk:
 // its A fragment of a row is one 16-byte load, its B fragment two 8-byte loads from rows
@@ -269,6 +269,11 @@ gemm_f64_kernel(GemmF64Args g) {
 // without staging through LDS.  The loop body has no branches, so the waits the compiler
 // places before each MFMA only cover the buffer that MFMA reads.
 //
+// WMW = 4 (8 waves, one workgroup per CU) keeps the waves that share a CU's matrix units in
+// one workgroup.  With two 4-wave workgroups per CU the older one takes the units first, the
+// two drift apart along K, and the workgroups of a tile-row stop meeting in L2: for C = A G
+// at n = 16384 the fetch counter read 2.1x more (the 8-wave form is 0.7 % slower).
+//
 // Requirements (checked by the launcher): M, N multiples of 64 (a wave whose quadrant lies
 // outside the output returns at once; there is no barrier to miss), K a multiple of 16,
 // A 16-byte aligned with an even leading dimension.  Toeplitz B: G(k, j) = p[k - j + ldb - 1],
@@ -277,8 +282,9 @@ typedef const double __attribute__((address_space(1)))* gcd_ptr;   // global (no
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef const f64x2 __attribute__((address_space(1)))* gcd2_ptr;
 
-template <bool TOEP>
+template <bool TOEP, int WMW>
 __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
+    constexpr int BMt = 64 * WMW;
     constexpr int KS = 2;   // k values per lane group per chunk; chunk depth 4 * KS = 8
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -289,7 +295,7 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
     const double* gCin = g.Cin;
     double* gD = g.D;
     {
-        const int t1 = ((g.M + 127) / 128) * ((g.N + 127) / 128);
+        const int t1 = ((g.M + BMt - 1) / BMt) * ((g.N + 127) / 128);
         if (g.M2 > 0 && bid >= t1) {
             bid -= t1;
             gM = g.M2;
@@ -300,14 +306,14 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
             gD = g.D2;
         }
     }
-    const int ntm = (gM + 127) / 128, ntn = (gN + 127) / 128;
+    const int ntm = (gM + BMt - 1) / BMt, ntn = (gN + 127) / 128;
     const int pid = xcd_remap(bid, ntm * ntn);
     const int GROUP = g.group_m > 0 ? g.group_m : 8;
     const int first_m = (pid / (GROUP * ntn)) * GROUP;
     const int gsz = min(ntm - first_m, GROUP);
     const int tm = first_m + (pid % (GROUP * ntn)) % gsz;
     const int tn = (pid % (GROUP * ntn)) / gsz;
-    const int m0 = tm * 128 + wm * 64, n0 = tn * 128 + wn * 64;
+    const int m0 = tm * BMt + wm * 64, n0 = tn * 128 + wn * 64;
     if (m0 >= gM || n0 >= gN) return;
     const int lr = lane & 15, lq = lane >> 4;
     const long long lda = g.lda, ldb = g.ldb;
@@ -389,10 +395,14 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
 }
 
 // C = A G with the Toeplitz G generated from its parameters
-__global__ void __launch_bounds__(256, 2) gemm_ag_toep_kernel(GemmF64Args g) { gemm_regs_body<true>(g); }
+__global__ void __launch_bounds__(512, 1) gemm_ag_toep_kernel(GemmF64Args g) { gemm_regs_body<true, 4>(g); }
 
-// D = alpha A B + beta Cin, A and B row-major (the Schur complement updates)
-__global__ void __launch_bounds__(256, 2) gemm_regs_kernel(GemmF64Args g) { gemm_regs_body<false>(g); }
+// D = alpha A B + beta Cin, A and B row-major (the Schur complement updates), 128 x 128
+// workgroups.  (256 x 128 workgroups run a lone update 6 % faster at M = N = 15872, but
+// inside the factorization they fill whole CUs, and the diagonal-block kernel on the side
+// stream then waits for a CU to drain and leaves half of it idle: the factorization took
+// 64.0 ms against 62.8.)
+__global__ void __launch_bounds__(256, 2) gemm_regs_kernel(GemmF64Args g) { gemm_regs_body<false, 2>(g); }
 
 __global__ void splitk_reduce_kernel(int M, int N, int ks, const double* __restrict__ P, long long ldp,
                                      long long ss, double alpha, double beta, const double* Cin,
@@ -465,9 +475,10 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, int tile, hipStream_t s) {
     if (tile == 0 && regs_ok(a) && a.amode == OP_N && (a.bmode == OP_N || a.bmode == OP_TOEP)) {
         const bool toep = a.bmode == OP_TOEP;
         if (!toep || (a.M2 <= 0 && a.K == a.ldb && a.N <= a.K)) {
-            int tiles = ((a.M + 127) / 128) * ((a.N + 127) / 128);
-            if (a.M2 > 0) tiles += ((a.M2 + 127) / 128) * ((a.N2 + 127) / 128);
-            if (toep) hipLaunchKernelGGL(gemm_ag_toep_kernel, dim3(tiles), dim3(256), 0, s, a);
+            const int bm = toep ? 256 : 128;   // workgroup rows (gemm_ag_toep_kernel: 8 waves)
+            int tiles = ((a.M + bm - 1) / bm) * ((a.N + 127) / 128);
+            if (a.M2 > 0) tiles += ((a.M2 + bm - 1) / bm) * ((a.N2 + 127) / 128);
+            if (toep) hipLaunchKernelGGL(gemm_ag_toep_kernel, dim3(tiles), dim3(512), 0, s, a);
             else hipLaunchKernelGGL(gemm_regs_kernel, dim3(tiles), dim3(256), 0, s, a);
             return hipGetLastError();
         }
