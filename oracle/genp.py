@@ -73,20 +73,54 @@ def circulant_cond(c: np.ndarray) -> float:
     return float(lam.max() / lo) if lo > 0 else float("inf")
 
 
+def householder_from_params(uv: np.ndarray, n: int) -> np.ndarray:
+    """Dense n x n Householder-type multiplier from uv = (u, v), 2n parameters:
+    G = I - 2 u v^T / (v^T u).
+
+    The multipliers named with Table 7.1 are written as I - u v^T / u^T v; taken
+    literally that matrix sends u to 0 and is singular for every u, v, so the
+    factor 2 is restored: G is then the oblique reflection (G^2 = I, det G = -1),
+    the classical Householder reflection when u = v."""
+    uv = np.asarray(uv, dtype=np.float64)
+    if uv.shape != (2 * n,):
+        raise ValueError("need 2n parameters (u, v)")
+    u, v = uv[:n], uv[n:]
+    return np.eye(n) - (2.0 / (v @ u)) * np.outer(u, v)
+
+
+def householder_cond(uv: np.ndarray) -> float:
+    """2-norm condition number of I - 2 u v^T / (v^T u): with a = ||u|| ||v|| / |v^T u|,
+    the singular values are 1 (n - 2 times) and a +- sqrt(a^2 - 1), so kappa_2 =
+    (a + sqrt(a^2 - 1))^2 (infinite when v^T u = 0)."""
+    uv = np.asarray(uv, dtype=np.float64)
+    n = uv.shape[0] // 2
+    u, v = uv[:n], uv[n:]
+    d = abs(v @ u)
+    if d == 0:
+        return float("inf")
+    a = max(1.0, np.linalg.norm(u) * np.linalg.norm(v) / d)
+    return float((a + np.sqrt(a * a - 1.0)) ** 2)
+
+
 def dense_multiplier(G: Optional[np.ndarray], p: Optional[np.ndarray], n: int) -> np.ndarray:
     """The multiplier as a dense matrix: G itself, or built from its parameters
-    (2n - 1 Toeplitz parameters, or n circulant parameters)."""
+    (2n - 1 Toeplitz parameters, n circulant parameters, or 2n Householder
+    parameters (u, v))."""
     if G is not None:
         return np.asarray(G, dtype=np.float64)
     if p is not None:
         p = np.asarray(p)
+        if p.shape[0] == 2 * n:
+            return householder_from_params(p, n)
         return circulant_from_params(p, n) if p.shape[0] == n and n > 1 else toeplitz_from_params(p, n)
     raise ValueError("need G or p")
 
 
-def precondition(A: np.ndarray, G: np.ndarray) -> np.ndarray:
-    """C = A G, the right multiplier of section 1.1 / Corollary 4.1(ii)."""
-    return np.asarray(A, dtype=np.float64) @ np.asarray(G, dtype=np.float64)
+def precondition(A: np.ndarray, G: np.ndarray, H: Optional[np.ndarray] = None) -> np.ndarray:
+    """C = A G, the right multiplier of section 1.1 / Corollary 4.1(ii); with a left
+    multiplier H (the G M case of Corollary 4.1), C = H A G."""
+    C = np.asarray(A, dtype=np.float64) @ np.asarray(G, dtype=np.float64)
+    return C if H is None else np.asarray(H, dtype=np.float64) @ C
 
 
 # ---------------------------------------------------------------------------
@@ -217,8 +251,12 @@ def lu_solve(LU: np.ndarray, B: np.ndarray) -> np.ndarray:
     return backward_upper(LU, forward_unit(LU, B))
 
 
-def solve(LU: np.ndarray, G: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """X = G U^{-1} L^{-1} B: the solution of A X = B from the factors of C = A G."""
+def solve(LU: np.ndarray, G: np.ndarray, B: np.ndarray, H: Optional[np.ndarray] = None) -> np.ndarray:
+    """X = G U^{-1} L^{-1} B: the solution of A X = B from the factors of C = A G.
+    With a left multiplier, C = H A G and A X = B  <=>  C (G^{-1} X) = H B, so
+    X = G U^{-1} L^{-1} H B."""
+    if H is not None:
+        B = np.asarray(H, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
     return G @ lu_solve(LU, B)
 
 
@@ -262,8 +300,9 @@ class SolveResult:
     steps: int
 
 
-def refine(A, G, LU, B, X, max_iter: int = 2, tol: float = 0.0) -> SolveResult:
-    """Iterative refinement in FP64: R = B - A X, X += G (LU)^{-1} R.
+def refine(A, G, LU, B, X, max_iter: int = 2, tol: float = 0.0, H: Optional[np.ndarray] = None) -> SolveResult:
+    """Iterative refinement in FP64: R = B - A X, X += G (LU)^{-1} R (G (LU)^{-1} H R
+    with a left multiplier H).
 
     Section 7.1 reports one refinement step after GENP (Table 7.1); section
     7.2 performs at most two.  Stops early when max_j eta_j <= tol.
@@ -273,21 +312,21 @@ def refine(A, G, LU, B, X, max_iter: int = 2, tol: float = 0.0) -> SolveResult:
     steps = 0
     while steps < max_iter and hist[-1] > tol:
         R = residual(A, X, B)
-        X += solve(LU, G, R)
+        X += solve(LU, G, R, H)
         steps += 1
         hist.append(float(np.max(backward_error_inf(A, X, B))))
     return SolveResult(X, hist, steps)
 
 
 def genp_solve(A, B, G, nb: Optional[int] = None, refine_steps: int = 2, tol: float = 0.0,
-               pivot_tol: float = 0.0):
-    """The whole path: C = AG, GENP, substitutions, X = GY, refinement."""
-    C = precondition(A, G)
+               pivot_tol: float = 0.0, H: Optional[np.ndarray] = None):
+    """The whole path: C = AG (or H A G), GENP, substitutions, X = GY, refinement."""
+    C = precondition(A, G, H)
     LU, info = genp_unblocked(C, pivot_tol) if nb is None else genp_blocked(C, nb, pivot_tol)
     if info.breakdown_col:
         return None, LU, info
-    X = solve(LU, G, B)
-    res = refine(A, G, LU, B, X, refine_steps, tol)
+    X = solve(LU, G, B, H)
+    res = refine(A, G, LU, B, X, refine_steps, tol, H)
     return res, LU, info
 
 

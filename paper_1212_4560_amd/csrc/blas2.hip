@@ -269,6 +269,125 @@ hipError_t gemv_dispatch(int M, int K, int nr, double alpha, const TA* A, long l
     }
 }
 
+// Transposed products y = alpha A^T X + beta yin with A stored K x M (y_j = sum_k A[k][j] X[k]),
+// in two deterministic passes: partial sums over row slices, then their sum.
+// Wide form (M >= 64): one thread per output j, blockIdx.y = row slice.
+template <int NR, typename TA>
+__global__ void __launch_bounds__(256)
+gemv_tw_part_kernel(int M, int K, int slice, const TA* __restrict__ A, long long lda, const double* __restrict__ X,
+                    long long ldx, double* __restrict__ part) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= M) return;
+    const int k0 = blockIdx.y * slice, k1 = min(K, k0 + slice);
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    int k = k0;
+    for (; k + 3 < k1; k += 4) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = (double)A[(long long)(k + u) * lda + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], X[(long long)(k + u) * ldx + c], acc[c]);
+    }
+    for (; k < k1; ++k) {
+        const double a = (double)A[(long long)k * lda + j];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = fma(a, X[(long long)k * ldx + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) part[((long long)blockIdx.y * M + j) * NR + c] = acc[c];
+}
+
+// Narrow form (M <= 4 outputs, one right-hand side): the block's threads stride over the rows
+// of its slice, then reduce in LDS.
+__global__ void __launch_bounds__(256)
+gemv_tn_part_kernel(int M, int K, int slice, const double* __restrict__ A, long long lda,
+                    const double* __restrict__ x, long long ldx, double* __restrict__ part) {
+    __shared__ double red[4][256];
+    const int t = threadIdx.x;
+    const int k0 = blockIdx.x * slice, k1 = min(K, k0 + slice);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = k0 + t; k < k1; k += 256) {
+        const double xv = x[(long long)k * ldx];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < M) acc[j] = fma(A[(long long)k * lda + j], xv, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[j][t] = acc[j];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[j][t] += red[j][t + h];
+        __syncthreads();
+    }
+    if (t < M) part[(long long)blockIdx.x * M + t] = red[t][0];
+}
+
+// y_j = alpha sum_p part[p][j] + beta yin_j (fixed order over p)
+__global__ void gemv_t_reduce_kernel(int M, int NR, int P, const double* __restrict__ part, double alpha,
+                                     double beta, const double* Yin, long long ldyi, double* Y, long long ldy) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * NR) return;
+    const int j = e / NR, c = e % NR;
+    double s = 0.0;
+    for (int q = 0; q < P; ++q) s += part[((long long)q * M + j) * NR + c];
+    double v = alpha * s;
+    if (beta != 0.0) v = fma(beta, Yin[(long long)j * ldyi + c], v);
+    Y[(long long)j * ldy + c] = v;
+}
+
+// Y = alpha (X - s a b^T) + beta Yin with s = factor / dot[0] read from device memory (the
+// Householder multiplier I - 2 u v^T / (v^T u) applied as a rank-1 update).  One block per row.
+template <typename TO>
+__global__ void __launch_bounds__(256)
+rank1_kernel(int M, int N, double alpha, const double* X, long long ldx, const double* __restrict__ a,
+             const double* __restrict__ b, const double* __restrict__ dot, double factor, double beta,
+             const double* Yin, long long ldyi, TO* Y, long long ldy) {
+    const int i = blockIdx.x;
+    if (i >= M) return;
+    const double sa = factor / dot[0] * a[i];
+    const double* xr = X + (long long)i * ldx;
+    const double* yr = (beta != 0.0) ? Yin + (long long)i * ldyi : nullptr;
+    TO* outr = Y + (long long)i * ldy;
+    for (int j = threadIdx.x; j < N; j += 256) {
+        double v = alpha * fma(-sa, b[j], xr[j]);
+        if (yr) v = fma(beta, yr[j], v);
+        outr[j] = (TO)v;
+    }
+}
+
+// out = (v^T u, u^T u, v^T v), one block, fixed reduction order
+__global__ void __launch_bounds__(1024) dot3_kernel(int n, const double* __restrict__ u, const double* __restrict__ v,
+                                                    double* __restrict__ out) {
+    __shared__ double red[3][1024];
+    const int t = threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = t; i < n; i += 1024) {
+        const double ui = u[i], vi = v[i];
+        a = fma(vi, ui, a);
+        b = fma(ui, ui, b);
+        c = fma(vi, vi, c);
+    }
+    red[0][t] = a;
+    red[1][t] = b;
+    red[2][t] = c;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] += red[1][t + h];
+            red[2][t] += red[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 3) out[t] = red[t][0];
+}
+
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -374,5 +493,62 @@ hipError_t launch_scale2d(double alpha, double* X, long long ldx, int rows, int 
     const long long tot = (long long)rows * cols;
     if (tot <= 0) return hipSuccess;
     hipLaunchKernelGGL(scale2d_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, alpha, X, ldx, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_t_f64(int M, int K, int nrhs, double alpha, const void* A, long long lda, int a_f32,
+                             const double* X, long long ldx, double beta, const double* Yin, long long ldyi,
+                             double* Y, long long ldy, double* part, long long part_cap, hipStream_t s) {
+    if (M <= 0 || nrhs <= 0) return hipSuccess;
+    if (nrhs > 4 || K <= 0) return hipErrorInvalidValue;
+    const bool narrow = M <= 4 && nrhs == 1 && !a_f32;
+    // slices: enough blocks to fill the GPU, at least 16 rows each, partials within part_cap
+    const long long cols = narrow ? 1 : (M + 255) / 256;
+    long long P = std::max<long long>(1, 2048 / cols);
+    P = std::min<long long>(P, std::max(1, K / 16));
+    P = std::min<long long>(P, part_cap / ((long long)M * nrhs));
+    if (P < 1) return hipErrorInvalidValue;
+    const int slice = (int)((K + P - 1) / P);
+    P = (K + slice - 1) / slice;
+    if (narrow) {
+        hipLaunchKernelGGL(gemv_tn_part_kernel, dim3((unsigned)P), dim3(256), 0, s, M, K, slice, (const double*)A,
+                           lda, X, ldx, part);
+    } else {
+#define GENP_GTW(NR)                                                                                          \
+    if (a_f32)                                                                                                \
+        hipLaunchKernelGGL((gemv_tw_part_kernel<NR, float>), dim3((unsigned)cols, (unsigned)P), dim3(256), 0, \
+                           s, M, K, slice, (const float*)A, lda, X, ldx, part);                               \
+    else                                                                                                      \
+        hipLaunchKernelGGL((gemv_tw_part_kernel<NR, double>), dim3((unsigned)cols, (unsigned)P), dim3(256), 0, \
+                           s, M, K, slice, (const double*)A, lda, X, ldx, part)
+        switch (nrhs) {
+            case 1: GENP_GTW(1); break;
+            case 2: GENP_GTW(2); break;
+            case 3: GENP_GTW(3); break;
+            default: GENP_GTW(4); break;
+        }
+#undef GENP_GTW
+    }
+    const int tot = M * nrhs;
+    hipLaunchKernelGGL(gemv_t_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, M, nrhs, (int)P, part, alpha,
+                       beta, Yin, ldyi, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank1(int M, int N, double alpha, const double* X, long long ldx, const double* a, const double* b,
+                        const double* dot, double factor, double beta, const double* Yin, long long ldyi, void* Y,
+                        int y_f32, long long ldy, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (y_f32)
+        hipLaunchKernelGGL(rank1_kernel<float>, dim3(M), dim3(256), 0, s, M, N, alpha, X, ldx, a, b, dot, factor, beta,
+                           Yin, ldyi, (float*)Y, ldy);
+    else
+        hipLaunchKernelGGL(rank1_kernel<double>, dim3(M), dim3(256), 0, s, M, N, alpha, X, ldx, a, b, dot, factor,
+                           beta, Yin, ldyi, (double*)Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot3(int n, const double* u, const double* v, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(dot3_kernel, dim3(1), dim3(1024), 0, s, n, u, v, out);
     return hipGetLastError();
 }

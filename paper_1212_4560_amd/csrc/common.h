@@ -97,6 +97,17 @@ hipError_t launch_copy2d(const double* src, long long lds, double* dst, long lon
 hipError_t launch_axpy2d(double alpha, const double* X, long long ldx, double* Y, long long ldy,
                          int rows, int cols, hipStream_t s);
 hipError_t launch_fill2d(double v, double* X, long long ldx, int rows, int cols, hipStream_t s);
+// y (M x nrhs) = alpha A^T X + beta yin for A stored K x M (row-major, lda), nrhs <= 4, in two
+// deterministic passes through part (at least M * nrhs doubles; more allows more row slices).
+hipError_t launch_gemv_t_f64(int M, int K, int nrhs, double alpha, const void* A, long long lda, int a_f32,
+                             const double* X, long long ldx, double beta, const double* Yin, long long ldyi,
+                             double* Y, long long ldy, double* part, long long part_cap, hipStream_t s);
+// Y (M x N, FP64 or FP32) = alpha (X - (factor / dot[0]) a b^T) + beta Yin; dot is a device scalar
+hipError_t launch_rank1(int M, int N, double alpha, const double* X, long long ldx, const double* a, const double* b,
+                        const double* dot, double factor, double beta, const double* Yin, long long ldyi, void* Y,
+                        int y_f32, long long ldy, hipStream_t s);
+// out[0..2] = (v^T u, u^T u, v^T v)
+hipError_t launch_dot3(int n, const double* u, const double* v, double* out, hipStream_t s);
 
 // y[i][c] = beta * yin[i][c] + alpha * sum_k op(A)(i, k) x[k][c] for nrhs <= 4 (one wave per row).
 hipError_t launch_gemv_f64(int M, int K, int nrhs, double alpha,

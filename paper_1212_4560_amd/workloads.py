@@ -43,6 +43,7 @@ MULT_DENSE = "dense"
 MULT_TOEPLITZ = "toeplitz"
 MULT_CIRCULANT = "circulant"
 MULT_CIRCULANT_PM1 = "circulant_pm1"   # circulant whose n entries are random signs +-1
+MULT_HOUSEHOLDER = "householder"       # 2n parameters (u, v), independent random signs +-1
 
 
 @dataclasses.dataclass
@@ -95,6 +96,8 @@ def _multiplier_draw(g: np.random.Generator, n: int, mult: str):
         return None, g.standard_normal(n)
     if mult == MULT_CIRCULANT_PM1:
         return None, pm1_signs(g, n)
+    if mult == MULT_HOUSEHOLDER:
+        return None, pm1_signs(g, 2 * n)
     raise ValueError(f"unknown multiplier kind {mult!r}")
 
 

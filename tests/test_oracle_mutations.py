@@ -163,8 +163,29 @@ def check_circulant_cond():
     return bool(np.isclose(og.circulant_cond(c), np.linalg.cond(og.circulant_from_params(c, n)), rtol=1e-9))
 
 
+def check_householder():
+    n = 7
+    g = np.random.default_rng(6)
+    uv = g.standard_normal(2 * n)
+    G = og.householder_from_params(uv, n)
+    return bool(np.allclose(G @ G, np.eye(n), atol=1e-12) and np.allclose(G @ uv[:n], -uv[:n], atol=1e-12)
+                and np.isclose(og.householder_cond(uv), np.linalg.cond(G), rtol=1e-8))
+
+
+def check_left():
+    n = 12
+    g = np.random.default_rng(7)
+    A, H, G, B = (g.standard_normal((n, n)), g.standard_normal((n, n)), g.standard_normal((n, n)),
+                  g.standard_normal((n, 2)))
+    LU, _ = og.genp_unblocked(og.precondition(A, G, H))
+    X = og.solve(LU, G, B, H)
+    res = og.refine(A, G, LU, B, X + 1e-6, 1, 0.0, H)
+    x0 = np.linalg.solve(A, B)
+    return bool(np.allclose(X, x0, atol=1e-8) and np.allclose(res.X, x0, atol=1e-8))
+
+
 CHECKS = [check_golden, check_exact, check_gepp_and_eta, check_toeplitz_scipy, check_blocked, check_adjoint_fd,
-          check_eta2, check_gmres, check_circulant, check_circulant_cond]
+          check_eta2, check_gmres, check_circulant, check_circulant_cond, check_householder, check_left]
 
 
 def run_checks():
@@ -307,6 +328,17 @@ SOURCE_MUTANTS = {
         "circulant_cond", "lam = np.abs(np.fft.fft(", "lam = np.real(np.fft.fft("),
     "circulant_cond: ratio upside down": (
         "circulant_cond", "return float(lam.max() / lo)", "return float(lo / lam.max())"),
+    "householder: the literal formula (factor 2 dropped)": (
+        "householder_from_params", "(2.0 / (v @ u))", "(1.0 / (v @ u))"),
+    "householder: rank-one term added": (
+        "householder_from_params", "np.eye(n) - (2.0", "np.eye(n) + (2.0"),
+    "householder_cond: reciprocal of the largest singular value": (
+        "householder_cond", "return float((a + np.sqrt(a * a - 1.0)) ** 2)", "return float(a + np.sqrt(a * a - 1.0))"),
+    "left multiplier: applied after the substitutions": (
+        "solve", "        B = np.asarray(H, dtype=np.float64) @ np.asarray(B, dtype=np.float64)\n    return G @ lu_solve(LU, B)",
+        "        return G @ (np.asarray(H, dtype=np.float64) @ lu_solve(LU, B))\n    return G @ lu_solve(LU, B)"),
+    "left multiplier: dropped from the product": (
+        "precondition", "return C if H is None else np.asarray(H, dtype=np.float64) @ C", "return C"),
     "circulant: transposed index": (
         "circulant_from_params", "return c[(i - j) % n]", "return c[(j - i) % n]"),
     "gmres_ir: residual with the wrong sign": (

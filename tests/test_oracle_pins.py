@@ -546,3 +546,87 @@ def test_table_7_1_claims_with_pm1_circulant():
         r0 = og.relative_residual(A, res.X, b)[0]
         r1 = og.relative_residual(A, og.refine(A, G, LU, b, res.X, 1).X, b)[0]
         assert r0 <= 8.0e-11 and r1 <= 5.3e-13, (seed, r0, r1)
+
+
+# ---------------------------------------------------------------------------
+# Householder-type multipliers; left and two-sided multipliers (Corollary 4.1)
+# ---------------------------------------------------------------------------
+
+def test_householder_reading_and_closed_forms():
+    """The literal I - u v^T / u^T v annihilates u (singular for every u, v), which is why the
+    oracle restores the factor 2.  G = I - 2 u v^T / (v^T u) is then an involution with
+    det G = -1, G u = -u and G w = w for v^T w = 0; with u = v it is orthogonal."""
+    n = 9
+    g = np.random.default_rng(30)
+    u, v = g.standard_normal(n), g.standard_normal(n)
+    literal = np.eye(n) - np.outer(u, v) / (u @ v)
+    assert np.allclose(literal @ u, 0.0, atol=1e-12)
+    G = og.householder_from_params(np.concatenate([u, v]), n)
+    assert np.allclose(G @ G, np.eye(n), atol=1e-12)
+    sign, logdet = np.linalg.slogdet(G)
+    assert sign == -1.0 and abs(logdet) < 1e-12
+    assert np.allclose(G @ u, -u, atol=1e-12)
+    w = g.standard_normal(n)
+    w -= (v @ w) / (v @ v) * v
+    assert np.allclose(G @ w, w, atol=1e-12)
+    R = og.householder_from_params(np.concatenate([u, u]), n)
+    assert np.allclose(R.T @ R, np.eye(n), atol=1e-12)
+
+
+def test_householder_cond_against_svd():
+    """kappa_2 = (a + sqrt(a^2 - 1))^2 with a = ||u|| ||v|| / |v^T u|, against the SVD, for
+    Gaussian and +-1 parameters; orthogonal (kappa 1) when u = v; infinite when v^T u = 0."""
+    g = np.random.default_rng(31)
+    for n in (5, 16, 40):
+        for uv in (g.standard_normal(2 * n), wl.pm1_signs(g, 2 * n)):
+            k = og.householder_cond(uv)
+            if np.isfinite(k):
+                assert np.isclose(k, np.linalg.cond(og.householder_from_params(uv, n)), rtol=1e-8)
+        u = g.standard_normal(n)
+        assert np.isclose(og.householder_cond(np.concatenate([u, u])), 1.0)
+    assert og.householder_cond(np.array([1.0, 1.0, 1.0, -1.0])) == float("inf")
+
+
+def test_householder_repairs_a_rank_deficiency_of_one_only():
+    """A G = A - 2 (A u) v^T / (v^T u) changes every leading block by rank one, so it can repair
+    a leading block whose rank is one short (GENP then succeeds) but not one whose rank is
+    short by more (GENP still breaks down)."""
+    n = 64
+    g = np.random.default_rng(32)
+    uv = wl.pm1_signs(g, 2 * n)
+    while not np.isfinite(og.householder_cond(uv)) or og.householder_cond(uv) > 1e6:
+        uv = wl.pm1_signs(g, 2 * n)
+    G = og.householder_from_params(uv, n)
+    tol = 1e-10   # far below every regular pivot here, far above the rounding of a singular block
+    for rank, repaired in ((7, True), (5, False)):
+        A = g.standard_normal((n, n))
+        A[:8, :8] = g.standard_normal((8, rank)) @ g.standard_normal((rank, 8))
+        _, info_a = og.genp_unblocked(A, pivot_tol=tol)
+        assert info_a.breakdown_col == rank + 1
+        _, info = og.genp_unblocked(og.precondition(A, G), pivot_tol=tol)
+        assert (info.breakdown_col == 0) == repaired, (rank, info.breakdown_col)
+
+
+def test_left_and_two_sided_multipliers_solve_the_system():
+    """With a left multiplier H, A x = b is solved as (H A G) y = H b, x = G y: the result equals
+    LAPACK's solution of A x = b, for H alone and for H with a Toeplitz G; a Gaussian left
+    multiplier repairs the rank-deficient leading block (Corollary 4.1, the G M case: the
+    leading columns of A have full rank) and refinement reaches eta <= 1e-14."""
+    n = 48
+    g = np.random.default_rng(33)
+    A = g.standard_normal((n, n))
+    B = g.standard_normal((n, 2))
+    H = g.standard_normal((n, n))
+    T = og.toeplitz_from_params(g.standard_normal(2 * n - 1), n)
+    x0 = np.linalg.solve(A, B)
+    for G in (np.eye(n), T):
+        LU, info = og.genp_unblocked(og.precondition(A, G, H))
+        assert info.breakdown_col == 0
+        X = og.solve(LU, G, B, H)
+        assert np.max(np.abs(X - x0)) <= 1e-8 * np.max(np.abs(x0))
+        assert not np.allclose(og.solve(LU, G, B), x0, atol=1e-3)   # without H B the result is wrong
+    w = wl.make("c1_n256_rankdef")
+    m = w.n
+    Hm = g.standard_normal((m, m))
+    res, LU, info = og.genp_solve(w.A, w.B, np.eye(m), refine_steps=2, tol=1e-14, pivot_tol=m * og.U64, H=Hm)
+    assert info.breakdown_col == 0 and res.eta_hist[-1] <= 1e-14
