@@ -12,8 +12,9 @@ Prints ONE JSON line.  GFLOP/s counts the method's algorithmic flops
 2n^3 + (2/3 n^3 - n^2/2 - n/6) + 4 n^2 k + it * 6 n^2 k.
 Beside the headline it reports, as context, the precision form (FP32 / BF16
 factors with FP64 GMRES refinement) and the same recipe with a Gaussian
-circulant multiplier applied by FFT (time to solution, not GFLOP/s: the FFT
-path does O(n^2 log n) work for the product instead of 2n^3).
+circulant multiplier applied by FFT and with a +-1 Householder-type multiplier
+(time to solution, not GFLOP/s: these products take O(n^2 log n) and O(n^2)
+work instead of 2n^3).
 """
 from __future__ import annotations
 
@@ -89,23 +90,36 @@ def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
     return res
 
 
-def circulant_comparison(args, n: int, f64_ms: float) -> dict:
-    """The same recipe with a Gaussian circulant multiplier (Definition 3.2) applied by FFT
-    instead of the Toeplitz product: one warm-up, then `steps` timed whole-path steps."""
+def structured_comparison(args, n: int, f64_ms: float, kind: str) -> dict:
+    """The same recipe with a structured multiplier applied in fewer than 2n^3 flops instead of
+    the Toeplitz product: a Gaussian circulant (Definition 3.2, by FFT) or a +-1 Householder-type
+    multiplier (rank-1 updates).  One warm-up, then `steps` timed whole-path steps."""
     import numpy as np
     import torch
     from paper_1212_4560_amd import genp, workloads as wl
-    name = "c3c_n16384_haar1e6_circulant"
+    name = {"circulant": "c3c_n16384_haar1e6_circulant", "householder": "c3h_n16384_haar1e6_householder"}[kind]
     w = wl.make(name, n=n, device="cuda")
     k = w.nrhs
     stream = torch.cuda.current_stream()
     s = genp.Solver(n, "f64", args.nb, stream=stream)
     X = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    par = w.p
+    kw = "c" if kind == "circulant" else "uv"
+    attempt = 0
+    while True:   # +-1 parameters can be singular (v^T u = 0): draw new signs
+        try:
+            s.precondition(w.A, **{kw: par})
+            break
+        except genp.GenpError as e:
+            if e.status != genp.ESINGULAR or kind != "householder" or attempt > 8:
+                raise
+            attempt += 1
+            par = torch.from_numpy(wl.pm1_redraw(2 * n, w.seed, attempt)).to("cuda")
 
     def step():
-        s.precondition(w.A, c=w.p)
+        s.precondition(w.A, **{kw: par})
         if s.factor(0.0):
-            raise RuntimeError("circulant multiplier: breakdown")
+            raise RuntimeError(f"{kind} multiplier: breakdown")
         s.solve(w.B, X)
         st, eta = s.refine(w.B, X, args.max_refine, args.tol, args.solver)
         return s.info()
@@ -126,13 +140,13 @@ def circulant_comparison(args, n: int, f64_ms: float) -> dict:
         from oracle import genp as og
         eta_orc = float(np.max(og.backward_error_inf(w.A.cpu().numpy(), X.cpu().numpy(), w.B.cpu().numpy())))
     res = {"workload": name, "n": n, "nrhs": k, "ms_per_step": round(ms, 3),
-           "stage_ms": {"precondition_fft": round(last["ms_precond"], 3), "factor": round(last["ms_factor"], 3),
+           "stage_ms": {"precondition": round(last["ms_precond"], 3), "factor": round(last["ms_factor"], 3),
                         "solve": round(last["ms_solve"], 3), "refine": round(last["ms_refine"], 3)},
            "refine_steps": [i["iters"] for i in infos], "eta_lib": max(i["eta"] for i in infos),
-           "eta_oracle": eta_orc, "growth": last["growth"],
+           "eta_oracle": eta_orc, "growth": last["growth"], "cond_g": last["cond_g"],
            "speedup_vs_toeplitz_gemm_path": round(f64_ms / ms, 3)}
-    log(f"[bench] circulant: {ms:.1f} ms per step (FFT product {last['ms_precond']:.2f} ms, factor "
-        f"{last['ms_factor']:.1f} ms), eta {res['eta_lib']:.2e}")
+    log(f"[bench] {kind}: {ms:.1f} ms per step (product {last['ms_precond']:.2f} ms, factor "
+        f"{last['ms_factor']:.1f} ms), eta {res['eta_lib']:.2e}, cond(G) {last['cond_g']:.3g}")
     del s, X, w
     torch.cuda.empty_cache()
     return res
@@ -244,7 +258,7 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain copy kernel of the n x n working matrix (PMC calibration)")
     ap.add_argument("--no-circulant", action="store_true",
-                    help="skip the circulant-multiplier (FFT) comparison")
+                    help="skip the structured-multiplier comparisons (circulant by FFT, Householder)")
     ap.add_argument("--table-7-1", type=int, default=0, metavar="TRIALS",
                     help="only run Table 7.1's experiment (n = 64, 256, 1024; TRIALS systems each) "
                          "and print its statistics as one JSON line")
@@ -364,10 +378,12 @@ def main() -> int:
     roof["traffic"] = traffic_if_current(n)
     if not args.no_mixed and args.prec == "f64":
         out["mixed"] = mixed_comparison(w, args, ms_per_step, value)
-    if not args.no_circulant and args.prec == "f64" and n >= 4 and n <= 16384 and n & (n - 1) == 0:
+    if not args.no_circulant and args.prec == "f64":
         del w
         torch.cuda.empty_cache()
-        out["circulant"] = circulant_comparison(args, n, ms_per_step)
+        if 4 <= n <= 16384 and n & (n - 1) == 0:
+            out["circulant"] = structured_comparison(args, n, ms_per_step, "circulant")
+        out["householder"] = structured_comparison(args, n, ms_per_step, "householder")
     if not args.no_cpu_baseline:
         del s
         torch.cuda.empty_cache()

@@ -58,8 +58,12 @@ enum {
     GENP_G_DENSE = 0,     /* G: n x n dense, row-major, leading dimension ldg        */
     GENP_G_TOEPLITZ = 1,  /* G: 2n-1 parameters p, G[i][j] = p[i - j + n - 1]        */
     GENP_G_NONE = 2,      /* no multiplier: C = A (plain GENP, for tests)            */
-    GENP_G_CIRCULANT = 3  /* G: n parameters c, G[i][j] = c[(i - j) mod n]; applied by
+    GENP_G_CIRCULANT = 3, /* G: n parameters c, G[i][j] = c[(i - j) mod n]; applied by
                              FFT; n a power of two, 4 <= n <= 16384                    */
+    GENP_G_HOUSEHOLDER = 4 /* G: 2n parameters (u, v), G = I - 2 u v^T / (v^T u): the
+                             Householder-type multipliers named with Table 7.1, read as a
+                             reflection (the printed I - u v^T / u^T v sends u to 0 and is
+                             singular); applied as rank-1 updates in O(n^2)             */
 };
 
 /* Refinement solvers for genp_refine. */
@@ -108,8 +112,11 @@ typedef struct {
     int32_t n_schur;            /* number of step pairs summed in ms_schur                   */
     double cond_g;              /* 2-norm condition number of G when it is known cheaply:
                                    circulant: max_f |DFT(c)[f]| / min_f |DFT(c)[f]| (exact, the
-                                   circulant being normal, Theorem 2.1); none: 1; dense and
-                                   Toeplitz: NaN (not computed)                              */
+                                   circulant being normal, Theorem 2.1); Householder:
+                                   (a + sqrt(a^2 - 1))^2, a = ||u|| ||v|| / |v^T u| (exact);
+                                   none: 1; dense and Toeplitz: NaN (not computed)           */
+    int32_t mult_left;          /* kind of the left multiplier H (GENP_G_NONE without one)   */
+    double cond_h;              /* the same for H                                            */
 } genp_info;
 
 /*
@@ -133,17 +140,35 @@ int genp_destroy(genp_ctx* ctx);
  * ldg ignored, copied), circulant (G = the n FP64 parameters c, ldg ignored;
  * the multiplier's spectrum is kept, and every product with G or G^T runs as
  * FFTs of length n, Theorem 2.1 -- n must be a power of two with
- * 4 <= n <= 16384, else GENP_ENOTSUP), or none (G ignored).  Also computes
- * ||A||_inf.  Resets the context to the "preconditioned" state.
- * A circulant multiplier whose spectrum has min |DFT(c)| <= n 2^-53 max |DFT(c)|,
- * or a non-finite one, is rejected with GENP_ESINGULAR (the context is then left
- * unpreconditioned): C = A G would be singular to working precision.  Draws with
- * entries +-1 hit this with probability about 2 sqrt(2 / (pi n)), whenever the
- * signs balance (DFT(c)[0] = 0) or balance over the even and odd positions
- * (DFT(c)[n/2] = 0); the caller draws new signs.
+ * 4 <= n <= 16384, else GENP_ENOTSUP), Householder (G = the 2n FP64 parameters
+ * (u, v), ldg ignored, copied; A G = A - (2 / v^T u) (A u) v^T costs two passes over A),
+ * or none (G ignored).  Also computes ||A||_inf.  Resets the context to the
+ * "preconditioned" state.
+ * A circulant multiplier whose spectrum has min |DFT(c)| <= n 2^-53 max |DFT(c)|, a
+ * Householder one with |v^T u| <= n 2^-53 ||u|| ||v||, or a non-finite one, is rejected
+ * with GENP_ESINGULAR (the context is then left unpreconditioned): C = A G would be
+ * singular to working precision.  Circulant draws with entries +-1 hit this with
+ * probability about 2 sqrt(2 / (pi n)), whenever the signs balance (DFT(c)[0] = 0) or
+ * balance over the even and odd positions (DFT(c)[n/2] = 0), and +-1 Householder draws
+ * whenever v^T u = 0; the caller draws new signs.
  */
 int genp_precondition(genp_ctx* ctx, const double* A, int64_t lda, int mult,
                       const double* G, int64_t ldg);
+
+/*
+ * C = H A G: a left multiplier H, a right multiplier G, or both (Corollary 4.1 covers the
+ * products G M and M H with Gaussian multipliers; the solve then takes C (G^{-1} x) = H b, so
+ * x = G U^{-1} L^{-1} H b, and refinement and the adjoint apply H and H^T likewise).
+ * left / H / ldh and right / G / ldg each take the kinds and layouts of genp_precondition
+ * (GENP_G_NONE: no multiplier on that side).  genp_precondition(ctx, A, lda, mult, G, ldg)
+ * is genp_precondition2(ctx, A, lda, GENP_G_NONE, NULL, 0, mult, G, ldg).
+ * A left multiplier needs the FP64 context (else GENP_ENOTSUP).  A dense H is borrowed like a
+ * dense G; with both a right multiplier and a dense or Toeplitz H the library allocates an
+ * n x n FP64 buffer (kept until genp_destroy).  Errors as genp_precondition; a singular
+ * circulant or Householder multiplier on either side gives GENP_ESINGULAR.
+ */
+int genp_precondition2(genp_ctx* ctx, const double* A, int64_t lda, int left, const double* H,
+                       int64_t ldh, int right, const double* G, int64_t ldg);
 
 /*
  * Blocked right-looking GENP of C in place (section 1.1; block Gaussian

@@ -42,7 +42,7 @@ __device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
 // of the circulant, which is normal (Theorem 2.1).  A NaN modulus makes both NaN.
 template <int MODE, bool CONJ, typename TO>
 __global__ void __launch_bounds__(CIRC_THREADS)
-circ_kernel(int n, int logN, const double* __restrict__ x, long long sx, long long bx,
+circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
             const double2* __restrict__ spec, const double2* __restrict__ tw, const double2* __restrict__ wp,
             double alpha, double beta, const double* yin, long long syi, long long byi, TO* y, long long sy,
             long long by, double2* __restrict__ spec_out) {

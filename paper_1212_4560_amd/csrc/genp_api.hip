@@ -34,6 +34,17 @@ enum { EV_PRE = 0, EV_FAC = 1, EV_SOL = 2, EV_REF = 3, EV_BWD = 4, EV_N = 5 };
 // device reduction slots (bit patterns of non-negative doubles)
 enum { R_MAXC = 0, R_MAXU = 1, R_ANORM = 2, R_COLS = 8 };   // R_COLS: 3 * 256 per-column maxima
 
+// One multiplier (right G or left H) as the library keeps it.
+struct Mult {
+    int kind = GENP_G_NONE;
+    const double* G = nullptr;   // dense: borrowed
+    int64_t ldg = 0;
+    double* p = nullptr;         // Toeplitz: the 2n - 1 parameters (owned copy)
+    double* p_rev = nullptr;     //           reversed: the parameters of the transpose
+    double2* spec = nullptr;     // circulant: spectrum X[0..n/2], then (max, min) modulus
+    double* uv = nullptr;        // Householder: u (n), v (n), then (v^T u, u^T u, v^T v)
+};
+
 }  // namespace
 
 struct genp_ctx {
@@ -48,15 +59,12 @@ struct genp_ctx {
     // borrowed / copied inputs
     const double* A = nullptr;
     int64_t lda = 0;
-    int mult = GENP_G_DENSE;
-    const double* G = nullptr;
-    int64_t ldg = 0;
-    double* p = nullptr;       // Toeplitz parameters (owned copy)
-    double* p_rev = nullptr;   // reversed: the parameters of G^T
-    // circulant multiplier: its spectrum and the FFT twiddles (n / 2 + 1, n / 4, n / 2 + 1)
-    double2* circ_spec = nullptr;
+    Mult mr, ml;               // right multiplier G and left multiplier H (C = H A G)
+    // FFT twiddles shared by circulant multipliers (n / 4 and n / 2 + 1 entries)
     double2* circ_tw = nullptr;
     double2* circ_wp = nullptr;
+    double* hw = nullptr;      // Householder: a length-n_pad work vector
+    double* w2 = nullptr;      // two-sided products with a dense or Toeplitz H: n x n copy of A G
     // right-hand-side scratch, capacity kcap columns
     int64_t kcap = 0;
     double* Z = nullptr;       // n_pad x kcap
@@ -134,6 +142,12 @@ int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_
         return GENP_OK;
     }
     if (k <= 4) {
+        if (amode == OP_T && M >= 64 && c->kcap > 0) {
+            // transposed operand: partial sums over row slices (coalesced), then their sum
+            HIPCK(launch_gemv_t_f64(M, K, k, alpha, A, lda, a_f32, X, ldx, beta, Yin, ldyi, Y, ldy, c->part,
+                                    (long long)KSPLIT_MAX * c->n_pad * c->kcap, c->stream));
+            return GENP_OK;
+        }
         HIPCK(launch_gemv_f64(M, K, k, alpha, A, lda, amode, a_f32, X, ldx, beta, Yin, ldyi, Y, ldy,
                               c->stream));
         return GENP_OK;
@@ -267,37 +281,50 @@ int lu_solve_trans_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     return GENP_OK;
 }
 
-// Y (n x k) = alpha * G Z + beta * Yin, or with G^T (trans), for the stored multiplier.
-int apply_g(genp_ctx* c, int trans, int k, double alpha, const double* Zin, int64_t ldz, double beta,
-            const double* Yin, int64_t ldyi, double* Y, int64_t ldy) {
+// Y (n x k) = alpha * M Z + beta * Yin, or with M^T (trans), for a stored multiplier M.
+int apply_mult(genp_ctx* c, const Mult& m, int trans, int k, double alpha, const double* Zin, int64_t ldz,
+               double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy) {
     const int n = (int)c->n;
-    if (c->mult == GENP_G_NONE) {
-        if (beta != 0.0 || alpha != 1.0) return GENP_ENOTSUP;
-        HIPCK(launch_copy2d(Zin, ldz, Y, ldy, n, k, c->stream));
-        return GENP_OK;
+    switch (m.kind) {
+        case GENP_G_NONE:
+            if (alpha != 1.0) return GENP_ENOTSUP;
+            if (beta == 0.0) HIPCK(launch_copy2d(Zin, ldz, Y, ldy, n, k, c->stream));
+            else if (beta == 1.0 && Yin == Y) HIPCK(launch_axpy2d(1.0, Zin, ldz, Y, ldy, n, k, c->stream));
+            else return GENP_ENOTSUP;
+            return GENP_OK;
+        case GENP_G_TOEPLITZ:
+            return skinny(c, n, n, k, alpha, trans ? m.p_rev : m.p, n, OP_TOEP, 0, Zin, ldz, beta, Yin, ldyi, Y, ldy);
+        case GENP_G_CIRCULANT:
+            // the k columns as k vectors: element t of column b at Z[t * ldz + b]
+            HIPCK(launch_circ_apply(n, k, trans, Zin, ldz, 1, m.spec, c->circ_tw, c->circ_wp, alpha, beta, Yin, ldyi,
+                                    1, Y, 0, ldy, 1, c->stream));
+            return GENP_OK;
+        case GENP_G_HOUSEHOLDER: {
+            // M Z = Z - (2 / v^T u) u (v^T Z);  M^T Z = Z - (2 / v^T u) v (u^T Z)
+            const double* u = m.uv;
+            const double* v = m.uv + n;
+            const double* a = trans ? v : u;
+            const double* b = trans ? u : v;
+            HIPCK(launch_gemv_t_f64(k, n, 1, 1.0, Zin, ldz, 0, b, 1, 0.0, nullptr, 0, c->hw, 1, c->part,
+                                    (long long)KSPLIT_MAX * c->n_pad * c->kcap, c->stream));
+            HIPCK(launch_rank1(n, k, alpha, Zin, ldz, a, c->hw, m.uv + 2 * n, 2.0, beta, Yin, ldyi, Y, 0, ldy,
+                               c->stream));
+            return GENP_OK;
+        }
+        default:
+            return skinny(c, n, n, k, alpha, m.G, m.ldg, trans ? OP_T : OP_N, 0, Zin, ldz, beta, Yin, ldyi, Y, ldy);
     }
-    if (c->mult == GENP_G_TOEPLITZ)
-        return skinny(c, n, n, k, alpha, trans ? c->p_rev : c->p, n, OP_TOEP, 0, Zin, ldz, beta, Yin, ldyi,
-                      Y, ldy);
-    if (c->mult == GENP_G_CIRCULANT) {
-        // the k columns as k vectors: element t of column b at Z[t * ldz + b]
-        HIPCK(launch_circ_apply(n, k, trans, Zin, ldz, 1, c->circ_spec, c->circ_tw, c->circ_wp, alpha, beta, Yin,
-                                ldyi, 1, Y, 0, ldy, 1, c->stream));
-        return GENP_OK;
-    }
-    return skinny(c, n, n, k, alpha, c->G, c->ldg, trans ? OP_T : OP_N, 0, Zin, ldz, beta, Yin, ldyi, Y,
-                  ldy);
 }
 
-// X (n x k) = G U^{-1} L^{-1} Bin, using Z as workspace (n_pad x k, ldz = k).
+// X (n x k) = G U^{-1} L^{-1} H Bin, using Z as workspace (n_pad x k, ldz = k).
 int solve_into(genp_ctx* c, const double* Bin, int64_t ldb, int k, double* X, int64_t ldx) {
     double* Z = c->Z;
     const int64_t ldz = k;
-    HIPCK(launch_copy2d(Bin, ldb, Z, ldz, (int)c->n, k, c->stream));
+    CK(apply_mult(c, c->ml, 0, k, 1.0, Bin, ldb, 0.0, nullptr, 0, Z, ldz));   // H B (a copy without H)
     if (c->n_pad > c->n)
         HIPCK(launch_fill2d(0.0, Z + c->n * ldz, ldz, (int)(c->n_pad - c->n), k, c->stream));
     CK(lu_solve_inplace(c, Z, ldz, k));
-    return apply_g(c, 0, k, 1.0, Z, ldz, 0.0, nullptr, 0, X, ldx);
+    return apply_mult(c, c->mr, 0, k, 1.0, Z, ldz, 0.0, nullptr, 0, X, ldx);
 }
 
 // eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf), host result.
@@ -445,6 +472,173 @@ int check_ctx(const genp_ctx* c) {
     return (hipSetDevice(c->device) == hipSuccess) ? GENP_OK : GENP_EDEVICE;
 }
 
+// Record a multiplier: dense G is borrowed; Toeplitz parameters are copied (and reversed for the
+// transpose); a circulant keeps its spectrum; Householder parameters are copied with their dots.
+int set_mult(genp_ctx* c, Mult& m, int kind, const double* G, int64_t ldg) {
+    const int64_t n = c->n;
+    m.kind = kind;
+    m.G = (kind == GENP_G_DENSE) ? G : nullptr;
+    m.ldg = ldg;
+    if (kind == GENP_G_TOEPLITZ) {
+        if (!m.p) {
+            if (hipMalloc(&m.p, (2 * n - 1) * sizeof(double)) != hipSuccess ||
+                hipMalloc(&m.p_rev, (2 * n - 1) * sizeof(double)) != hipSuccess)
+                return GENP_ENOMEM;
+        }
+        HIPCK(hipMemcpyAsync(m.p, G, (2 * n - 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        // T^T(i, k) = T(k, i) = p[k - i + n - 1] = p_rev[i - k + n - 1] with p_rev[t] = p[2n - 2 - t]
+        HIPCK(launch_copy2d(G, 1, m.p_rev + (2 * n - 2), -1, (int)(2 * n - 1), 1, c->stream));
+    } else if (kind == GENP_G_CIRCULANT) {
+        const int64_t N = n / 2;
+        if (!c->circ_tw) {
+            // twiddles of the length-N complex FFT and of the real-spectrum packing, in FP64 on the host
+            std::vector<double2> tw(N / 2), wp(N + 1);
+            const double pi = 3.14159265358979323846264338327950288;
+            for (int64_t k = 0; k < N / 2; ++k)
+                tw[k] = make_double2(cos(2.0 * pi * (double)k / (double)N), -sin(2.0 * pi * (double)k / (double)N));
+            for (int64_t f = 0; f <= N; ++f)
+                wp[f] = make_double2(cos(2.0 * pi * (double)f / (double)n), -sin(2.0 * pi * (double)f / (double)n));
+            if (hipMalloc(&c->circ_tw, std::max<int64_t>(1, N / 2) * sizeof(double2)) != hipSuccess ||
+                hipMalloc(&c->circ_wp, (N + 1) * sizeof(double2)) != hipSuccess)
+                return GENP_ENOMEM;
+            HIPCK(hipMemcpy(c->circ_tw, tw.data(), (N / 2) * sizeof(double2), hipMemcpyHostToDevice));
+            HIPCK(hipMemcpy(c->circ_wp, wp.data(), (N + 1) * sizeof(double2), hipMemcpyHostToDevice));
+        }
+        if (!m.spec && hipMalloc(&m.spec, (N + 2) * sizeof(double2)) != hipSuccess) return GENP_ENOMEM;
+        HIPCK(launch_circ_spectrum((int)n, G, c->circ_tw, c->circ_wp, m.spec, c->stream));
+    } else if (kind == GENP_G_HOUSEHOLDER) {
+        if (!m.uv && hipMalloc(&m.uv, (2 * n + 3) * sizeof(double)) != hipSuccess) return GENP_ENOMEM;
+        if (!c->hw && hipMalloc(&c->hw, std::max<int64_t>(c->n_pad, 256) * sizeof(double)) != hipSuccess)
+            return GENP_ENOMEM;
+        HIPCK(hipMemcpyAsync(m.uv, G, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCK(launch_dot3((int)n, m.uv, m.uv + n, m.uv + 2 * n, c->stream));
+    }
+    return GENP_OK;
+}
+
+// C = A G (or C = A without a right multiplier), in the working precision.
+int right_product(genp_ctx* c, const double* A, int64_t lda) {
+    const int64_t n = c->n;
+    const Mult& m = c->mr;
+    const int lp = c->prec != GENP_F64;
+    if (m.kind == GENP_G_NONE) {
+        if (!lp) HIPCK(launch_copy2d(A, lda, (double*)c->C, c->ldc, (int)n, (int)n, c->stream));
+        else HIPCK(launch_convert_f64_f32(A, lda, (float*)c->C, c->ldc, (int)n, (int)n, c->stream));
+        return GENP_OK;
+    }
+    if (m.kind == GENP_G_CIRCULANT) {
+        // each row of A correlated with c, by FFT
+        HIPCK(launch_circ_apply((int)n, (int)n, 1, A, 1, lda, m.spec, c->circ_tw, c->circ_wp, 1.0, 0.0, nullptr, 0, 0,
+                                c->C, lp, 1, c->ldc, c->stream));
+        return GENP_OK;
+    }
+    if (m.kind == GENP_G_HOUSEHOLDER) {
+        // A G = A - (2 / v^T u) (A u) v^T: one product with A, one rank-1 pass
+        const double* u = m.uv;
+        const double* v = m.uv + n;
+        HIPCK(launch_gemv_f64((int)n, (int)n, 1, 1.0, A, lda, OP_N, 0, u, 1, 0.0, nullptr, 0, c->hw, 1, c->stream));
+        HIPCK(launch_rank1((int)n, (int)n, 1.0, A, lda, c->hw, v, m.uv + 2 * n, 2.0, 0.0, nullptr, 0, c->C, lp, c->ldc,
+                           c->stream));
+        return GENP_OK;
+    }
+    if (!lp) {
+        GemmF64Args g{};
+        g.M = g.N = g.K = (int)n;
+        g.A = A;
+        g.lda = lda;
+        g.amode = OP_N;
+        if (m.kind == GENP_G_DENSE) {
+            g.B = m.G;
+            g.ldb = m.ldg;
+            g.bmode = OP_N;
+        } else {
+            g.B = m.p;
+            g.ldb = n;
+            g.bmode = OP_TOEP;
+            g.group_m = 1;
+        }
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        g.D = (double*)c->C;
+        g.ldd = c->ldc;
+        g.ksplit = 1;
+        HIPCK(launch_gemm_f64(g, 0, c->stream));
+        return GENP_OK;
+    }
+    // precision form: operands rounded FP64 -> FP32 (-> BF16) in the loader, FP32 accumulation
+    GemmLpArgs g{};
+    g.M = g.N = g.K = (int)n;
+    g.A = A;
+    g.lda = lda;
+    g.amode = OP_N;
+    g.a_f64 = 1;
+    g.B = (m.kind == GENP_G_DENSE) ? (const void*)m.G : (const void*)m.p;
+    g.ldb = (m.kind == GENP_G_DENSE) ? m.ldg : n;
+    g.bmode = (m.kind == GENP_G_DENSE) ? OP_N : OP_TOEP;
+    g.b_f64 = 1;
+    g.alpha = 1.f;
+    g.beta = 0.f;
+    g.D = (float*)c->C;
+    g.ldd = c->ldc;
+    g.bf16 = c->prec == GENP_BF16;
+    HIPCK(launch_gemm_lp(g, 0, c->stream));
+    return GENP_OK;
+}
+
+// C := H C (FP64), C holding A G; from_a: there is no right multiplier, so C holds a copy of A
+// and a product with a dense or Toeplitz H can read A itself.
+int left_product(genp_ctx* c, const double* A, int64_t lda, bool from_a) {
+    const int64_t n = c->n;
+    const Mult& m = c->ml;
+    double* C = (double*)c->C;
+    if (m.kind == GENP_G_CIRCULANT) {
+        // each column convolved with c, by FFT, in place (a column is read whole before it is written)
+        HIPCK(launch_circ_apply((int)n, (int)n, 0, C, c->ldc, 1, m.spec, c->circ_tw, c->circ_wp, 1.0, 0.0, nullptr, 0,
+                                0, C, 0, c->ldc, 1, c->stream));
+        return GENP_OK;
+    }
+    if (m.kind == GENP_G_HOUSEHOLDER) {
+        // H C = C - (2 / v^T u) u (C^T v)^T
+        const double* u = m.uv;
+        const double* v = m.uv + n;
+        HIPCK(launch_gemv_t_f64((int)n, (int)n, 1, 1.0, C, c->ldc, 0, v, 1, 0.0, nullptr, 0, c->hw, 1, c->part,
+                                (long long)KSPLIT_MAX * c->n_pad * c->kcap, c->stream));
+        HIPCK(launch_rank1((int)n, (int)n, 1.0, C, c->ldc, u, c->hw, m.uv + 2 * n, 2.0, 0.0, nullptr, 0, C, 0, c->ldc,
+                           c->stream));
+        return GENP_OK;
+    }
+    // dense or Toeplitz H: an out-of-place product
+    const double* Bsrc = A;
+    int64_t ldb = lda;
+    if (!from_a) {
+        if (!c->w2 && hipMalloc(&c->w2, (size_t)n * n * sizeof(double)) != hipSuccess) return GENP_ENOMEM;
+        HIPCK(launch_copy2d(C, c->ldc, c->w2, n, (int)n, (int)n, c->stream));
+        Bsrc = c->w2;
+        ldb = n;
+    }
+    GemmF64Args g{};
+    g.M = g.N = g.K = (int)n;
+    if (m.kind == GENP_G_DENSE) {
+        g.A = m.G;
+        g.lda = m.ldg;
+        g.amode = OP_N;
+    } else {
+        g.A = m.p;   // H(i, k) = p[i - k + n - 1]: the Toeplitz order travels in lda
+        g.lda = n;
+        g.amode = OP_TOEP;
+    }
+    g.B = Bsrc;
+    g.ldb = ldb;
+    g.bmode = OP_N;
+    g.alpha = 1.0;
+    g.beta = 0.0;
+    g.D = C;
+    g.ldd = c->ldc;
+    g.ksplit = 1;
+    HIPCK(launch_gemm_f64(g, 0, c->stream));
+    return GENP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -529,9 +723,14 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->stats);
     hipFree(c->red);
     hipFree(c->tsync);
-    hipFree(c->p);
-    hipFree(c->p_rev);
-    hipFree(c->circ_spec);
+    for (Mult* m : {&c->mr, &c->ml}) {
+        hipFree(m->p);
+        hipFree(m->p_rev);
+        hipFree(m->spec);
+        hipFree(m->uv);
+    }
+    hipFree(c->hw);
+    hipFree(c->w2);
     hipFree(c->circ_tw);
     hipFree(c->circ_wp);
     hipFree(c->Z);
@@ -556,131 +755,89 @@ int genp_destroy(genp_ctx* c) {
 }
 
 int genp_precondition(genp_ctx* c, const double* A, int64_t lda, int mult, const double* G, int64_t ldg) {
+    return genp_precondition2(c, A, lda, GENP_G_NONE, nullptr, 0, mult, G, ldg);
+}
+
+int genp_precondition2(genp_ctx* c, const double* A, int64_t lda, int left, const double* H, int64_t ldh, int right,
+                       const double* G, int64_t ldg) {
     CK(check_ctx(c));
     const int64_t n = c->n;
     if (!A || lda < n) return GENP_EINVAL;
-    if (mult != GENP_G_DENSE && mult != GENP_G_TOEPLITZ && mult != GENP_G_NONE && mult != GENP_G_CIRCULANT)
-        return GENP_EINVAL;
-    if (mult == GENP_G_CIRCULANT && !circ_size_ok(n)) return GENP_ENOTSUP;
-    if (mult != GENP_G_NONE && !G) return GENP_EINVAL;
-    if (mult == GENP_G_DENSE && ldg < n) return GENP_EINVAL;
+    for (int kind : {left, right})
+        if (kind < GENP_G_DENSE || kind > GENP_G_HOUSEHOLDER) return GENP_EINVAL;
+    if ((right != GENP_G_NONE && !G) || (left != GENP_G_NONE && !H)) return GENP_EINVAL;
+    if ((right == GENP_G_DENSE && ldg < n) || (left == GENP_G_DENSE && ldh < n)) return GENP_EINVAL;
+    if ((right == GENP_G_CIRCULANT || left == GENP_G_CIRCULANT) && !circ_size_ok(n)) return GENP_ENOTSUP;
+    if (left != GENP_G_NONE && c->prec != GENP_F64) return GENP_ENOTSUP;
     c->state = ST_CREATED;
     c->A = A;
     c->lda = lda;
-    c->mult = mult;
-    c->G = (mult == GENP_G_DENSE) ? G : nullptr;
-    c->ldg = ldg;
+    if (right == GENP_G_HOUSEHOLDER || left == GENP_G_HOUSEHOLDER) CK(ensure_rhs(c, 4));
     ev_begin(c, EV_PRE);
-    if (mult == GENP_G_TOEPLITZ) {
-        if (!c->p) {
-            if (hipMalloc(&c->p, (2 * n - 1) * sizeof(double)) != hipSuccess ||
-                hipMalloc(&c->p_rev, (2 * n - 1) * sizeof(double)) != hipSuccess)
-                return GENP_ENOMEM;
-        }
-        HIPCK(hipMemcpyAsync(c->p, G, (2 * n - 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        // G^T(i, k) = G(k, i) = p[k - i + n - 1] = p_rev[i - k + n - 1] with p_rev[t] = p[2n - 2 - t]
-        HIPCK(launch_copy2d(G, 1, c->p_rev + (2 * n - 2), -1, (int)(2 * n - 1), 1, c->stream));
-    }
-    if (mult == GENP_G_CIRCULANT) {
-        const int64_t N = n / 2;
-        if (!c->circ_spec) {
-            // twiddles of the length-N complex FFT and of the real-spectrum packing, in FP64 on the host
-            std::vector<double2> tw(N / 2), wp(N + 1);
-            const double pi = 3.14159265358979323846264338327950288;
-            for (int64_t k = 0; k < N / 2; ++k)
-                tw[k] = make_double2(cos(2.0 * pi * (double)k / (double)N), -sin(2.0 * pi * (double)k / (double)N));
-            for (int64_t f = 0; f <= N; ++f)
-                wp[f] = make_double2(cos(2.0 * pi * (double)f / (double)n), -sin(2.0 * pi * (double)f / (double)n));
-            if (hipMalloc(&c->circ_spec, (N + 2) * sizeof(double2)) != hipSuccess ||
-                hipMalloc(&c->circ_tw, std::max<int64_t>(1, N / 2) * sizeof(double2)) != hipSuccess ||
-                hipMalloc(&c->circ_wp, (N + 1) * sizeof(double2)) != hipSuccess)
-                return GENP_ENOMEM;
-            HIPCK(hipMemcpy(c->circ_tw, tw.data(), (N / 2) * sizeof(double2), hipMemcpyHostToDevice));
-            HIPCK(hipMemcpy(c->circ_wp, wp.data(), (N + 1) * sizeof(double2), hipMemcpyHostToDevice));
-        }
-        HIPCK(launch_circ_spectrum((int)n, G, c->circ_tw, c->circ_wp, c->circ_spec, c->stream));
-    }
+    CK(set_mult(c, c->mr, right, G, ldg));
+    CK(set_mult(c, c->ml, left, H, ldh));
     HIPCK(hipMemsetAsync(c->red, 0, sizeof(unsigned long long) * R_COLS, c->stream));
-    if (mult == GENP_G_CIRCULANT) {
-        // C = A G: each row of A correlated with c, by FFT
-        HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
-        HIPCK(launch_circ_apply((int)n, (int)n, 1, A, 1, lda, c->circ_spec, c->circ_tw, c->circ_wp, 1.0, 0.0,
-                                nullptr, 0, 0, c->C, c->prec != GENP_F64, 1, c->ldc, c->stream));
-        HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
-    } else if (mult == GENP_G_NONE) {
-        if (c->prec == GENP_F64) HIPCK(launch_copy2d(A, lda, (double*)c->C, c->ldc, (int)n, (int)n, c->stream));
-        else HIPCK(launch_convert_f64_f32(A, lda, (float*)c->C, c->ldc, (int)n, (int)n, c->stream));
-    } else if (c->prec == GENP_F64) {
-        GemmF64Args g{};
-        g.M = g.N = g.K = (int)n;
-        g.A = A;
-        g.lda = lda;
-        g.amode = OP_N;
-        if (mult == GENP_G_DENSE) {
-            g.B = G;
-            g.ldb = ldg;
-            g.bmode = OP_N;
-        } else {
-            g.B = c->p;
-            g.ldb = n;
-            g.bmode = OP_TOEP;
-            g.group_m = 1;
-        }
-        g.alpha = 1.0;
-        g.beta = 0.0;
-        g.D = (double*)c->C;
-        g.ldd = c->ldc;
-        g.ksplit = 1;
-        HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
-        HIPCK(launch_gemm_f64(g, 0, c->stream));
-        HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
-    } else {
-        // precision form: operands rounded FP64 -> FP32 (-> BF16) in the loader, FP32 accumulation
-        GemmLpArgs g{};
-        g.M = g.N = g.K = (int)n;
-        g.A = A;
-        g.lda = lda;
-        g.amode = OP_N;
-        g.a_f64 = 1;
-        g.B = (mult == GENP_G_DENSE) ? (const void*)G : (const void*)c->p;
-        g.ldb = (mult == GENP_G_DENSE) ? ldg : n;
-        g.bmode = (mult == GENP_G_DENSE) ? OP_N : OP_TOEP;
-        g.b_f64 = 1;
-        g.alpha = 1.f;
-        g.beta = 0.f;
-        g.D = (float*)c->C;
-        g.ldd = c->ldc;
-        g.bf16 = c->prec == GENP_BF16;
-        HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
-        HIPCK(launch_gemm_lp(g, 0, c->stream));
-        HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
-    }
+    HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
+    CK(right_product(c, A, lda));
+    if (left != GENP_G_NONE) CK(left_product(c, A, lda, right == GENP_G_NONE));
+    HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
     HIPCK(launch_pad_identity(c->prec, c->C, c->ldc, (int)n, (int)c->n_pad, c->stream));
     HIPCK(launch_max_abs(c->prec, c->C, c->ldc, (int)n, (int)n, 0, c->red + R_MAXC, c->stream));
     HIPCK(launch_row_abs_sum_max(A, lda, (int)n, c->red + R_ANORM, c->stream));
     ev_end(c, EV_PRE);
     unsigned long long h[3];
-    double2 sv = make_double2(0.0, 0.0);   // circulant: (max, min) modulus of the spectrum
+    double2 sv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};   // circulant: (max, min) |spectrum|
+    double dots[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};               // Householder: v^T u, u^T u, v^T v
     HIPCK(hipMemcpyAsync(h, c->red, sizeof h, hipMemcpyDeviceToHost, c->stream));
-    if (mult == GENP_G_CIRCULANT)
-        HIPCK(hipMemcpyAsync(&sv, c->circ_spec + n / 2 + 1, sizeof sv, hipMemcpyDeviceToHost, c->stream));
+    const Mult* ms[2] = {&c->mr, &c->ml};
+    for (int q = 0; q < 2; ++q) {
+        if (ms[q]->kind == GENP_G_CIRCULANT)
+            HIPCK(hipMemcpyAsync(&sv[q], ms[q]->spec + n / 2 + 1, sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+        if (ms[q]->kind == GENP_G_HOUSEHOLDER)
+            HIPCK(hipMemcpyAsync(dots[q], ms[q]->uv + 2 * n, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
     HIPCK(hipStreamSynchronize(c->stream));
     float ms_ag = 0.f;
-    c->info.ms_ag = (mult != GENP_G_NONE && hipEventElapsedTime(&ms_ag, c->ev_ag[0], c->ev_ag[1]) == hipSuccess)
-                        ? ms_ag : 0.0;
+    c->info.ms_ag = (hipEventElapsedTime(&ms_ag, c->ev_ag[0], c->ev_ag[1]) == hipSuccess) ? ms_ag : 0.0;
     c->anorm = bits_to_double(h[R_ANORM]);
     c->info.max_abs_c = bits_to_double(h[R_MAXC]);
     c->info.anorm_inf = c->anorm;
-    c->info.mult = mult;
-    c->info.cond_g = std::numeric_limits<double>::quiet_NaN();
-    if (mult == GENP_G_NONE) c->info.cond_g = 1.0;
-    if (mult == GENP_G_CIRCULANT) {
-        // the circulant is normal: its singular values are the moduli of its spectrum (Theorem 2.1)
-        c->info.cond_g = (sv.y > 0.0) ? sv.x / sv.y : std::numeric_limits<double>::infinity();
-        if (sv.x != sv.x || sv.y != sv.y) c->info.cond_g = std::numeric_limits<double>::quiet_NaN();
-        // singular to working precision (or non-finite): C = A G would be singular too
-        if (!(sv.y > (double)n * 0x1p-53 * sv.x) || !std::isfinite(sv.x)) return GENP_ESINGULAR;
+    c->info.mult = right;
+    c->info.mult_left = left;
+    bool singular = false;
+    double conds[2];
+    for (int q = 0; q < 2; ++q) {
+        double& k = conds[q];
+        k = std::numeric_limits<double>::quiet_NaN();
+        switch (ms[q]->kind) {
+            case GENP_G_NONE: k = 1.0; break;
+            case GENP_G_CIRCULANT: {
+                // the circulant is normal: its singular values are the moduli of its spectrum (Theorem 2.1)
+                const double mx = sv[q].x, mn = sv[q].y;
+                k = (mn > 0.0) ? mx / mn : std::numeric_limits<double>::infinity();
+                if (mx != mx || mn != mn) k = std::numeric_limits<double>::quiet_NaN();
+                if (!(mn > (double)n * 0x1p-53 * mx) || !std::isfinite(mx)) singular = true;
+                break;
+            }
+            case GENP_G_HOUSEHOLDER: {
+                // singular values 1 and a +- sqrt(a^2 - 1), a = ||u|| ||v|| / |v^T u|
+                const double d = fabs(dots[q][0]), nn = sqrt(dots[q][1]) * sqrt(dots[q][2]);
+                if (!(d > (double)n * 0x1p-53 * nn) || !std::isfinite(nn)) {
+                    singular = true;
+                    k = std::numeric_limits<double>::infinity();
+                } else {
+                    const double a = std::max(1.0, nn / d);
+                    k = (a + sqrt(a * a - 1.0)) * (a + sqrt(a * a - 1.0));
+                }
+                break;
+            }
+            default: break;
+        }
     }
+    c->info.cond_g = conds[0];
+    c->info.cond_h = conds[1];
+    // a multiplier singular to working precision makes C singular too
+    if (singular) return GENP_ESINGULAR;
     c->state = ST_PRECOND;
     return GENP_OK;
 }
@@ -1004,7 +1161,7 @@ int genp_solve_backward(genp_ctx* c, const double* W, int64_t ldw, const double*
     CK(ensure_rhs(c, nrhs));
     const int k = (int)nrhs, n = (int)c->n;
     ev_begin(c, EV_BWD);
-    // dB = L^{-T} U^{-T} G^T W ; then refinement against A^T
+    // dB = H^T L^{-T} U^{-T} G^T W ; then refinement against A^T
     for (int step = 0; step <= refine_iters; ++step) {
         const double* rhs = W;
         int64_t ldr = ldw;
@@ -1016,10 +1173,10 @@ int genp_solve_backward(genp_ctx* c, const double* W, int64_t ldw, const double*
         }
         // Z = G^T rhs (rows n..n_pad zero)
         if (c->n_pad > c->n) HIPCK(launch_fill2d(0.0, c->Z + (int64_t)n * k, k, (int)(c->n_pad - n), k, c->stream));
-        CK(apply_g(c, 1, k, 1.0, rhs, ldr, 0.0, nullptr, 0, c->Z, k));
+        CK(apply_mult(c, c->mr, 1, k, 1.0, rhs, ldr, 0.0, nullptr, 0, c->Z, k));
         CK(lu_solve_trans_inplace(c, c->Z, k, k));
-        if (step == 0) HIPCK(launch_copy2d(c->Z, k, dB, lddb, n, k, c->stream));
-        else HIPCK(launch_axpy2d(1.0, c->Z, k, dB, lddb, n, k, c->stream));
+        // dB (+)= H^T Z
+        CK(apply_mult(c, c->ml, 1, k, 1.0, c->Z, k, step == 0 ? 0.0 : 1.0, dB, lddb, dB, lddb));
     }
     if (dA) {
         // dA = -dB X^T

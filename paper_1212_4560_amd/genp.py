@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgenp.so")
 
 F64, F32, BF16 = 0, 1, 2
-G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT = 0, 1, 2, 3
+G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT, G_HOUSEHOLDER = 0, 1, 2, 3, 4
 SOLVER_LUIR, SOLVER_GMRES = 0, 1
 OK, BREAKDOWN, ENOCONV = 0, 1, 2
 EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP, ESINGULAR = -1, -2, -3, -4, -5, -6
@@ -33,7 +33,7 @@ PRECS = {"f64": F64, "f32": F32, "bf16": BF16}
 SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 
 # the entry points declared in include/genp.h
-EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_factor", "genp_solve",
+EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",
            "genp_refine", "genp_solve_backward", "genp_get_info", "genp_copy_work", "genp_strerror")
 
 
@@ -54,6 +54,7 @@ class GenpInfo(ctypes.Structure):
         ("ms_ag", ctypes.c_double), ("ms_schur", ctypes.c_double), ("ms_panel", ctypes.c_double),
         ("n_schur", ctypes.c_int32),
         ("cond_g", ctypes.c_double),
+        ("mult_left", ctypes.c_int32), ("cond_h", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.genp_create.argtypes = [ctypes.POINTER(vp), i64, i32, i32, vp]
     L.genp_destroy.argtypes = [vp]
     L.genp_precondition.argtypes = [vp, vp, i64, i32, vp, i64]
+    L.genp_precondition2.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64]
     L.genp_factor.argtypes = [vp, dbl, ctypes.POINTER(i64)]
     L.genp_solve.argtypes = [vp, vp, i64, i64, vp, i64]
     L.genp_refine.argtypes = [vp, vp, i64, i64, vp, i64, i32, dbl, i32, ctypes.POINTER(dbl)]
@@ -155,26 +157,46 @@ class Solver:
         except Exception:
             pass
 
-    def precondition(self, A, G=None, p=None, c=None):
-        """C = A G (dense G, Toeplitz with parameters p, circulant with first column c,
-        or no multiplier)."""
+    def _mult(self, kind, t):
+        """(kind code, pointer, leading dimension) of a multiplier given as (kind name, tensor)."""
+        n = self.n
+        if kind is None:
+            return G_NONE, 0, n
+        if kind == "dense":
+            g, ld = _mat(t, "G", n, n)
+            return G_DENSE, g, ld
+        shapes = {"toeplitz": (G_TOEPLITZ, 2 * n - 1), "circulant": (G_CIRCULANT, n),
+                  "householder": (G_HOUSEHOLDER, 2 * n)}
+        if kind not in shapes:
+            raise ValueError(f"unknown multiplier kind {kind!r}")
+        code, length = shapes[kind]
+        g, _ = _mat(t, kind, length)
+        return code, g, n
+
+    def precondition(self, A, G=None, p=None, c=None, uv=None, left=None):
+        """C = H A G.  The right multiplier G: dense G, Toeplitz with parameters p, circulant
+        with first column c, Householder with parameters uv = (u, v), or none.  The left
+        multiplier H: left = (kind, tensor) with kind "dense", "toeplitz", "circulant" or
+        "householder" (FP64 contexts only), or None."""
         n = self.n
         a, lda = _mat(A, "A", n, n)
         if G is not None:
-            g, ldg = _mat(G, "G", n, n)
-            mult = G_DENSE
+            right = ("dense", G)
         elif p is not None:
-            g, ldg = _mat(p, "p", 2 * n - 1)
-            mult = G_TOEPLITZ
-            ldg = n
+            right = ("toeplitz", p)
         elif c is not None:
-            g, ldg = _mat(c, "c", n)
-            mult = G_CIRCULANT
-            ldg = n
+            right = ("circulant", c)
+        elif uv is not None:
+            right = ("householder", uv)
         else:
-            g, ldg, mult = 0, n, G_NONE
-        _check(load().genp_precondition(self._h, a, lda, mult, g, ldg), "genp_precondition")
-        self._keep = (A, G, p, c)
+            right = (None, None)
+        rk, g, ldg = self._mult(*right)
+        lk, h, ldh = self._mult(*(left if left is not None else (None, None)))
+        if lk == G_NONE:
+            _check(load().genp_precondition(self._h, a, lda, rk, g, ldg), "genp_precondition")
+        else:
+            _check(load().genp_precondition2(self._h, a, lda, lk, h, ldh, rk, g, ldg), "genp_precondition2")
+        self._keep = (A, right[1], left)
         return self
 
     def factor(self, pivot_tol: float = 0.0) -> int:
@@ -235,14 +257,15 @@ class Solver:
 
 
 def solve(A, B, G=None, p=None, prec: str = "f64", nb: int = 256, refine: int = 2,
-          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir", c=None):
-    """The whole path: C = A G, GENP, substitutions, X = G Y, refinement.
-    The multiplier: dense G, Toeplitz parameters p, or circulant first column c.
+          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir", c=None, uv=None, left=None):
+    """The whole path: C = H A G, GENP, substitutions, X = G Y, refinement.
+    The right multiplier: dense G, Toeplitz parameters p, circulant first column c or
+    Householder parameters uv; the left one: left = (kind, tensor) or None.
 
     Returns (X, info dict, solver object).  Raises GenpError on breakdown.
     """
     s = Solver(A.shape[0], prec, nb)
-    s.precondition(A, G=G, p=p, c=c)
+    s.precondition(A, G=G, p=p, c=c, uv=uv, left=left)
     bk = s.factor(pivot_tol)
     if bk:
         raise GenpError(BREAKDOWN, f"genp_factor (column {bk})")
@@ -263,8 +286,9 @@ def _autograd_function():
         """
 
         @staticmethod
-        def forward(ctx, A, B, G=None, p=None, prec="f64", nb=256, refine=2, refine_bwd=1, c=None):
-            X, _, s = solve(A.detach(), B.detach(), G=G, p=p, prec=prec, nb=nb, refine=refine, c=c)
+        def forward(ctx, A, B, G=None, p=None, prec="f64", nb=256, refine=2, refine_bwd=1, c=None, uv=None,
+                    left=None):
+            X, _, s = solve(A.detach(), B.detach(), G=G, p=p, prec=prec, nb=nb, refine=refine, c=c, uv=uv, left=left)
             ctx.solver = s
             ctx.refine_bwd = refine_bwd
             ctx.save_for_backward(X)
@@ -275,7 +299,7 @@ def _autograd_function():
             (X,) = ctx.saved_tensors
             dB, dA = ctx.solver.solve_backward(gX.contiguous(), X, want_dA=ctx.needs_input_grad[0],
                                                refine_iters=ctx.refine_bwd)
-            return dA, dB, None, None, None, None, None, None, None
+            return dA, dB, None, None, None, None, None, None, None, None, None
 
     return GenpSolve
 

@@ -233,6 +233,8 @@ NAMED = {
     # the benchmark's A with a Gaussian circulant multiplier (n parameters), applied by FFT
     "c3c_n16384_haar1e6_circulant": dict(kind="haar_logspaced", n=16384, smax=1e6,
                                          mult=MULT_CIRCULANT, nrhs=1, seed=3),
+    "c3h_n16384_haar1e6_householder": dict(kind="haar_logspaced", n=16384, smax=1e6,
+                                           mult=MULT_HOUSEHOLDER, nrhs=1, seed=3),
 }
 
 

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "genp.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(genp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(genp_[a-z_0-9]+)\s*\(", src)))
 
 
 def _lib():
@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared():
         assert hasattr(L, name), name
     nm = os.popen(f"nm -D --defined-only {genp.LIB_PATH}").read()
-    exported = set(re.findall(r" T (genp_[a-z_]+)", nm))
+    exported = set(re.findall(r" T (genp_[a-z_0-9]+)", nm))
     assert set(_declared()) <= exported
 
 
