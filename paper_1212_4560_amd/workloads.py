@@ -136,6 +136,26 @@ def cs_illcond_lead(n: int, seed: int = 0, nrhs: int = 1, smallest_cos: float = 
     return Workload("cs_illcond_lead", n, seed, np.ascontiguousarray(A), B, MULT_CIRCULANT_PM1, p=c)
 
 
+def svd_head_matrix(n: int, q: int, seed: int = 0, tail: float = 1e-10, mult: str = MULT_DENSE,
+                    rho_plus: Optional[int] = None):
+    """Table 7.2's matrices: A = S diag(sigma) T^T with Haar orthogonal S, T (positive-R QR of
+    Gaussian matrices), sigma_j = 1/j for j <= q and `tail` beyond, so ||A||_2 = 1 and
+    kappa(A) = 1 / tail.  Returns (A, S, sigma, T, G) with G the m x rho_+ multiplier
+    (Gaussian, or the m + rho_+ - 1 Toeplitz parameters for mult = MULT_TOEPLITZ)."""
+    g = np.random.default_rng(seed)
+    S = _q_positive_r_numpy(g.standard_normal((n, n)))
+    T = _q_positive_r_numpy(g.standard_normal((n, n)))
+    sig = np.full(n, tail)
+    sig[:q] = 1.0 / np.arange(1, q + 1)
+    A = np.ascontiguousarray((S * sig[None, :]) @ T.T)
+    k = q if rho_plus is None else rho_plus
+    if mult == MULT_TOEPLITZ:
+        G = g.standard_normal(n + k - 1)
+    else:
+        G = g.standard_normal((n, k))
+    return A, S, sig, T, G
+
+
 def rank_deficient_lead(n: int = 256, seed: int = 1, nrhs: int = 1,
                         lead: int = 8, rank: int = 4) -> Workload:
     """A ~ N(0,1) with a rank-`rank` leading lead x lead block; dense G."""
