@@ -152,6 +152,34 @@ def structured_comparison(args, n: int, f64_ms: float, kind: str) -> dict:
     return res
 
 
+def lowrank_measure(args) -> dict:
+    """Randomized low-rank approximation (Proto-Algorithm 5.1) at m = n = 16384, rho_+ = 32, on
+    A = X Y^T + E of numerical rank 16: time per call, stages, rank, residual, and the HBM
+    roofline of the sketch A^T G (one pass over A: 8 m n bytes)."""
+    import torch
+    from paper_1212_4560_amd import genp, workloads as wl
+    n, q, k = 16384, 16, 32
+    A, G = wl.lowrank_plus_noise(n, n, q, k, device="cuda")
+    torch.cuda.synchronize()
+    genp.lowrank(A, k, G=G)          # warm-up
+    infos = [genp.lowrank(A, k, G=G)["info"] for _ in range(max(1, args.steps))]
+    best = min(infos, key=lambda i: i["ms_total"])
+    r = genp.lowrank(A, k, G=G)
+    sk_bytes = 8.0 * n * n
+    gbs = sk_bytes / (best["ms_sketch"] * 1e-3) / 1e9
+    res = {"workload": "lowrank_plus_noise m=n=16384 q=16 rho_plus=32 noise=1e-10", "rank": r["rank"],
+           "resid_rel_fro": r["info"]["resid_fro"] / r["info"]["a_fro"],
+           "ms_total": round(sum(i["ms_total"] for i in infos) / len(infos), 3),
+           "stage_ms": {s: round(best["ms_" + s], 3) for s in ("sketch", "basis", "project", "resid")},
+           "roofline_sketch": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": sk_bytes}}
+    log(f"[bench] lowrank: {res['ms_total']:.2f} ms (sketch {best['ms_sketch']:.2f}, basis {best['ms_basis']:.2f}, "
+        f"project {best['ms_project']:.2f}, resid {best['ms_resid']:.2f}), rank {r['rank']}")
+    del A, G, r
+    torch.cuda.empty_cache()
+    return res
+
+
 def table_7_1(trials: int, sizes=(64, 256, 1024)) -> dict:
     """Table 7.1's experiment through the library: relative residuals ||A y - b||_2 / ||b||_2
     of GENP with a +-1 circulant multiplier, before and after one refinement step, on
@@ -259,6 +287,7 @@ def main() -> int:
                     help="also run one plain copy kernel of the n x n working matrix (PMC calibration)")
     ap.add_argument("--no-circulant", action="store_true",
                     help="skip the structured-multiplier comparisons (circulant by FFT, Householder)")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank approximation measurement")
     ap.add_argument("--table-7-1", type=int, default=0, metavar="TRIALS",
                     help="only run Table 7.1's experiment (n = 64, 256, 1024; TRIALS systems each) "
                          "and print its statistics as one JSON line")
@@ -384,6 +413,8 @@ def main() -> int:
         if 4 <= n <= 16384 and n & (n - 1) == 0:
             out["circulant"] = structured_comparison(args, n, ms_per_step, "circulant")
         out["householder"] = structured_comparison(args, n, ms_per_step, "householder")
+    if not args.no_lowrank and args.prec == "f64":
+        out["lowrank"] = lowrank_measure(args)
     if not args.no_cpu_baseline:
         del s
         torch.cuda.empty_cache()

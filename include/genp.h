@@ -236,6 +236,43 @@ int genp_copy_work(const genp_ctx* ctx, double* out, int64_t ldo);
 /* Static description of a status code. */
 const char* genp_strerror(int status);
 
+/* ------------------------------------------------------------------------- */
+/* Randomized low-rank approximation (Proto-Algorithm 5.1, section 5.3, with the
+ * orthogonal basis of Remark 5.4).  Independent of the GENP context.          */
+
+typedef struct {
+    int64_t m, n, rho_plus;
+    int64_t rank;               /* s: columns kept at Stage 2                                */
+    int32_t failed;             /* 1: ||A - A_hat||_F > tau2 ||A||_F (the FAILURE of Stage 3) */
+    double a_fro;               /* ||A||_F                                                   */
+    double tail_fro;            /* Frobenius norm of the columns of T' left after Stage 2    */
+    double resid_fro;           /* ||A - W_s T_s^T||_F                                        */
+    double ms_total, ms_sketch, ms_basis, ms_project, ms_resid;   /* HIP-event times       */
+} genp_lr_info;
+
+/*
+ * Rank-s approximation A_hat = W_s T_s^T of an m x n FP64 matrix A (row-major, lda >= n),
+ * all device pointers, on `stream` (hipStream_t, NULL = null stream) of the current device:
+ *   Stage 1  T' = A^T G, n x rho_+; mult = GENP_G_DENSE: G is m x rho_+ (ldg >= rho_+);
+ *            GENP_G_TOEPLITZ: G holds the m + rho_+ - 1 parameters of G[i][j] = p[i - j + rho_+ - 1]
+ *            (ldg ignored).  The random numbers are the caller's.
+ *   Stage 2  Gram-Schmidt with column pivoting on T' (each projection applied twice), a
+ *            rank-revealing QR: it stops at the least s for which the remaining columns have
+ *            Frobenius norm <= tau ||A||_F; T_s = its first s orthonormal columns.
+ *   Stage 3  W = A T; failed = ||A - W_s T_s^T||_F > tau2 ||A||_F.
+ * Outputs: T (n x rho_+, ldt >= rho_+) and W (m x rho_+, ldw >= rho_+), of which the first
+ * `rank` columns are the result (the others are scratch); A_hat = W_s T_s^T (m x n, ldah >= n)
+ * when Ahat is not NULL; perm_out (host, rho_+ entries, may be NULL): the columns of T' in
+ * pivot order; info (host).  1 <= rho_+ <= min(64, m, n).  Allocates and frees its own device
+ * scratch (O((m + n) rho_+) plus one double per 64 x 64 tile of A).  Waits for the stream
+ * once, at the end.  Errors: GENP_EINVAL, GENP_ENOTSUP (other multiplier kinds),
+ * GENP_ENOMEM, GENP_EDEVICE.
+ */
+int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, int mult, const double* G,
+                 int64_t ldg, int64_t rho_plus, double tau, double tau2, double* T, int64_t ldt,
+                 double* W, int64_t ldw, double* Ahat, int64_t ldah, int32_t* perm_out,
+                 genp_lr_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,7 @@ SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 
 # the entry points declared in include/genp.h
 EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",
+           "genp_lowrank",
            "genp_refine", "genp_solve_backward", "genp_get_info", "genp_copy_work", "genp_strerror")
 
 
@@ -63,6 +64,19 @@ class GenpInfo(ctypes.Structure):
         return d
 
 
+class GenpLrInfo(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("rho_plus", ctypes.c_int64),
+        ("rank", ctypes.c_int64), ("failed", ctypes.c_int32),
+        ("a_fro", ctypes.c_double), ("tail_fro", ctypes.c_double), ("resid_fro", ctypes.c_double),
+        ("ms_total", ctypes.c_double), ("ms_sketch", ctypes.c_double), ("ms_basis", ctypes.c_double),
+        ("ms_project", ctypes.c_double), ("ms_resid", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class GenpError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -85,6 +99,8 @@ def load(path: str = LIB_PATH):
     L.genp_destroy.argtypes = [vp]
     L.genp_precondition.argtypes = [vp, vp, i64, i32, vp, i64]
     L.genp_precondition2.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64]
+    L.genp_lowrank.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, dbl, dbl, vp, i64, vp, i64, vp, i64,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(GenpLrInfo), vp]
     L.genp_factor.argtypes = [vp, dbl, ctypes.POINTER(i64)]
     L.genp_solve.argtypes = [vp, vp, i64, i64, vp, i64]
     L.genp_refine.argtypes = [vp, vp, i64, i64, vp, i64, i32, dbl, i32, ctypes.POINTER(dbl)]
@@ -273,6 +289,39 @@ def solve(A, B, G=None, p=None, prec: str = "f64", nb: int = 256, refine: int = 
     if refine > 0:
         s.refine(B, X, refine, tol, solver)
     return X, s.info(), s
+
+
+def lowrank(A, rho_plus: int, G=None, p=None, tau: float = 1e-8, tau2: float = 1e-6, want_ahat: bool = False,
+            stream=None):
+    """Randomized rank-s approximation A ~ W_s T_s^T (Proto-Algorithm 5.1, orthogonal basis of
+    Remark 5.4) through genp_lowrank.  G: m x rho_+ multiplier, or p: its m + rho_+ - 1 Toeplitz
+    parameters.  Returns dict(rank, T (n x s), W (m x s), Ahat or None, perm, info)."""
+    import torch
+    m, n = A.shape
+    k = int(rho_plus)
+    a, lda = _mat(A, "A", m, n)
+    if G is not None:
+        g, ldg = _mat(G, "G", m, k)
+        mult = G_DENSE
+    elif p is not None:
+        g, _ = _mat(p, "p", m + k - 1)
+        ldg, mult = k, G_TOEPLITZ
+    else:
+        raise ValueError("need G or p")
+    T = torch.empty((n, k), dtype=torch.float64, device=A.device)
+    W = torch.empty((m, k), dtype=torch.float64, device=A.device)
+    Ah = torch.empty((m, n), dtype=torch.float64, device=A.device) if want_ahat else None
+    t, ldt = _mat(T, "T", n, k)
+    w, ldw = _mat(W, "W", m, k)
+    ah, ldah = (_mat(Ah, "Ahat", m, n) if Ah is not None else (0, n))
+    perm = (ctypes.c_int32 * k)()
+    info = GenpLrInfo()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().genp_lowrank(a, m, n, lda, mult, g, ldg, k, float(tau), float(tau2), t, ldt, w, ldw, ah, ldah,
+                               perm, ctypes.byref(info), ctypes.c_void_p(st.cuda_stream)), "genp_lowrank")
+    s = int(info.rank)
+    return {"rank": s, "T": T[:, :s], "W": W[:, :s], "Ahat": Ah, "perm": [perm[i] for i in range(k)],
+            "info": info.as_dict(), "_keep": (A, G, p)}
 
 
 def _autograd_function():

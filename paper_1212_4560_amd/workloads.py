@@ -156,6 +156,23 @@ def svd_head_matrix(n: int, q: int, seed: int = 0, tail: float = 1e-10, mult: st
     return A, S, sig, T, G
 
 
+def lowrank_plus_noise(m: int, n: int, q: int, rho_plus: int, noise: float = 1e-10, seed: int = 12,
+                       device: str = "cpu"):
+    """A = X Y^T + E: X (m x q), Y (n x q) Gaussian, E Gaussian scaled so that
+    ||E||_F = noise ||X Y^T||_F (numerical rank q); G (m x rho_+) Gaussian.  The large-size
+    low-rank workload (the tables of section 7 stop at n = 256).  Returns (A, G)."""
+    import torch
+    g = np.random.default_rng(seed)
+    X = torch.from_numpy(g.standard_normal((m, q))).to(device)
+    Y = torch.from_numpy(g.standard_normal((n, q))).to(device)
+    A = X @ Y.T
+    E = torch.from_numpy(g.standard_normal((m, n))).to(device)
+    A += E * (noise * float(torch.linalg.norm(A)) / float(torch.linalg.norm(E)))
+    del E
+    G = torch.from_numpy(g.standard_normal((m, rho_plus))).to(device)
+    return A.contiguous(), G
+
+
 def rank_deficient_lead(n: int = 256, seed: int = 1, nrhs: int = 1,
                         lead: int = 8, rank: int = 4) -> Workload:
     """A ~ N(0,1) with a rank-`rank` leading lead x lead block; dense G."""

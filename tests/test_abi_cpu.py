@@ -44,24 +44,26 @@ def test_strerror_covers_codes():
     assert "unknown" in genp.strerror(99)
 
 
-def test_info_struct_layout_matches_header(tmp_path):
-    """The binding's genp_info mirror has the C struct's size and field offsets."""
+@pytest.mark.parametrize("cname,pyname", [("genp_info", "GenpInfo"), ("genp_lr_info", "GenpLrInfo")])
+def test_info_struct_layout_matches_header(tmp_path, cname, pyname):
+    """The binding's mirrors of the info structs have the C structs' sizes and field offsets."""
     import shutil
     import subprocess
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
-    fields = [f for f, _ in genp.GenpInfo._fields_]
+    cls = getattr(genp, pyname)
+    fields = [f for f, _ in cls._fields_]
     src = tmp_path / "layout.c"
-    body = "".join(f'    printf("{f} %zu\\n", offsetof(genp_info, {f}));\n' for f in fields)
+    body = "".join(f'    printf("{f} %zu\\n", offsetof({cname}, {f}));\n' for f in fields)
     src.write_text(f'#include <stddef.h>\n#include <stdio.h>\n#include "genp.h"\nint main(void) {{\n'
-                   f'    printf("sizeof %zu\\n", sizeof(genp_info));\n{body}    return 0;\n}}\n')
+                   f'    printf("sizeof %zu\\n", sizeof({cname}));\n{body}    return 0;\n}}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                          check=True).stdout.splitlines())
-    assert int(out["sizeof"]) == ctypes.sizeof(genp.GenpInfo)
+    assert int(out["sizeof"]) == ctypes.sizeof(cls)
     for f in fields:
-        assert int(out[f]) == getattr(genp.GenpInfo, f).offset, f
+        assert int(out[f]) == getattr(cls, f).offset, f
 
 
 def test_invalid_arguments_rejected_before_device():
