@@ -180,6 +180,39 @@ def lowrank_measure(args) -> dict:
     return res
 
 
+def table_7_2(trials: int) -> dict:
+    """Tables 7.2 and 7.3 through the library: A = S diag(1/j (j <= q), 1e-10) T^T, multiplier
+    G Gaussian (7.2) or Toeplitz (7.3) with rho_+ = q, all q columns kept (tau = 0):
+    rn1 = ||B Y - T_q||_2 (least-squares fit of the exact leading basis T_q by the sketch; the
+    library's orthonormal T spans the sketch, so rn1 = ||T T^T T_q - T_q||_2) and
+    rn2 = ||A - A T T^T||_2, both on the host from the library's T."""
+    import numpy as np
+    import torch
+    from paper_1212_4560_amd import genp, workloads as wl
+
+    def stats(v):
+        v = np.asarray(v)
+        return {"min": float(v.min()), "max": float(v.max()), "mean": float(v.mean()), "std": float(v.std())}
+
+    out = {}
+    for table, mult, qs in (("7.2", wl.MULT_DENSE, (1, 8, 32)), ("7.3", wl.MULT_TOEPLITZ, (8, 32))):
+        for q in qs:
+            for n in (64, 128, 256):
+                rn1, rn2 = [], []
+                for seed in range(trials):
+                    A, S, sig, Tt, G = wl.svd_head_matrix(n, q, seed=1000 * q + seed, mult=mult)
+                    kw = {"G": torch.from_numpy(G).cuda()} if mult == wl.MULT_DENSE else {"p": torch.from_numpy(G).cuda()}
+                    r = genp.lowrank(torch.from_numpy(A).cuda(), q, tau=0.0, tau2=1.0, **kw)
+                    T = r["T"].cpu().numpy()
+                    Tq = Tt[:, :q]
+                    rn1.append(float(np.linalg.norm(T @ (T.T @ Tq) - Tq, 2)))
+                    rn2.append(float(np.linalg.norm(A - (A @ T) @ T.T, 2)))
+                out[f"table{table} q={q} n={n}"] = {"rn1": stats(rn1), "rn2": stats(rn2), "trials": trials}
+                log(f"[table {table}] q={q} n={n}: rn1 max {max(rn1):.2e} mean {np.mean(rn1):.2e}; "
+                    f"rn2 max {max(rn2):.2e} mean {np.mean(rn2):.2e}")
+    return out
+
+
 def table_7_1(trials: int, sizes=(64, 256, 1024)) -> dict:
     """Table 7.1's experiment through the library: relative residuals ||A y - b||_2 / ||b||_2
     of GENP with a +-1 circulant multiplier, before and after one refinement step, on
@@ -288,6 +321,8 @@ def main() -> int:
     ap.add_argument("--no-circulant", action="store_true",
                     help="skip the structured-multiplier comparisons (circulant by FFT, Householder)")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank approximation measurement")
+    ap.add_argument("--table-7-2", type=int, default=0, metavar="TRIALS",
+                    help="only run the experiments of Tables 7.2 / 7.3 (low-rank approximation) and print one JSON line")
     ap.add_argument("--table-7-1", type=int, default=0, metavar="TRIALS",
                     help="only run Table 7.1's experiment (n = 64, 256, 1024; TRIALS systems each) "
                          "and print its statistics as one JSON line")
@@ -307,6 +342,10 @@ def main() -> int:
     from paper_1212_4560_amd import genp, workloads as wl
 
     torch.cuda.set_device(0)
+    if args.table_7_2:
+        print(json.dumps({"experiment": "Tables 7.2 / 7.3: randomized low-rank approximation residuals",
+                          "data": "synthetic", "results": table_7_2(args.table_7_2)}), flush=True)
+        return 0
     if args.table_7_1:
         print(json.dumps({"experiment": "Table 7.1: relative residuals, +-1 circulant GENP",
                           "data": "synthetic", "results": table_7_1(args.table_7_1)}), flush=True)
