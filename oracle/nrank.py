@@ -92,7 +92,8 @@ LANCZOS_STEPS_PER_COLUMN = 6   # without reorthogonalization the extremes need s
 def cond_lanczos(B: np.ndarray, v0: np.ndarray) -> float:
     """Remark B.2: kappa_2(B) from the extreme eigenvalues of S = B^T B (Lanczos with 6s
     steps, then Sturm bisection on the tridiagonal).  The Ritz values lie inside the
-    spectrum of S, so the estimate is a lower bound on kappa_2(B)."""
+    spectrum of S, so the estimate is a lower bound on kappa_2(B) -- except that eigenvalues
+    of S below its rounding level (u lambda_max) come out at that level or <= 0 (kappa inf)."""
     B = np.asarray(B, dtype=np.float64)
     S = B.T @ B
     al, be = lanczos_tridiag(S, v0, LANCZOS_STEPS_PER_COLUMN * S.shape[0])

@@ -26,9 +26,10 @@ def test_sturm_extremes_against_eigvalsh():
 
 def test_lanczos_cond_against_svd():
     """Remark B.2's COND (Lanczos on B^T B without reorthogonalization, Sturm bisection) against
-    kappa_2 from the SVD: accurate for spectra graded up to kappa 1e3, and -- the case the rank
-    search meets at s = nrank + 1 -- an isolated tiny singular value is found (the estimate is
-    a lower bound, since Ritz values lie inside the spectrum)."""
+    kappa_2 from the SVD: accurate for spectra graded up to kappa 1e3 (a lower bound, since Ritz
+    values lie inside the spectrum), and -- the case the rank search meets at s = nrank + 1 --
+    an isolated singular value of 1e-10 is found (its square is at the rounding level of S,
+    so the estimate is huge or infinite)."""
     g = np.random.default_rng(2)
     for s, kap, rtol in ((1, 1.0, 1e-12), (5, 10.0, 1e-8), (16, 1e2, 1e-6), (40, 1e3, 1e-6), (64, 1e3, 1e-2)):
         U = np.linalg.qr(g.standard_normal((200, s)))[0]
@@ -43,8 +44,7 @@ def test_lanczos_cond_against_svd():
         sig = 1.0 / np.arange(1, s + 1)
         sig[-1] = 1e-10
         B = (U * sig) @ V.T
-        k = onr.cond_lanczos(B, g.standard_normal(s))
-        assert k <= onr.cond_svd(B) * (1 + 1e-6) and k >= 1e7
+        assert onr.cond_lanczos(B, g.standard_normal(s)) >= 1e7   # lambda_min(S) ~ 1e-20: at the rounding level
 
 
 @pytest.mark.parametrize("q", [1, 8, 32])
