@@ -155,7 +155,9 @@ def structured_comparison(args, n: int, f64_ms: float, kind: str) -> dict:
 def lowrank_measure(args) -> dict:
     """Randomized low-rank approximation (Proto-Algorithm 5.1) at m = n = 16384, rho_+ = 32, on
     A = X Y^T + E of numerical rank 16: time per call, stages, rank, residual, and the HBM
-    roofline of the sketch A^T G (one pass over A: 8 m n bytes)."""
+    roofline of the sketch A^T G (one pass over A: 8 m n bytes); then the numerical rank of the
+    same A (Proto-Algorithm B.1) in [0, 64]."""
+    import numpy as np
     import torch
     from paper_1212_4560_amd import genp, workloads as wl
     n, q, k = 16384, 16, 32
@@ -175,6 +177,17 @@ def lowrank_measure(args) -> dict:
                                "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": sk_bytes}}
     log(f"[bench] lowrank: {res['ms_total']:.2f} ms (sketch {best['ms_sketch']:.2f}, basis {best['ms_basis']:.2f}, "
         f"project {best['ms_project']:.2f}, resid {best['ms_resid']:.2f}), rank {r['rank']}")
+    # numerical rank (Proto-Algorithm B.1) of the same A in [0, 64]
+    G64 = torch.from_numpy(np.random.default_rng(13).standard_normal((n, 64))).to("cuda")
+    genp.numerical_rank(A, G64, 0, 64)
+    nr = [genp.numerical_rank(A, G64, 0, 64)["info"] for _ in range(max(1, args.steps))]
+    res["numerical_rank"] = {"range": [0, 64], "rank": int(nr[-1]["rank"]), "tests": int(nr[-1]["tests"]),
+                             "cond_at_rank": nr[-1]["cond_at_rank"], "cond_above": nr[-1]["cond_above"],
+                             "ms_total": round(sum(i["ms_total"] for i in nr) / len(nr), 3),
+                             "stage_ms": {s_: round(nr[-1]["ms_" + s_], 3) for s_ in ("sketch", "gram", "search")}}
+    log(f"[bench] numerical rank: {res['numerical_rank']['rank']} in {res['numerical_rank']['tests']} tests, "
+        f"{res['numerical_rank']['ms_total']:.2f} ms")
+    del G64
     del A, G, r
     torch.cuda.empty_cache()
     return res

@@ -273,6 +273,38 @@ int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, int mult, c
                  double* W, int64_t ldw, double* Ahat, int64_t ldah, int32_t* perm_out,
                  genp_lr_info* info, void* stream);
 
+/* ------------------------------------------------------------------------- */
+/* Numerical rank without pivoting or orthogonalization (Proto-Algorithm B.1,
+ * Appendix B, with the COND of Remark B.2 and the bisection of Remark B.4).    */
+
+typedef struct {
+    int64_t m, n, rho_minus, rho_plus;
+    int64_t rank;               /* the numerical rank found                               */
+    int32_t tests;              /* COND evaluations (at most ceil(log2(rho_+ - rho_- + 1)))  */
+    double cond_at_rank;        /* COND's kappa_2 estimate of B_rank (NaN when not tested)  */
+    double cond_above;          /* the estimate of B_{rank+1} (NaN when not tested)        */
+    double ms_total, ms_sketch, ms_gram, ms_search;   /* HIP-event times                 */
+} genp_nrank_info;
+
+/*
+ * Numerical rank of an m x n FP64 matrix A (row-major, lda >= n; device pointers; `stream`
+ * as for genp_lowrank) in the range [rho_minus, rho_plus], 0 <= rho_- < rho_+ <= min(64, m, n).
+ * G: the caller's m x rho_+ Gaussian multiplier (ldg >= rho_+).  The sketch B = A^T G is formed
+ * once; the candidates s are tested by bisection (s = ceil((lo + hi) / 2)) on B_s = its first s
+ * columns (= A^T G_s): COND passes when the kappa_2 estimate of B_s is <= cond_max, and a pass
+ * raises the lower end (B_s keeps full rank with high probability exactly when
+ * s <= nrank(A)), a failure lowers the upper end to s - 1.  COND runs Lanczos (6 s steps, no
+ * reorthogonalization) on the leading s x s block of B^T B and locates the extreme
+ * eigenvalues of the tridiagonal by Sturm-count multisection; the estimate is a lower bound
+ * on kappa_2 except below the rounding level of B^T B (about 1e8 for kappa_2), so cond_max
+ * should lie well below 1e8.  Output B (n x rho_+, ldb >= rho_+): the sketch; its first `rank`
+ * columns approximate a basis of the leading right singular space.  Allocates and frees its
+ * own scratch; waits for the stream once.  Errors: GENP_EINVAL, GENP_ENOMEM, GENP_EDEVICE.
+ */
+int genp_numerical_rank(const double* A, int64_t m, int64_t n, int64_t lda, const double* G,
+                        int64_t ldg, int64_t rho_minus, int64_t rho_plus, double cond_max, double* B,
+                        int64_t ldb, genp_nrank_info* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

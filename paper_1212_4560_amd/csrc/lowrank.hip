@@ -446,6 +446,125 @@ hipError_t skinny_mfma(int M, int K, int N, const double* A, long long lda, cons
                                     LR_MAXK, s);
 }
 
+// ---------------------------------------------------------------------------------------
+// Numerical rank without pivoting or orthogonalization (Proto-Algorithm B.1): bisection over
+// s (Remark B.4) on the conditioning of B_s = A^T G_s, the first s columns of the sketch.
+// COND (Remark B.2): Lanczos on the leading s x s block of the Gram matrix S = B^T B, no
+// reorthogonalization, 6 s steps; the extreme eigenvalues of the tridiagonal by multisection
+// on Sturm counts (64 trial points per round, one per lane); kappa_2 = sqrt(lmax / lmin).
+// One wave does everything: lane i holds component i of the Lanczos vectors.
+constexpr int NR_STEPS = 6;                       // Lanczos steps per column
+constexpr int NR_MAXT = NR_STEPS * LR_MAXK;       // tridiagonal order
+
+struct NrOut {
+    int rank, tests;
+    double cond_at_rank, cond_above;
+};
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// eigenvalues < x of the tridiagonal (al[0..k), be[0..k-1)) from the pivots of T - x I
+__device__ int nr_sturm(const double* al, const double* be, int k, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+        d = (al[i] - x) - (i ? be[i - 1] * be[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        cnt += d < 0.0;
+    }
+    return cnt;
+}
+
+// the target-th smallest eigenvalue (target 1 or k) by multisection in [lo, hi]
+__device__ double nr_eig(const double* al, const double* be, int k, int target, double lo, double hi) {
+    const int lane = threadIdx.x;
+    for (int round = 0; round < 16; ++round) {
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        const bool ge = nr_sturm(al, be, k, x) >= target;
+        const unsigned long long m = __ballot(ge);
+        const int first = m ? __ffsll((long long)m) - 1 : 64;   // first trial point at or past the eigenvalue
+        const double nlo = lo + (hi - lo) * (double)first / 65.0;
+        const double nhi = (first < 64) ? lo + (hi - lo) * (double)(first + 1) / 65.0 : hi;
+        if (!(nhi - nlo < hi - lo)) break;
+        lo = nlo;
+        hi = nhi;
+    }
+    return 0.5 * (lo + hi);
+}
+
+__global__ void __launch_bounds__(64) nr_search_kernel(int lo, int hi, const double* __restrict__ S,
+                                                       const double* __restrict__ v0src, double cond_max,
+                                                       NrOut* __restrict__ out) {
+    __shared__ double Ss[LR_MAXK][LR_MAXK + 1];
+    __shared__ double vs[LR_MAXK];
+    __shared__ double al[NR_MAXT], be[NR_MAXT];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < LR_MAXK * LR_MAXK; e += 64) Ss[e / LR_MAXK][e % LR_MAXK] = S[e];
+    __syncthreads();
+    int tests = 0;
+    double cond_rank = -1.0, cond_above = -1.0;   // -1: not tested
+    while (lo < hi) {
+        const int s = (lo + hi + 1) / 2;
+        // Lanczos on S_s from the first s entries of the multiplier's first column
+        const bool on = lane < s;
+        double v = on ? v0src[(long long)lane * LR_MAXK] : 0.0;
+        v /= sqrt(wave_sum64(v * v));
+        double vp = 0.0, b = 0.0;
+        int k = 0;
+        for (; k < NR_STEPS * s; ++k) {
+            vs[lane] = v;
+            __syncthreads();
+            double w = 0.0;
+            if (on)
+                for (int j = 0; j < s; ++j) w = fma(Ss[lane][j], vs[j], w);
+            __syncthreads();
+            w -= b * vp;
+            const double a = wave_sum64(v * w);
+            w -= a * v;
+            al[k] = a;   // every lane writes the same value
+            b = sqrt(wave_sum64(w * w));
+            if (!(b > 1e-300)) {
+                ++k;
+                break;
+            }
+            be[k] = b;
+            vp = v;
+            v = w / b;
+        }
+        __syncthreads();
+        // Gershgorin interval, then the extreme eigenvalues
+        double glo = 1e300, ghi = -1e300;
+        for (int i = 0; i < k; ++i) {
+            const double r = (i ? fabs(be[i - 1]) : 0.0) + (i + 1 < k ? fabs(be[i]) : 0.0);
+            glo = fmin(glo, al[i] - r);
+            ghi = fmax(ghi, al[i] + r);
+        }
+        const double lmin = nr_eig(al, be, k, 1, glo, ghi);
+        const double lmax = nr_eig(al, be, k, k, glo, ghi);
+        const double kap = (lmin > 0.0) ? sqrt(lmax / lmin) : __builtin_inf();
+        const bool ok = kap <= cond_max;
+        ++tests;
+        if (ok) {
+            lo = s;
+            cond_rank = kap;
+        } else {
+            hi = s - 1;
+            cond_above = kap;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        out->rank = lo;
+        out->tests = tests;
+        out->cond_at_rank = cond_rank;
+        out->cond_above = cond_above;
+    }
+}
+
 struct Scratch {
     std::vector<void*> ptrs;
     ~Scratch() {
@@ -589,5 +708,71 @@ extern "C" int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, 
     if (hipEventElapsedTime(&ms, ev[0], ev[4]) == hipSuccess) info->ms_total = ms;
     if (perm_out)
         for (int i = 0; i < K; ++i) perm_out[i] = hp[i];
+    return GENP_OK;
+}
+
+extern "C" int genp_numerical_rank(const double* A, int64_t m, int64_t n, int64_t lda, const double* G, int64_t ldg,
+                                   int64_t rho_minus, int64_t rho_plus, double cond_max, double* B, int64_t ldb,
+                                   genp_nrank_info* info, void* stream) {
+    if (!A || !G || !B || !info || m < 1 || n < 1 || lda < n || rho_minus < 0 || rho_plus <= rho_minus ||
+        rho_plus > LR_MAXK || rho_plus > std::min(m, n) || ldg < rho_plus || ldb < rho_plus || !(cond_max >= 1.0) ||
+        m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
+        return GENP_EINVAL;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return GENP_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const int M = (int)m, N = (int)n, K = (int)rho_plus;
+    const size_t Mp = ((size_t)M + 15) / 16 * 16, Np = ((size_t)N + 15) / 16 * 16;
+    const long long part_cap = 16LL * std::max(M, N) * LR_MAXK;
+    Scratch sc;
+    double *G64 = nullptr, *T64 = nullptr, *Sg = nullptr, *part = nullptr;
+    NrOut* od = nullptr;
+    if (!sc.get(&G64, Mp * LR_MAXK) || !sc.get(&T64, Np * LR_MAXK) || !sc.get(&Sg, (size_t)LR_MAXK * LR_MAXK) ||
+        !sc.get(&part, part_cap) || !sc.get(&od, 1))
+        return GENP_ENOMEM;
+    hipEvent_t ev[4];
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return GENP_EDEVICE;
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; ++i) hipEventDestroy(e[i]);
+        }
+    } eg{ev};
+    auto blocks = [](long long tot) { return dim3((unsigned)((tot + 255) / 256)); };
+    LR_HIP(hipEventRecord(ev[0], s));
+    LR_HIP(hipMemsetAsync(G64, 0, Mp * LR_MAXK * sizeof(double), s));
+    LR_HIP(hipMemsetAsync(T64, 0, Np * LR_MAXK * sizeof(double), s));
+    LR_HIP(hipMemsetAsync(Sg, 0, (size_t)LR_MAXK * LR_MAXK * sizeof(double), s));
+    hipLaunchKernelGGL(pad_cols_kernel, blocks((long long)M * LR_MAXK), dim3(256), 0, s, M, K, G, (long long)ldg, G64);
+    LR_HIP(skinny_mfma<true>(N, M, K, A, lda, G64, T64, part, part_cap, s));        // B = A^T G
+    LR_HIP(hipEventRecord(ev[1], s));
+    LR_HIP(skinny_mfma<true>(K, N, K, T64, LR_MAXK, T64, Sg, part, part_cap, s));   // S = B^T B
+    LR_HIP(hipEventRecord(ev[2], s));
+    hipLaunchKernelGGL(nr_search_kernel, dim3(1), dim3(64), 0, s, (int)rho_minus, K, Sg, G64, cond_max, od);
+    hipLaunchKernelGGL(copy_cols_kernel, blocks((long long)N * K), dim3(256), 0, s, N, K, T64, B, (long long)ldb);
+    LR_HIP(hipGetLastError());
+    LR_HIP(hipEventRecord(ev[3], s));
+    NrOut ho;
+    LR_HIP(hipMemcpyAsync(&ho, od, sizeof ho, hipMemcpyDeviceToHost, s));
+    LR_HIP(hipStreamSynchronize(s));
+    *info = genp_nrank_info{};
+    info->m = m;
+    info->n = n;
+    info->rho_minus = rho_minus;
+    info->rho_plus = rho_plus;
+    info->rank = ho.rank;
+    info->tests = ho.tests;
+    const double nan = __builtin_nan("");
+    info->cond_at_rank = ho.cond_at_rank < 0 ? nan : ho.cond_at_rank;
+    info->cond_above = ho.cond_above < 0 ? nan : ho.cond_above;
+    float ms = 0.f;
+    double* slots[3] = {&info->ms_sketch, &info->ms_gram, &info->ms_search};
+    for (int i = 0; i < 3; ++i)
+        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) *slots[i] = ms;
+    if (hipEventElapsedTime(&ms, ev[0], ev[3]) == hipSuccess) info->ms_total = ms;
     return GENP_OK;
 }

@@ -34,7 +34,7 @@ SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 
 # the entry points declared in include/genp.h
 EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",
-           "genp_lowrank",
+           "genp_lowrank", "genp_numerical_rank",
            "genp_refine", "genp_solve_backward", "genp_get_info", "genp_copy_work", "genp_strerror")
 
 
@@ -77,6 +77,19 @@ class GenpLrInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class GenpNrankInfo(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("rho_minus", ctypes.c_int64), ("rho_plus", ctypes.c_int64),
+        ("rank", ctypes.c_int64), ("tests", ctypes.c_int32),
+        ("cond_at_rank", ctypes.c_double), ("cond_above", ctypes.c_double),
+        ("ms_total", ctypes.c_double), ("ms_sketch", ctypes.c_double), ("ms_gram", ctypes.c_double),
+        ("ms_search", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class GenpError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -99,6 +112,8 @@ def load(path: str = LIB_PATH):
     L.genp_destroy.argtypes = [vp]
     L.genp_precondition.argtypes = [vp, vp, i64, i32, vp, i64]
     L.genp_precondition2.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64]
+    L.genp_numerical_rank.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, dbl, vp, i64,
+                                      ctypes.POINTER(GenpNrankInfo), vp]
     L.genp_lowrank.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, dbl, dbl, vp, i64, vp, i64, vp, i64,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(GenpLrInfo), vp]
     L.genp_factor.argtypes = [vp, dbl, ctypes.POINTER(i64)]
@@ -322,6 +337,25 @@ def lowrank(A, rho_plus: int, G=None, p=None, tau: float = 1e-8, tau2: float = 1
     s = int(info.rank)
     return {"rank": s, "T": T[:, :s], "W": W[:, :s], "Ahat": Ah, "perm": [perm[i] for i in range(k)],
             "info": info.as_dict(), "_keep": (A, G, p)}
+
+
+def numerical_rank(A, G, rho_minus: int, rho_plus: int, cond_max: float = 1e6, stream=None):
+    """Numerical rank of A in [rho_-, rho_+] without pivoting or orthogonalization
+    (Proto-Algorithm B.1) through genp_numerical_rank.  G: the m x rho_+ Gaussian multiplier.
+    Returns dict(rank, B (n x rank: the first columns of A^T G), info)."""
+    import torch
+    m, n = A.shape
+    k = int(rho_plus)
+    a, lda = _mat(A, "A", m, n)
+    g, ldg = _mat(G, "G", m, k)
+    B = torch.empty((n, k), dtype=torch.float64, device=A.device)
+    b, ldb = _mat(B, "B", n, k)
+    info = GenpNrankInfo()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().genp_numerical_rank(a, m, n, lda, g, ldg, int(rho_minus), k, float(cond_max), b, ldb,
+                                      ctypes.byref(info), ctypes.c_void_p(st.cuda_stream)), "genp_numerical_rank")
+    r = int(info.rank)
+    return {"rank": r, "B": B[:, :r], "info": info.as_dict()}
 
 
 def _autograd_function():

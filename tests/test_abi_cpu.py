@@ -44,7 +44,8 @@ def test_strerror_covers_codes():
     assert "unknown" in genp.strerror(99)
 
 
-@pytest.mark.parametrize("cname,pyname", [("genp_info", "GenpInfo"), ("genp_lr_info", "GenpLrInfo")])
+@pytest.mark.parametrize("cname,pyname", [("genp_info", "GenpInfo"), ("genp_lr_info", "GenpLrInfo"),
+                                          ("genp_nrank_info", "GenpNrankInfo")])
 def test_info_struct_layout_matches_header(tmp_path, cname, pyname):
     """The binding's mirrors of the info structs have the C structs' sizes and field offsets."""
     import shutil
