@@ -466,6 +466,11 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    // the right-hand side of this block's rows, read before the waits (only this workgroup
+    // writes them, at the end)
+    double bv[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) bv[c] = (part == 0) ? X[(r0 + ri) * ldx + c] : 0.0;
     for (int s_ = 0; s_ < q; ++s_) {
         const int p = order(s_);
         const int buf = s_ & 1;
@@ -500,7 +505,7 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     }
     if (part == 0) {
 #pragma unroll
-        for (int c = 0; c < NR; ++c) zs[ri][c] = X[(r0 + ri) * ldx + c] - acc[c];
+        for (int c = 0; c < NR; ++c) zs[ri][c] = bv[c] - acc[c];
     }
     __syncthreads();
     if (wave == 0) {
@@ -508,10 +513,15 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
 #pragma unroll
         for (int c = 0; c < NR; ++c) z[c] = zs[lane][c];
         const double rd = UNIT ? 1.0 : 1.0 / Td[lane][lane];
+        // this lane's row of the diagonal block in registers: the sweep then reads no LDS
+        double trow[BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) trow[i] = Td[lane][i];
+#pragma unroll
         for (int u = 0; u < BS; ++u) {
             const int i = LOWER ? u : BS - 1 - u;
             const double ri_ = UNIT ? 1.0 : readlane_d(rd, i);
-            const double m = Td[lane][i];
+            const double m = trow[i];
             const bool upd = LOWER ? lane > i : lane < i;
             const bool own = lane == i;
 #pragma unroll
