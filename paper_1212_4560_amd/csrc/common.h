@@ -79,6 +79,9 @@ struct GemmLpArgs {
 hipError_t launch_gemm_lp(const GemmLpArgs& a, int tile, hipStream_t s);
 
 // Diagonal block LU (no pivoting) in place, one workgroup; records PanelStats.
+// FP64 256 x 256 diagonal block as two LDS-resident 128 blocks, the panel solves and one update
+hipError_t launch_diag_lu_split(void* Dblk, long long ldd, int nvalid, long long col0, const double* maxc,
+                                double pivot_tol, PanelStats* st, hipStream_t s);
 hipError_t launch_diag_lu(int prec, void* Dblk, long long ldd, int nb, int nvalid,
                           long long col0, const double* maxc, double pivot_tol,
                           PanelStats* st, hipStream_t s);

@@ -90,6 +90,7 @@ struct genp_ctx {
     // chained triangular solves (<= 4 right-hand sides): ticket, sticky error word, one flag per 64 rows
     unsigned* tsync = nullptr;
     bool trsv_chain = true;
+    bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
     double anorm = 0.0;
 };
 
@@ -701,6 +702,8 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
         c->lookahead = !(la && la[0] == '0');
         const char* tv = getenv("GENP_TRSV");   // "step": one launch per block instead of the chained solve
         c->trsv_chain = !(tv && strcmp(tv, "step") == 0);
+        const char* dg = getenv("GENP_DIAG");   // "single": one workgroup per 256 diagonal block
+        c->diag_split = !(dg && strcmp(dg, "single") == 0);
     }
     if (ok) ok = ensure_rhs(c, 4) == GENP_OK;
     if (!ok) {
@@ -860,7 +863,10 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         const int64_t k = j * nb;
         const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
         HIPCK(hipEventRecord(ev(j, 2), st));
-        HIPCK(launch_diag_lu(c->prec, at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+        if (c->diag_split && c->prec == GENP_F64 && nb == 256)
+            HIPCK(launch_diag_lu_split(at(k, k), ldc, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+        else
+            HIPCK(launch_diag_lu(c->prec, at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
         return GENP_OK;
     };
     auto solves = [&](int64_t j, hipStream_t st) -> int {

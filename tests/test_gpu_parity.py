@@ -328,6 +328,39 @@ def test_lookahead_does_not_change_the_factors(monkeypatch, n, nb, prec):
     assert np.array_equal(on, off)
 
 
+@pytest.mark.parametrize("n", [512, 1280, 1100])
+def test_split_diagonal_blocks_match_single_workgroup_blocks(monkeypatch, n):
+    """FP64 nb = 256: the diagonal block as two LDS-resident 128 halves with the panel solves
+    and one update between them (block GE on the block, Theorem 2.2) against one workgroup
+    eliminating it column by column: the same pivots in exact arithmetic, so on a strongly well
+    conditioned C the factors agree to rounding (1e-12 relative), including a ragged last block."""
+    g = np.random.default_rng(n + 7)
+    A = g.standard_normal((n, n)) + 2 * np.sqrt(n) * np.eye(n)
+    G = np.eye(n) + 0.1 * g.standard_normal((n, n)) / np.sqrt(n)
+    _, split = _factor_with_env(monkeypatch, "GENP_DIAG", "split", A, G, n, 256)
+    _, single = _factor_with_env(monkeypatch, "GENP_DIAG", "single", A, G, n, 256)
+    assert np.max(np.abs(split - single)) <= 1e-12 * np.max(np.abs(single))
+
+
+@pytest.mark.parametrize("mode", ["split", "single"])
+def test_breakdown_in_the_second_half_of_a_diagonal_block(monkeypatch, mode):
+    """A leading 200 x 200 block of rank 199 (no multiplier): GENP breaks down at column 200,
+    which lies in the second 128-column half of the first 256 block.  The failing pivot is
+    rounding noise (2e-10 max|C| on the host, measured up to 2e-10 max|C| with one workgroup
+    and 2e-8 max|C| with the split block, whose products sum in another order); every
+    regular pivot is >= 5e-3 max|C|, so pivot_tol = 1e-7 separates them with margin."""
+    monkeypatch.setenv("GENP_DIAG", mode)
+    n = 512
+    g = np.random.default_rng(5)
+    A = g.standard_normal((n, n))
+    A[:200, :200] = g.standard_normal((200, 199)) @ g.standard_normal((199, 200))
+    s = genp.Solver(n, "f64", 256)
+    s.precondition(dev(A))
+    assert s.factor(1e-7) == 200
+    inf = s.info()
+    assert inf["min_abs_piv"] >= 5e-3 * inf["max_abs_c"]
+
+
 @pytest.mark.parametrize("nrhs", [1, 2, 3, 4])
 def test_chained_triangular_solves_match_per_block_solves(monkeypatch, nrhs):
     """The single-launch solves (forward/backward for the solution, transposed for the
