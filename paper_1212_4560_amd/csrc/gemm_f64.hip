@@ -369,26 +369,34 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
     __builtin_amdgcn_sched_barrier(0);
     mma(0);
     __builtin_amdgcn_sched_barrier(0);
-    mma(1);
-    // epilogue: D = alpha acc + beta Cin; Cin may alias D, so each 16-row strip's loads are
-    // issued as a batch before its stores
+    // Epilogue: D = alpha acc + beta Cin, one 16-row strip at a time, with the loads of the
+    // next strip of Cin in flight while a strip is stored: the first strip's loads go out
+    // before the last chunk's MFMAs, into the registers the first buffer has freed.  Each
+    // element is read before it is written and the strips are disjoint, so Cin may alias D.
     const bool rd = g.beta != 0.0;
+    double cv[2][4][4];
+    auto load_c = [&](int buf, int mi) {
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                cv[buf][ni][r] = ((gcd_ptr)gCin)[(long long)(m0 + mi * 16 + lq + 4 * r) * g.ldci + n0 + ni * 16 + lr];
+    };
+    if (rd) load_c(0, 0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    mma(1);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
-        double cv[4][4];
-        if (rd) {
-#pragma unroll
-            for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    cv[ni][r] = ((gcd_ptr)gCin)[(long long)(m0 + mi * 16 + lq + 4 * r) * g.ldci + n0 + ni * 16 + lr];
-        }
+        if (mi + 1 < 4 && rd) load_c((mi + 1) & 1, mi + 1);
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double v = g.alpha * acc[mi][ni][r];
-                if (rd) v = fma(g.beta, cv[ni][r], v);
+                if (rd) v = fma(g.beta, cv[mi & 1][ni][r], v);
                 ((double __attribute__((address_space(1)))*)gD)[(long long)(m0 + mi * 16 + lq + 4 * r) * g.ldd + n0 + ni * 16 + lr] = v;
             }
     }
