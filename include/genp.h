@@ -117,6 +117,8 @@ typedef struct {
                                    none: 1; dense and Toeplitz: NaN (not computed)           */
     int32_t mult_left;          /* kind of the left multiplier H (GENP_G_NONE without one)   */
     double cond_h;              /* the same for H                                            */
+    int32_t block_ge;           /* 1 after genp_factor_block, 0 after genp_factor             */
+    int64_t row_swaps;          /* genp_factor_block: rows r with perm[r] != r (0 for GENP)   */
 } genp_info;
 
 /*
@@ -182,6 +184,45 @@ int genp_precondition2(genp_ctx* ctx, const double* A, int64_t lda, int left, co
  * columns before breakdown_col).  Synchronizes the stream.
  */
 int genp_factor(genp_ctx* ctx, double pivot_tol, int64_t* breakdown_col);
+
+/*
+ * Block Gaussian elimination of C in place with the diagonal nb x nb blocks of
+ * the successive Schur complements as explicit block pivots (Theorem 2.2 and
+ * Fact 2.1: B_k is the leading block of the k-th Schur complement, which is then
+ * replaced by its Schur complement with respect to B_k).  B_k^{-1} is applied
+ * through Gaussian elimination with row interchanges inside B_k only: at each
+ * column the row of the block with the largest |entry| (the first on ties)
+ * becomes the pivot row, and the interchange is applied to the whole row of C.
+ * The result is P C = L U with P block diagonal (one permutation per block
+ * pivot), L unit lower and U upper triangular, stored like genp_factor's.
+ * Needs only the leading nb, 2nb, 3nb, ... blocks of C to be nonsingular, where
+ * GENP needs every leading block.  FP64 contexts only (else GENP_ENOTSUP).
+ *   pivot_tol, breakdown_col  as for genp_factor; a breakdown now means that a
+ *                block pivot is numerically singular (its largest candidate in
+ *                some column is non-finite or <= pivot_tol * max|C|).
+ * Solve, refine and the adjoint then apply P (and P^T) themselves.  A new
+ * genp_precondition returns the context to GENP.  Synchronizes the stream.
+ */
+int genp_factor_block(genp_ctx* ctx, double pivot_tol, int64_t* breakdown_col);
+
+/*
+ * The explicit block pivots of the last successful factorization (FP64
+ * contexts): out (device, n x ldo, ldo >= nb) receives B_k = P_k^T L_kk U_kk in
+ * rows k nb .. k nb + w - 1 (w = min(nb, n - k nb)), columns 0 .. w - 1, in the
+ * row order of C; columns w .. nb - 1 of a ragged last block are set to 0.
+ * After genp_factor P_k = I (B_k = L_kk U_kk, the same blocks of the Schur
+ * complements).  The caller owns out.  Stream-ordered; GENP_ESTATE before a
+ * successful factorization, GENP_ENOTSUP for FP32/BF16 contexts.
+ */
+int genp_block_pivots(const genp_ctx* ctx, double* out, int64_t ldo);
+
+/*
+ * The row permutation of the last factorization: perm (device, n int32) receives
+ * the row of C that factor row r came from (P C = L U, row r of P C = row
+ * perm[r] of C).  The identity after genp_factor.  Stream-ordered; GENP_ESTATE
+ * before a factorization.
+ */
+int genp_row_perm(const genp_ctx* ctx, int32_t* perm);
 
 /*
  * X = G U^{-1} L^{-1} B for nrhs right-hand sides (B: n x nrhs, ldb >= nrhs;

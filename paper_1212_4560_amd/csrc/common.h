@@ -85,6 +85,20 @@ hipError_t launch_diag_lu_split(void* Dblk, long long ldd, int nvalid, long long
 hipError_t launch_diag_lu(int prec, void* Dblk, long long ldd, int nb, int nvalid,
                           long long col0, const double* maxc, double pivot_tol,
                           PanelStats* st, hipStream_t s);
+// Block Gaussian elimination (Theorem 2.2): the FP64 diagonal block as the block pivot, rows
+// interchanged inside it; perm[r] (r < nb) receives the global row that factor row r came from.
+hipError_t launch_diag_lu_piv(double* Dblk, long long ldd, int nb, int nvalid, long long col0, const double* maxc,
+                              double pivot_tol, PanelStats* st, int* perm, hipStream_t s);
+// Rows row0 .. row0+nb-1 take the block's interchanges in the columns outside the diagonal block.
+hipError_t launch_block_row_perm(double* C, long long ldc, long long row0, int nb, int ncols, const int* perm,
+                                 hipStream_t s);
+// out (n x ldo): the explicit block pivots P_k^T L_kk U_kk of the packed factors (perm may be null).
+hipError_t launch_block_pivots(const double* C, long long ldc, int n, int nb, const int* perm, double* out,
+                               long long ldo, hipStream_t s);
+// dst row i = src row perm[i] (gather), or dst row perm[i] = src row i (scatter); n x k, FP64.
+hipError_t launch_permute_rows(int n, int k, const double* src, long long lds, double* dst, long long ldd,
+                               const int* perm, int scatter, hipStream_t s);
+hipError_t launch_iota(int* p, int n, hipStream_t s);
 // Fill the padding of an n_pad x n_pad working matrix: zeros off the diagonal, ones on it.
 hipError_t launch_pad_identity(int prec, void* C, long long ldc, int n, int n_pad, hipStream_t s);
 hipError_t launch_max_abs(int prec, const void* X, long long ldx, int rows, int cols, int upper_only,

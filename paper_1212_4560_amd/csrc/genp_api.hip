@@ -91,6 +91,10 @@ struct genp_ctx {
     unsigned* tsync = nullptr;
     bool trsv_chain = true;
     bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
+    // block Gaussian elimination: rows interchanged inside the diagonal blocks, P C = L U;
+    // factor row r came from row perm[r] of C (n_pad entries)
+    bool block_ge = false;
+    int* perm = nullptr;
     double anorm = 0.0;
 };
 
@@ -193,13 +197,20 @@ int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_
     return GENP_OK;
 }
 
-// Z (n_pad x k, ldz) := U^{-1} L^{-1} Z, block by block: substitution with the
+int lu_solve_trans_core(genp_ctx* c, double* Z, int64_t ldz, int k);
+
+// Z (n_pad x k, ldz) := U^{-1} L^{-1} P Z (P = I for GENP), block by block: substitution with the
 // diagonal block, then the block column below (above) updates the remaining rows.
 int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const int64_t nb = c->nb, nblk = c->n_pad / nb;
     const int f32 = c->prec != GENP_F64;
     const size_t es = esize(c->prec);
     const char* Cb = (const char*)c->C;
+    if (c->block_ge) {
+        // P Z through the split-K scratch (at least n_pad x k)
+        HIPCK(launch_permute_rows((int)c->n_pad, k, Z, ldz, c->part, k, c->perm, 0, c->stream));
+        HIPCK(launch_copy2d(c->part, k, Z, ldz, (int)c->n_pad, k, c->stream));
+    }
     if (k <= 4) {
         // few right-hand sides: one chained launch per triangle (or one launch per 128-row block)
         if (c->trsv_chain) {
@@ -236,8 +247,17 @@ int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     return GENP_OK;
 }
 
-// Z (n_pad x k) := L^{-T} U^{-T} Z (the transposed solve of the adjoint).
+// Z (n_pad x k) := P^T L^{-T} U^{-T} Z (the transposed solve of the adjoint; P = I for GENP).
 int lu_solve_trans_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
+    CK(lu_solve_trans_core(c, Z, ldz, k));
+    if (c->block_ge) {
+        HIPCK(launch_copy2d(Z, ldz, c->part, k, (int)c->n_pad, k, c->stream));
+        HIPCK(launch_permute_rows((int)c->n_pad, k, c->part, k, Z, ldz, c->perm, 1, c->stream));
+    }
+    return GENP_OK;
+}
+
+int lu_solve_trans_core(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const int64_t nb = c->nb, nblk = c->n_pad / nb;
     const int f32 = c->prec != GENP_F64;
     const size_t es = esize(c->prec);
@@ -726,6 +746,7 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->stats);
     hipFree(c->red);
     hipFree(c->tsync);
+    hipFree(c->perm);
     for (Mult* m : {&c->mr, &c->ml}) {
         hipFree(m->p);
         hipFree(m->p_rev);
@@ -842,13 +863,20 @@ int genp_precondition2(genp_ctx* c, const double* A, int64_t lda, int left, cons
     // a multiplier singular to working precision makes C singular too
     if (singular) return GENP_ESINGULAR;
     c->state = ST_PRECOND;
+    c->block_ge = false;
     return GENP_OK;
 }
 
-int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
+static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bool block) {
     CK(check_ctx(c));
     if (c->state != ST_PRECOND) return GENP_ESTATE;
     if (!(pivot_tol >= 0.0)) return GENP_EINVAL;
+    if (block) {
+        if (c->prec != GENP_F64) return GENP_ENOTSUP;
+        if (!c->perm && hipMalloc(&c->perm, c->n_pad * sizeof(int)) != hipSuccess) return GENP_ENOMEM;
+        HIPCK(launch_iota(c->perm, (int)c->n_pad, c->stream));
+    }
+    c->block_ge = block;
     const int64_t nb = c->nb, np = c->n_pad, ldc = c->ldc;
     const int lp = c->prec != GENP_F64;
     const size_t es = esize(c->prec);
@@ -863,7 +891,13 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         const int64_t k = j * nb;
         const int nvalid = (int)std::max<int64_t>(0, std::min<int64_t>(nb, c->n - k));
         HIPCK(hipEventRecord(ev(j, 2), st));
-        if (c->diag_split && c->prec == GENP_F64 && nb == 256)
+        if (block) {
+            // the block pivot with interchanges inside it, then the same interchanges on the
+            // rest of its block row (L of earlier steps to the left, A12 to the right)
+            HIPCK(launch_diag_lu_piv((double*)at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j,
+                                     c->perm + k, st));
+            HIPCK(launch_block_row_perm((double*)c->C, ldc, k, (int)nb, (int)np, c->perm + k, st));
+        } else if (c->diag_split && c->prec == GENP_F64 && nb == 256)
             HIPCK(launch_diag_lu_split(at(k, k), ldc, nvalid, k, maxc, pivot_tol, c->stats + j, st));
         else
             HIPCK(launch_diag_lu(c->prec, at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
@@ -1052,6 +1086,13 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         }
     }
     c->info.breakdown_col = bad >= 0 ? bad + 1 : 0;
+    c->info.block_ge = block ? 1 : 0;
+    c->info.row_swaps = 0;
+    if (block) {
+        std::vector<int> pr(np);
+        HIPCK(hipMemcpy(pr.data(), c->perm, np * sizeof(int), hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < np; ++r) c->info.row_swaps += pr[r] != r;
+    }
     c->info.min_abs_piv = mn;
     c->info.max_abs_piv = mx;
     c->info.max_abs_u = bits_to_double(mu);
@@ -1062,6 +1103,37 @@ int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
         return GENP_BREAKDOWN;
     }
     c->state = ST_FACTORED;
+    return GENP_OK;
+}
+
+int genp_factor(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
+    return factor_impl(c, pivot_tol, breakdown_col, false);
+}
+
+int genp_factor_block(genp_ctx* c, double pivot_tol, int64_t* breakdown_col) {
+    return factor_impl(c, pivot_tol, breakdown_col, true);
+}
+
+int genp_block_pivots(const genp_ctx* cc, double* out, int64_t ldo) {
+    genp_ctx* c = const_cast<genp_ctx*>(cc);
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    if (c->prec != GENP_F64) return GENP_ENOTSUP;
+    if (!out || ldo < c->nb) return GENP_EINVAL;
+    HIPCK(launch_block_pivots((const double*)c->C, c->ldc, (int)c->n, (int)c->nb, c->block_ge ? c->perm : nullptr,
+                              out, ldo, c->stream));
+    return GENP_OK;
+}
+
+int genp_row_perm(const genp_ctx* cc, int32_t* perm) {
+    genp_ctx* c = const_cast<genp_ctx*>(cc);
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED && c->state != ST_BROKEN) return GENP_ESTATE;
+    if (!perm) return GENP_EINVAL;
+    if (c->block_ge)
+        HIPCK(hipMemcpyAsync(perm, c->perm, c->n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    else
+        HIPCK(launch_iota(perm, (int)c->n, c->stream));
     return GENP_OK;
 }
 

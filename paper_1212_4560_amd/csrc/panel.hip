@@ -34,16 +34,31 @@ __device__ inline double readlane_d(double v, int lane) {
 //  3. the trailing block takes the rank-16 Schur update (Fact 2.1) on the
 //     matrix cores: 16 x 16 tiles, 8 per wave per batch of loads, operands from
 //     LDS (the panel below the diagonal and the new rows of U).
-template <typename T>
+//
+// PIV: block Gaussian elimination with the diagonal block as the block pivot (Theorem 2.2):
+// rows are interchanged inside the block, at each column the row with the largest |entry|
+// among the block's remaining rows (the first on ties) becomes the pivot row.  The panel's
+// interchanges are made in wave 0's registers, then on the block's other columns (net row
+// movement, all loads before any store, one column per thread), and the block's net
+// permutation is written to perm: factor row r comes from row perm[r] (global index).
+template <typename T, bool PIV>
 __global__ void __launch_bounds__(256)
 diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long col0,
-               const double* __restrict__ maxc, double pivot_tol, PanelStats* __restrict__ st) {
+               const double* __restrict__ maxc, double pivot_tol, PanelStats* __restrict__ st,
+               int* __restrict__ perm) {
     __shared__ double Ls[MAXNB][PW + 1];        // panel rows kb.. (row r - kb), 16 columns
     __shared__ double Rs[PW][MAXNB - PW + 1];   // rows kb..kb+15 of U right of the panel
+    __shared__ int sw[MAXNB];                   // PIV: row interchanged with row r at step r
+    __shared__ int ptmp[MAXNB];                 // PIV: the current panel's net row movement
+    __shared__ int bperm[MAXNB];                // PIV: the block's net permutation so far
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double tol_abs = pivot_tol * maxc[0];
     double s_min = INFINITY, s_max = 0.0;
     long long s_bad = -1;
+    if (PIV) {
+        bperm[tid] = tid;
+        __syncthreads();
+    }
     for (int kb = 0; kb < nb; kb += PW) {
         const int rows = nb - kb;
         if (wave == 0) {
@@ -56,6 +71,51 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
             }
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
+                if (PIV) {
+                    int q = c;
+                    if (kb + c < nvalid) {
+                        double best = -1.0;
+                        int bi = 1 << 30;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int r = s * 64 + lane;
+                            const double a = fabs(p[s][c]);
+                            if (r >= c && kb + r < nvalid && a > best) {
+                                best = a;
+                                bi = r;
+                            }
+                        }
+#pragma unroll
+                        for (int off = 32; off >= 1; off >>= 1) {
+                            const double ob = __shfl_xor(best, off);
+                            const int oi = __shfl_xor(bi, off);
+                            if (ob > best || (ob == best && oi < bi)) {
+                                best = ob;
+                                bi = oi;
+                            }
+                        }
+                        q = __builtin_amdgcn_readfirstlane(bi);
+                        if (q >= rows) q = c;   // no candidate (a column of NaN): keep the row
+                    }
+                    if (lane == 0) sw[kb + c] = kb + q;
+                    if (q != c) {
+                        // exchange panel rows c (lane c, slot 0) and q (lane q % 64, slot q / 64)
+                        const int qs = q >> 6, ql = q & 63;
+#pragma unroll
+                        for (int t = 0; t < PW; ++t) {
+                            const double rc = readlane_d(p[0][t], c);
+                            const double v = qs == 0 ? p[0][t] : qs == 1 ? p[1][t] : qs == 2 ? p[2][t] : p[3][t];
+                            const double rq = readlane_d(v, ql);
+                            if (lane == ql) {
+                                if (qs == 0) p[0][t] = rc;
+                                else if (qs == 1) p[1][t] = rc;
+                                else if (qs == 2) p[2][t] = rc;
+                                else p[3][t] = rc;
+                            }
+                            if (lane == c) p[0][t] = rq;
+                        }
+                    }
+                }
                 // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
                 double prow[PW];
 #pragma unroll
@@ -95,6 +155,39 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
             }
         }
         __syncthreads();
+        if (PIV) {
+            ptmp[tid] = tid;
+            __syncthreads();
+            if (tid == 0) {
+                for (int c = 0; c < PW; ++c) {
+                    const int a = kb + c, b = sw[kb + c];
+                    int t = ptmp[a];
+                    ptmp[a] = ptmp[b];
+                    ptmp[b] = t;
+                    t = bperm[a];
+                    bperm[a] = bperm[b];
+                    bperm[b] = t;
+                }
+            }
+            __syncthreads();
+            // rows that move: kb..kb+15 and the rows they were exchanged with
+            const int j = tid;
+            if (j < nb && (j < kb || j >= kb + PW)) {
+                double v[2 * PW];
+#pragma unroll
+                for (int i = 0; i < 2 * PW; ++i) {
+                    const int q = i < PW ? kb + i : sw[kb + i - PW];
+                    const int src = ptmp[q];
+                    v[i] = src != q ? (double)D[(long long)src * ldd + j] : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 2 * PW; ++i) {
+                    const int q = i < PW ? kb + i : sw[kb + i - PW];
+                    if (ptmp[q] != q) D[(long long)q * ldd + j] = (T)v[i];
+                }
+            }
+            __syncthreads();
+        }
         const int ncols = rows - PW;
         if (ncols > 0) {
             if (tid < ncols) {
@@ -165,6 +258,7 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
         st->max_abs = s_max;
         st->first_bad = s_bad;
     }
+    if (PIV && tid < nb) perm[tid] = (int)(col0 + bperm[tid]);
 }
 
 // GENP of a 128 x 128 FP64 block held in LDS for the whole elimination (the same steps as
@@ -288,11 +382,113 @@ hipError_t launch_diag_lu(int prec, void* Dblk, long long ldd, int nb, int nvali
                           const double* maxc, double pivot_tol, PanelStats* st, hipStream_t s) {
     if (nb <= 0 || nb > MAXNB || nb % PW) return hipErrorInvalidValue;   // nb: multiple of 16, <= 256
     if (prec == PREC_F64)
-        hipLaunchKernelGGL(diag_lu_kernel<double>, dim3(1), dim3(256), 0, s, (double*)Dblk, ldd, nb,
-                           nvalid, col0, maxc, pivot_tol, st);
+        hipLaunchKernelGGL((diag_lu_kernel<double, false>), dim3(1), dim3(256), 0, s, (double*)Dblk, ldd, nb,
+                           nvalid, col0, maxc, pivot_tol, st, nullptr);
     else
-        hipLaunchKernelGGL(diag_lu_kernel<float>, dim3(1), dim3(256), 0, s, (float*)Dblk, ldd, nb,
-                           nvalid, col0, maxc, pivot_tol, st);
+        hipLaunchKernelGGL((diag_lu_kernel<float, false>), dim3(1), dim3(256), 0, s, (float*)Dblk, ldd, nb,
+                           nvalid, col0, maxc, pivot_tol, st, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_lu_piv(double* Dblk, long long ldd, int nb, int nvalid, long long col0, const double* maxc,
+                              double pivot_tol, PanelStats* st, int* perm, hipStream_t s) {
+    if (nb <= 0 || nb > MAXNB || nb % PW || !perm) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((diag_lu_kernel<double, true>), dim3(1), dim3(256), 0, s, Dblk, ldd, nb, nvalid, col0, maxc,
+                       pivot_tol, st, perm);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Rows row0 .. row0 + nb - 1 of C take their block's interchanges in every column outside the
+// diagonal block: row r becomes the former row perm[r] (global index, inside the block).  One
+// workgroup per 32 columns: the block's rows are staged in LDS, then written back permuted.
+constexpr int RP_COLS = 32;
+__global__ void __launch_bounds__(256)
+block_row_perm_kernel(double* __restrict__ C, long long ldc, long long row0, int nb, int ncols,
+                      const int* __restrict__ perm) {
+    __shared__ double tile[MAXNB][RP_COLS + 1];
+    const long long c0 = (long long)blockIdx.x * RP_COLS;
+    if (c0 >= row0 && c0 + RP_COLS <= row0 + nb) return;   // inside the diagonal block: nothing to do
+    const int cl = threadIdx.x & (RP_COLS - 1), rg = threadIdx.x / RP_COLS;
+    const long long col = c0 + cl;
+    const bool in = col < ncols && !(col >= row0 && col < row0 + nb);
+    for (int r = rg; r < nb; r += 256 / RP_COLS) tile[r][cl] = in ? C[(row0 + r) * ldc + col] : 0.0;
+    __syncthreads();
+    for (int r = rg; r < nb; r += 256 / RP_COLS) {
+        const int src = (int)(perm[r] - row0);
+        if (in && src != r) C[(row0 + r) * ldc + col] = tile[src][cl];
+    }
+}
+
+// The explicit block pivots B_k = P_k^T L_kk U_kk: factor row i of block k (rows k0 .. k0+w-1,
+// w = min(nb, n - k0)) gives row perm[i] of the output (row i when perm is null).  One
+// workgroup per row, one thread per column; columns w .. nb-1 of a ragged last block are 0.
+__global__ void __launch_bounds__(256)
+block_pivots_kernel(const double* __restrict__ C, long long ldc, int n, int nb, const int* __restrict__ perm,
+                    double* __restrict__ out, long long ldo) {
+    const int i = blockIdx.x;
+    const int k0 = (i / nb) * nb, r = i - k0, w = min(nb, n - k0);
+    const int j = threadIdx.x;
+    if (j >= nb) return;
+    double s = 0.0;
+    if (j < w) {
+        // (L U)(r, j) = sum over t <= min(r, j) of L(r, t) U(t, j), with L(r, r) = 1
+        const double* Lr = C + (long long)(k0 + r) * ldc + k0;
+        const double* Ub = C + (long long)k0 * ldc + k0 + j;
+        const int tmax = r <= j ? r : j + 1;
+        for (int t = 0; t < tmax; ++t) s = fma(Lr[t], Ub[(long long)t * ldc], s);
+        if (r <= j) s += Lr[j];
+    }
+    const long long orow = perm ? perm[i] : i;
+    out[orow * ldo + j] = s;
+}
+
+__global__ void permute_rows_kernel(int n, int k, const double* __restrict__ src, long long lds,
+                                    double* __restrict__ dst, long long ldd, const int* __restrict__ perm,
+                                    int scatter) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n * k) return;
+    const int i = (int)(idx / k), b = (int)(idx % k);
+    if (scatter) dst[(long long)perm[i] * ldd + b] = src[(long long)i * lds + b];
+    else dst[(long long)i * ldd + b] = src[(long long)perm[i] * lds + b];
+}
+
+__global__ void iota_kernel(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+}  // namespace
+
+hipError_t launch_block_row_perm(double* C, long long ldc, long long row0, int nb, int ncols, const int* perm,
+                                 hipStream_t s) {
+    if (nb <= 0 || nb > MAXNB || ncols <= 0 || row0 < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(block_row_perm_kernel, dim3((ncols + RP_COLS - 1) / RP_COLS), dim3(256), 0, s, C, ldc, row0,
+                       nb, ncols, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_pivots(const double* C, long long ldc, int n, int nb, const int* perm, double* out,
+                               long long ldo, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (nb <= 0 || nb > MAXNB || ldo < nb) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(block_pivots_kernel, dim3(n), dim3((nb + 63) / 64 * 64), 0, s, C, ldc, n, nb, perm, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_rows(int n, int k, const double* src, long long lds, double* dst, long long ldd,
+                               const int* perm, int scatter, hipStream_t s) {
+    const long long tot = (long long)n * k;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, k, src, lds,
+                       dst, ldd, perm, scatter);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

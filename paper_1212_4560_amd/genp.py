@@ -34,6 +34,7 @@ SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 
 # the entry points declared in include/genp.h
 EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",
+           "genp_factor_block", "genp_block_pivots", "genp_row_perm",
            "genp_lowrank", "genp_numerical_rank",
            "genp_refine", "genp_solve_backward", "genp_get_info", "genp_copy_work", "genp_strerror")
 
@@ -56,6 +57,7 @@ class GenpInfo(ctypes.Structure):
         ("n_schur", ctypes.c_int32),
         ("cond_g", ctypes.c_double),
         ("mult_left", ctypes.c_int32), ("cond_h", ctypes.c_double),
+        ("block_ge", ctypes.c_int32), ("row_swaps", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -117,6 +119,9 @@ def load(path: str = LIB_PATH):
     L.genp_lowrank.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, dbl, dbl, vp, i64, vp, i64, vp, i64,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(GenpLrInfo), vp]
     L.genp_factor.argtypes = [vp, dbl, ctypes.POINTER(i64)]
+    L.genp_factor_block.argtypes = [vp, dbl, ctypes.POINTER(i64)]
+    L.genp_block_pivots.argtypes = [vp, vp, i64]
+    L.genp_row_perm.argtypes = [vp, vp]
     L.genp_solve.argtypes = [vp, vp, i64, i64, vp, i64]
     L.genp_refine.argtypes = [vp, vp, i64, i64, vp, i64, i32, dbl, i32, ctypes.POINTER(dbl)]
     L.genp_solve_backward.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp, i64, i32]
@@ -167,6 +172,7 @@ class Solver:
         import torch
         L = load()
         self.n = int(n)
+        self.nb = int(nb)
         self.prec = prec
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -230,12 +236,29 @@ class Solver:
         self._keep = (A, right[1], left)
         return self
 
-    def factor(self, pivot_tol: float = 0.0) -> int:
-        """Blocked GENP; returns the 1-based breakdown column (0 = none)."""
+    def factor(self, pivot_tol: float = 0.0, block: bool = False) -> int:
+        """Blocked GENP, or with block=True block Gaussian elimination with row
+        interchanges inside each diagonal block pivot (genp_factor_block); returns the
+        1-based breakdown column (0 = none)."""
         bk = ctypes.c_int64(0)
-        _check(load().genp_factor(self._h, float(pivot_tol), ctypes.byref(bk)), "genp_factor",
-               allow=(OK, BREAKDOWN))
+        name = "genp_factor_block" if block else "genp_factor"
+        _check(getattr(load(), name)(self._h, float(pivot_tol), ctypes.byref(bk)), name, allow=(OK, BREAKDOWN))
         return int(bk.value)
+
+    def block_pivots(self):
+        """The explicit block pivots B_k stacked by rows: an n x nb FP64 tensor."""
+        import torch
+        out = torch.empty((self.n, self.nb), dtype=torch.float64, device="cuda")
+        o, ldo = _mat(out, "out", self.n, self.nb)
+        _check(load().genp_block_pivots(self._h, o, ldo), "genp_block_pivots")
+        return out
+
+    def row_perm(self):
+        """Row r of the factors is row perm[r] of C (int32 tensor of n)."""
+        import torch
+        perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(load().genp_row_perm(self._h, ctypes.c_void_p(perm.data_ptr())), "genp_row_perm")
+        return perm
 
     def solve(self, B, X=None):
         import torch
@@ -288,16 +311,18 @@ class Solver:
 
 
 def solve(A, B, G=None, p=None, prec: str = "f64", nb: int = 256, refine: int = 2,
-          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir", c=None, uv=None, left=None):
+          tol: float = 0.0, pivot_tol: float = 0.0, solver: str = "luir", c=None, uv=None, left=None,
+          block: bool = False):
     """The whole path: C = H A G, GENP, substitutions, X = G Y, refinement.
     The right multiplier: dense G, Toeplitz parameters p, circulant first column c or
     Householder parameters uv; the left one: left = (kind, tensor) or None.
+    block=True factors by block Gaussian elimination with explicit block pivots.
 
     Returns (X, info dict, solver object).  Raises GenpError on breakdown.
     """
     s = Solver(A.shape[0], prec, nb)
     s.precondition(A, G=G, p=p, c=c, uv=uv, left=left)
-    bk = s.factor(pivot_tol)
+    bk = s.factor(pivot_tol, block=block)
     if bk:
         raise GenpError(BREAKDOWN, f"genp_factor (column {bk})")
     X = s.solve(B)
