@@ -90,6 +90,63 @@ def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
     return res
 
 
+def block_ge_measure(w, args, f64_ms: float) -> dict:
+    """The benchmark workload factored by block Gaussian elimination with explicit block
+    pivots (Theorem 2.2): row interchanges inside each nb x nb diagonal block.  One warm-up,
+    then `steps` timed whole-path steps; the explicit block pivots of the last step give
+    max_k ||B_k||_2 and max_k ||B_k^{-1}||_2 (host SVDs, outside the timed region)."""
+    import numpy as np
+    import torch
+    from paper_1212_4560_amd import genp
+    n, k = w.A.shape[0], w.nrhs
+    stream = torch.cuda.current_stream()
+    s = genp.Solver(n, "f64", args.nb, stream=stream)
+    X = torch.empty((n, k), dtype=torch.float64, device="cuda")
+
+    def step():
+        s.precondition(w.A, p=w.p)
+        if s.factor(0.0, block=True):
+            raise RuntimeError("block Gaussian elimination: singular block pivot")
+        s.solve(w.B, X)
+        s.refine(w.B, X, args.max_refine, args.tol, args.solver)
+        return s.info()
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    e0.record(stream)
+    for _ in range(args.steps):
+        infos.append(step())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    last = infos[-1]
+    Bk = s.block_pivots().cpu().numpy()
+    nb = args.nb
+    sv = [np.linalg.svd(Bk[r:r + nb, :min(nb, n - r)], compute_uv=False) for r in range(0, n, nb)]
+    eta_orc = None
+    if not args.no_host_check:
+        from oracle import genp as og
+        eta_orc = float(np.max(og.backward_error_inf(w.A.cpu().numpy(), X.cpu().numpy(), w.B.cpu().numpy())))
+    flops = method_flops(n, k, max(i["iters"] for i in infos))
+    res = {"workload": args.workload, "n": n, "nrhs": k, "ms_per_step": round(ms, 3),
+           "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+           "stage_ms": {"precondition": round(last["ms_precond"], 3), "factor": round(last["ms_factor"], 3),
+                        "solve": round(last["ms_solve"], 3), "refine": round(last["ms_refine"], 3)},
+           "refine_steps": [i["iters"] for i in infos], "eta_lib": max(i["eta"] for i in infos),
+           "eta_oracle": eta_orc, "row_swaps": last["row_swaps"],
+           "max_block_pivot_norm2": float(max(v[0] for v in sv)),
+           "max_block_pivot_inv_norm2": float(max(1.0 / v[-1] for v in sv)),
+           "ratio_to_genp_path": round(ms / f64_ms, 3)}
+    log(f"[bench] block GE: {ms:.1f} ms per step (factor {last['ms_factor']:.1f} ms), eta {res['eta_lib']:.2e}, "
+        f"{last['row_swaps']} rows moved, max ||B_k|| {res['max_block_pivot_norm2']:.3g}, "
+        f"max ||B_k^-1|| {res['max_block_pivot_inv_norm2']:.3g}")
+    del s, X
+    torch.cuda.empty_cache()
+    return res
+
+
 def structured_comparison(args, n: int, f64_ms: float, kind: str) -> dict:
     """The same recipe with a structured multiplier applied in fewer than 2n^3 flops instead of
     the Toeplitz product: a Gaussian circulant (Definition 3.2, by FFT) or a +-1 Householder-type
@@ -334,6 +391,8 @@ def main() -> int:
     ap.add_argument("--no-circulant", action="store_true",
                     help="skip the structured-multiplier comparisons (circulant by FFT, Householder)")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank approximation measurement")
+    ap.add_argument("--no-block-ge", action="store_true",
+                    help="skip the block Gaussian elimination (explicit block pivots) measurement")
     ap.add_argument("--table-7-2", type=int, default=0, metavar="TRIALS",
                     help="only run the experiments of Tables 7.2 / 7.3 (low-rank approximation) and print one JSON line")
     ap.add_argument("--table-7-1", type=int, default=0, metavar="TRIALS",
@@ -459,6 +518,8 @@ def main() -> int:
     roof["traffic"] = traffic_if_current(n)
     if not args.no_mixed and args.prec == "f64":
         out["mixed"] = mixed_comparison(w, args, ms_per_step, value)
+    if not args.no_block_ge and args.prec == "f64":
+        out["block_ge"] = block_ge_measure(w, args, ms_per_step)
     if not args.no_circulant and args.prec == "f64":
         del w
         torch.cuda.empty_cache()

@@ -24,6 +24,39 @@ __device__ inline double readlane_d(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Wave-wide max (doubles) and min (ints) with DPP moves: shifts by 1, 2, 4, 8 inside each row
+// of 16 lanes leave a row's result in its lane 15; the row broadcasts of lanes 15 and 31 then
+// bring the whole wave's into lane 63, which is read out.  A lane with no source keeps its own
+// value.
+template <int CTRL, int ROWS>
+__device__ inline int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ inline double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, ROWS>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL, ROWS>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double wave_max_d(double v) {
+    v = fmax(v, dpp_d<0x111, 0xf>(v));
+    v = fmax(v, dpp_d<0x112, 0xf>(v));
+    v = fmax(v, dpp_d<0x114, 0xf>(v));
+    v = fmax(v, dpp_d<0x118, 0xf>(v));
+    v = fmax(v, dpp_d<0x142, 0xa>(v));
+    v = fmax(v, dpp_d<0x143, 0xc>(v));
+    return readlane_d(v, 63);
+}
+__device__ inline int wave_min_i(int v) {
+    v = min(v, dpp_i<0x111, 0xf>(v));
+    v = min(v, dpp_i<0x112, 0xf>(v));
+    v = min(v, dpp_i<0x114, 0xf>(v));
+    v = min(v, dpp_i<0x118, 0xf>(v));
+    v = min(v, dpp_i<0x142, 0xa>(v));
+    v = min(v, dpp_i<0x143, 0xc>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // One workgroup of 256 threads (one wave per SIMD), FP64 arithmetic for either
 // storage type.  For each 16-column panel:
 //  1. wave 0 factors the panel alone, with no barrier: lane l holds rows
@@ -69,57 +102,75 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
 #pragma unroll
                 for (int c = 0; c < PW; ++c) p[s][c] = (r < rows) ? (double)D[(long long)(kb + r) * ldd + kb + c] : 0.0;
             }
+            // PIV: the panel's rows stay in their registers; pos[s] is the current position of
+            // the row in slot s (LAPACK's interchange order: at step c the chosen row takes
+            // position c and the row that held position c takes the chosen row's place) and
+            // done[s] marks rows already taken as pivot rows.  Rows are written back at their
+            // final positions.  Without PIV, pos[s] = r and pivot row c sits in lane c, slot 0.
+            int pos[4];
+            bool done[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                pos[s] = s * 64 + lane;
+                done[s] = false;
+            }
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
+                double prow[PW];
                 if (PIV) {
-                    int q = c;
+                    // pivot: the largest |entry| of column c among the rows not yet taken (valid
+                    // rows only; a NaN counts below every number), the smallest position on ties
+                    int q = c, qpos = c;   // pad columns: the pad row at position c, never moved
                     if (kb + c < nvalid) {
                         double best = -1.0;
-                        int bi = 1 << 30;
+                        int bp = 1 << 30, bi = c;
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
                             const int r = s * 64 + lane;
                             const double a = fabs(p[s][c]);
-                            if (r >= c && kb + r < nvalid && a > best) {
-                                best = a;
+                            const double key = a == a ? a : -0.5;
+                            if (!done[s] && kb + r < nvalid && (key > best || (key == best && pos[s] < bp))) {
+                                best = key;
+                                bp = pos[s];
                                 bi = r;
                             }
                         }
-#pragma unroll
-                        for (int off = 32; off >= 1; off >>= 1) {
-                            const double ob = __shfl_xor(best, off);
-                            const int oi = __shfl_xor(bi, off);
-                            if (ob > best || (ob == best && oi < bi)) {
-                                best = ob;
-                                bi = oi;
-                            }
+                        const double m = wave_max_d(best);
+                        unsigned long long hold = __ballot(best == m);
+                        if (__popcll(hold) > 1) {
+                            // several lanes hold the maximum: keep those with the smallest position
+                            const int mp = wave_min_i(best == m ? bp : 1 << 30);
+                            hold = __ballot(best == m && bp == mp);
                         }
-                        q = __builtin_amdgcn_readfirstlane(bi);
-                        if (q >= rows) q = c;   // no candidate (a column of NaN): keep the row
+                        const int wl = __builtin_ctzll(hold);
+                        q = __builtin_amdgcn_readlane(bi, wl);
+                        qpos = __builtin_amdgcn_readlane(bp, wl);
                     }
-                    if (lane == 0) sw[kb + c] = kb + q;
-                    if (q != c) {
-                        // exchange panel rows c (lane c, slot 0) and q (lane q % 64, slot q / 64)
-                        const int qs = q >> 6, ql = q & 63;
+                    if (lane == 0) sw[kb + c] = kb + qpos;
+                    const int qs = q >> 6, ql = q & 63;
 #pragma unroll
-                        for (int t = 0; t < PW; ++t) {
-                            const double rc = readlane_d(p[0][t], c);
-                            const double v = qs == 0 ? p[0][t] : qs == 1 ? p[1][t] : qs == 2 ? p[2][t] : p[3][t];
-                            const double rq = readlane_d(v, ql);
-                            if (lane == ql) {
-                                if (qs == 0) p[0][t] = rc;
-                                else if (qs == 1) p[1][t] = rc;
-                                else if (qs == 2) p[2][t] = rc;
-                                else p[3][t] = rc;
-                            }
-                            if (lane == c) p[0][t] = rq;
+                    for (int s = 0; s < 4; ++s) {
+                        if (pos[s] == c) pos[s] = qpos;
+                        if (s == qs && lane == ql) {
+                            pos[s] = c;
+                            done[s] = true;
                         }
                     }
+                    auto get = [&](const double (&row)[PW]) {
+#pragma unroll
+                        for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(row[t], ql) : 0.0;
+                    };
+                    switch (qs) {
+                        case 0: get(p[0]); break;
+                        case 1: get(p[1]); break;
+                        case 2: get(p[2]); break;
+                        default: get(p[3]); break;
+                    }
+                } else {
+                    // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
+#pragma unroll
+                    for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(p[0][t], c) : 0.0;
                 }
-                // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
-                double prow[PW];
-#pragma unroll
-                for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(p[0][t], c) : 0.0;
                 const double piv = prow[c];
                 if (lane == 0 && kb + c < nvalid) {
                     const double a = fabs(piv);
@@ -133,7 +184,7 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int r = s * 64 + lane;
-                    if (r > c && r < rows) {
+                    if ((PIV ? !done[s] : r > c) && r < rows) {
                         const double l = p[s][c] * rp;
                         p[s][c] = l;
 #pragma unroll
@@ -148,28 +199,29 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                 if (r < rows) {
 #pragma unroll
                     for (int c = 0; c < PW; ++c) {
-                        D[(long long)(kb + r) * ldd + kb + c] = (T)p[s][c];
-                        Ls[r][c] = p[s][c];
+                        D[(long long)(kb + pos[s]) * ldd + kb + c] = (T)p[s][c];
+                        Ls[pos[s]][c] = p[s][c];
+                    }
+                }
+            }
+            if (PIV) {
+                // the panel's net row movement (ptmp: new position -> old position) and the
+                // block's permutation so far, from the rows' final positions
+                int ob[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) ob[s] = s * 64 + lane < rows ? bperm[kb + s * 64 + lane] : 0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = s * 64 + lane;
+                    if (r < rows) {
+                        ptmp[kb + pos[s]] = kb + r;
+                        bperm[kb + pos[s]] = ob[s];
                     }
                 }
             }
         }
         __syncthreads();
         if (PIV) {
-            ptmp[tid] = tid;
-            __syncthreads();
-            if (tid == 0) {
-                for (int c = 0; c < PW; ++c) {
-                    const int a = kb + c, b = sw[kb + c];
-                    int t = ptmp[a];
-                    ptmp[a] = ptmp[b];
-                    ptmp[b] = t;
-                    t = bperm[a];
-                    bperm[a] = bperm[b];
-                    bperm[b] = t;
-                }
-            }
-            __syncthreads();
             // rows that move: kb..kb+15 and the rows they were exchanged with
             const int j = tid;
             if (j < nb && (j < kb || j >= kb + PW)) {

@@ -222,3 +222,21 @@ def test_errors():
         s.block_pivots()
     with pytest.raises(genp.GenpError):
         s.row_perm()
+
+
+def test_ties_follow_the_interchange_order():
+    """Rows of a Sylvester Hadamard matrix shuffled inside each block: every column of every
+    block pivot has many entries of equal magnitude, and every value is a power of two, so
+    both sides compute exactly and must take the same row at every tie (the first in the
+    current row order): factors and permutation bit for bit."""
+    import scipy.linalg as sl
+    n, nb = 256, 64
+    g = np.random.default_rng(3)
+    P = np.concatenate([k + g.permutation(nb) for k in range(0, n, nb)])
+    C = sl.hadamard(n).astype(np.float64)[P]
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(dev(C))
+    assert s.factor(0.0, block=True) == 0
+    res = obg.block_ge(C, nb)
+    assert np.array_equal(host(s.row_perm()).astype(np.int64), res.perm)
+    assert np.array_equal(host(s.work()), res.LU)

@@ -214,3 +214,17 @@ def test_mutant_is_caught(name, monkeypatch):
 
 def test_checks_pass_on_the_oracle():
     assert all(_checks())
+
+
+def test_hadamard_rows_factor_exactly():
+    # powers of two throughout: P C = L U holds without rounding, |L| in {0, 1}
+    import scipy.linalg as sl
+    n, nb = 128, 32
+    g = np.random.default_rng(3)
+    P = np.concatenate([k + g.permutation(nb) for k in range(0, n, nb)])
+    C = sl.hadamard(n).astype(np.float64)[P]
+    res = obg.block_ge(C, nb)
+    L, U = og.unpack(res.LU)
+    assert res.breakdown_col == 0
+    assert np.array_equal(C[res.perm], L @ U)
+    assert set(np.unique(np.abs(np.tril(L, -1)))) <= {0.0, 1.0}
