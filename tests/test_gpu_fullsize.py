@@ -74,6 +74,59 @@ def test_fullsize_n16384_toeplitz_sampled():
     assert np.all(eta_o <= 1e-14)
 
 
+def test_fullsize_n16384_block_ge_sampled():
+    """Block Gaussian elimination at the benchmark size: the permutation stays inside the
+    blocks, (P C)_ij = c_{perm[i], j} against (L U)_ij at sampled entries, the explicit block
+    pivots against L_kk U_kk of the same factors, and the refined solution's backward error."""
+    print("full size n=16384 block GE: building inputs", flush=True)
+    w = wl.make("c3_n16384_haar1e6_toeplitz", device="cuda")
+    n, nb = w.n, 256
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(w.A, p=w.p)
+    rng = np.random.default_rng(1)
+    I = rng.integers(0, n, 96)
+    J = rng.integers(0, n, 96)
+    C = s.work()
+    print("  factor_block", flush=True)
+    assert s.factor(0.0, block=True) == 0
+    perm = host(s.row_perm()).astype(np.int64)
+    assert np.array_equal(np.sort(perm.reshape(-1, nb), axis=1), np.arange(n).reshape(-1, nb))
+    Cs = host(C[torch.as_tensor(perm[I], device="cuda"), torch.as_tensor(J, device="cuda")])
+    del C
+    LU = s.work()
+    rows = host(LU[torch.as_tensor(I, device="cuda")])
+    colsU = host(LU[:, torch.as_tensor(J, device="cuda")])
+    del LU
+    for t, (i, j) in enumerate(zip(I, J)):
+        li = rows[t].copy()
+        li[i] = 1.0
+        li[i + 1:] = 0.0
+        uj = colsU[:, t].copy()
+        uj[j + 1:] = 0.0
+        m = min(i, j) + 1
+        prod = li[:m] @ uj[:m]
+        bound = 10 * og.gamma(n) * (np.abs(li[:m]) @ np.abs(uj[:m]))
+        assert abs(Cs[t] - prod) <= bound + 2 * og.gamma(n) * abs(Cs[t])
+    print("  P C = L U sampled entries ok; block pivots", flush=True)
+    Bk = s.block_pivots()
+    for k in rng.integers(0, n // nb, 3):
+        r0 = int(k) * nb
+        D = host(s.work()[r0:r0 + nb, r0:r0 + nb])
+        L = np.tril(D, -1) + np.eye(nb)
+        U = np.triu(D)
+        ref = np.empty((nb, nb))
+        ref[perm[r0:r0 + nb] - r0] = L @ U
+        got = host(Bk[r0:r0 + nb])
+        assert np.max(np.abs(got - ref)) <= 10 * og.gamma(nb) * np.max(np.abs(L) @ np.abs(U))
+    print("  block pivots ok; solve + refine", flush=True)
+    X = s.solve(w.B)
+    st, eta = s.refine(w.B, X, 2, 1e-14)
+    assert st == genp.OK
+    eta_o = og.backward_error_inf(host(w.A), host(X), host(w.B))
+    print(f"  eta library {max(eta):.2e} oracle {eta_o.max():.2e}", flush=True)
+    assert np.all(eta_o <= 1e-14)
+
+
 def test_fullsize_n4096_dense_whole_path():
     print("full size n=4096 dense, 16 RHS", flush=True)
     w = wl.make("c2_n4096_haar1e4_dense")
