@@ -469,7 +469,7 @@ def main() -> int:
         infos.append(inf)
         ag_ms.append(inf["ms_ag"])
         log(f"[bench] step {i}: precond {inf['ms_precond']:.1f} (A*G {inf['ms_ag']:.1f}) factor "
-            f"{inf['ms_factor']:.1f} (update pairs {inf['ms_schur']:.1f}, panels {inf['ms_panel']:.1f}) solve "
+            f"{inf['ms_factor']:.1f} (update groups {inf['ms_schur']:.1f}, panels {inf['ms_panel']:.1f}) solve "
             f"{inf['ms_solve']:.1f} refine {inf['ms_refine']:.1f} ms; it={inf['iters']} inner={inf['inner_iters']} "
             f"eta={inf['eta']:.2e}")
     ev1.record(stream)
@@ -506,7 +506,7 @@ def main() -> int:
                    "multiplier": w.mult, "smax": w.smax, "refine_tol": args.tol},
         "eta_lib": eta_lib, "eta_oracle": eta_orc, "refine_steps": its,
         "stage_ms": {"precondition": round(last["ms_precond"], 3), "ag_gemm": round(last["ms_ag"], 3),
-                     "factor": round(last["ms_factor"], 3), "update_pairs": round(last["ms_schur"], 3),
+                     "factor": round(last["ms_factor"], 3), "update_groups": round(last["ms_schur"], 3),
                      "panels": round(last["ms_panel"], 3), "solve": round(last["ms_solve"], 3),
                      "refine": round(last["ms_refine"], 3)},
         "growth": last["growth"], "wall_s": round(wall, 2),

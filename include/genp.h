@@ -104,12 +104,12 @@ typedef struct {
     double eta_hist[GENP_ETA_HIST]; /* eta before each refinement step and at the end     */
     double ms_precond, ms_factor, ms_solve, ms_refine, ms_backward; /* HIP-event times   */
     double ms_ag;               /* the C = A G product kernel alone (last genp_precondition) */
-    double ms_schur;            /* last genp_factor: sum over its step pairs of the main-stream
-                                   interval from the pair's first Schur update to its last
+    double ms_schur;            /* last genp_factor: sum over its step groups of the main-stream
+                                   interval from the group's first Schur update to its last
                                    block solve (updates, plus the block solves between them) */
     double ms_panel;            /* sum over panels of diagonal-block LU start to block-solve
                                    end (overlaps the updates)                                 */
-    int32_t n_schur;            /* number of step pairs summed in ms_schur                   */
+    int32_t n_schur;            /* number of step groups summed in ms_schur                  */
     double cond_g;              /* 2-norm condition number of G when it is known cheaply:
                                    circulant: max_f |DFT(c)[f]| / min_f |DFT(c)[f]| (exact, the
                                    circulant being normal, Theorem 2.1); Householder:

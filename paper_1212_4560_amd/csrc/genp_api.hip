@@ -91,6 +91,10 @@ struct genp_ctx {
     unsigned* tsync = nullptr;
     bool trsv_chain = true;
     bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
+    // steps per group of the factorization: g_big while the trailing matrix has at least
+    // g_switch rows, then g_small
+    int g_big = 3, g_small = 2;
+    int64_t g_switch = 8192;
     // block Gaussian elimination: rows interchanged inside the diagonal blocks, P C = L U;
     // factor row r came from row perm[r] of C (n_pad entries)
     bool block_ge = false;
@@ -720,6 +724,17 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
     if (ok) {
         const char* la = getenv("GENP_LOOKAHEAD");
         c->lookahead = !(la && la[0] == '0');
+        const char* gg = getenv("GENP_GROUP");  // "g" or "g_big,rows,g_small"
+        if (gg) {
+            int g1 = 0, g2 = 0;
+            long long sw = 0;
+            const int nf = sscanf(gg, "%d,%lld,%d", &g1, &sw, &g2);
+            if (nf >= 1 && g1 >= 1 && g1 <= 8) c->g_big = c->g_small = g1;
+            if (nf == 3 && g2 >= 1 && g2 <= 8 && sw >= 0) {
+                c->g_switch = sw;
+                c->g_small = g2;
+            }
+        }
         const char* tv = getenv("GENP_TRSV");   // "step": one launch per block instead of the chained solve
         c->trsv_chain = !(tv && strcmp(tv, "step") == 0);
         const char* dg = getenv("GENP_DIAG");   // "single": one workgroup per 256 diagonal block
@@ -994,17 +1009,19 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         return GENP_OK;
     };
     ev_begin(c, EV_FAC);
-    // Steps go in pairs (a, a+1) so that the bulk of the trailing matrix takes both
-    // Schur updates as one product with K = 2 nb.  Invariant at the top of the loop:
-    // panels a and a+1 are factored, and the trailing block from row/column (a+2) nb
-    // has every update before step a.  Per pair, on the main stream: updates a, a+1 on
-    // the next two block columns and rows; the first half of the bulk update; the block
-    // solves of panel a+2; update a+2 on block a+3; the second half of the bulk; the
-    // block solves of panel a+3.  The two diagonal-block factorizations (one workgroup
-    // each) run on the side stream, each under one half of the bulk.  The block solves
-    // need the whole GPU for a short time, so they run between the halves rather than
-    // beside them.  Without look-ahead the same products run in the same order on one
-    // stream (identical values).
+    // Steps go in groups of g so that the bulk of the trailing matrix takes the g Schur
+    // updates as one product with K = g nb.  Invariant at the top of the loop for the group
+    // of steps a .. a+g-1: their panels are factored, and the trailing block from
+    // row/column (a+g) nb has every update before step a.  The next gn panels form the
+    // look-ahead region.  Per group, on the main stream: updates a .. a+g-1 on the region's
+    // block columns and rows; then for each region panel j, one of gn column parts of the
+    // bulk update, the block solves of panel j and the update of step j on the rest of the
+    // region.  The diagonal-block factorizations (one workgroup each) run on the side
+    // stream, each under one part of the bulk.  The block solves need the whole GPU for a
+    // short time, so they run between the parts rather than beside them.  Groups are large
+    // (g_big) while the bulk is large and smaller (g_small) near the end, where the chain
+    // of diagonal blocks and block solves is the critical path.  Without look-ahead the
+    // same products run in the same order on one stream (identical values).
     hipStream_t PS = c->lookahead ? P : S;
     auto diag_async = [&](int64_t j, int e_after) -> int {
         // diagonal block j on the side stream once the main stream reaches this point
@@ -1020,33 +1037,45 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         if (PS != S) HIPCK(hipStreamWaitEvent(S, ev(j, 5), 0));
         return GENP_OK;
     };
+    auto group_size = [&](int64_t a) -> int64_t {
+        const int64_t g = np - a * nb >= c->g_switch ? c->g_big : c->g_small;
+        return std::max<int64_t>(1, std::min<int64_t>(g, K - a));
+    };
+    // step j's update on the rest of the region that ends at block column e: block columns
+    // j+1 .. e-1 (all rows below) and block rows j+1 .. e-1 (all columns right of the region)
+    auto region_update = [&](int64_t j, int64_t e) -> int {
+        const int64_t r = (j + 1) * nb, w = (e - j - 1) * nb;
+        if (w <= 0) return GENP_OK;
+        return schur_two(j, r, r, np - r, w, r, e * nb, w, np - e * nb, S);
+    };
+    std::vector<int64_t> gstart;
+    int64_t a = 0, g = group_size(0);
     CK(panel(0, S));
-    if (K > 1) {
-        CK(schur_two(0, nb, nb, np - nb, nb, nb, 2 * nb, nb, np - 2 * nb, S));
-        CK(panel(1, S));
+    for (int64_t i = 1; i < g; ++i) {
+        CK(region_update(i - 1, g));
+        CK(panel(i, S));
     }
-    for (int64_t a = 0; a + 2 < K; a += 2) {
-        const int64_t r2 = (a + 2) * nb, m = np - r2;
-        const int64_t nb2 = std::min<int64_t>(2, K - (a + 2));   // panels in the next pair
-        const int64_t w = nb2 * nb;
+    while (a + g < K) {
+        const int64_t a2 = a + g, gn = group_size(a2);
+        const int64_t r2 = a2 * nb, m = np - r2;
+        const int64_t w = gn * nb;
         const int64_t rb = r2 + w, mb = m - w;                   // the bulk: rows/cols rb.. (mb of them)
-        const int64_t n1 = (mb / 2 + nb - 1) / nb * nb;          // its first column half
+        const int64_t bb = mb / nb;                              // its block columns, split into gn parts
         HIPCK(hipEventRecord(ev(a, 0), S));
-        CK(schur_two(a, r2, r2, m, w, r2, r2 + w, w, m - w, S, 2));
-        CK(diag_async(a + 2, 4));
-        CK(schur(a, rb, rb, mb, n1, S, 2));
-        CK(wait_diag(a + 2));
-        CK(solves(a + 2, S));
-        if (nb2 == 2) {
-            CK(schur_two(a + 2, r2 + nb, r2 + nb, m - nb, nb, r2 + nb, r2 + 2 * nb, nb, m - 2 * nb, S));
-            CK(diag_async(a + 3, 4));
-        }
-        CK(schur(a, rb, rb + n1, mb, mb - n1, S, 2));
-        if (nb2 == 2) {
-            CK(wait_diag(a + 3));
-            CK(solves(a + 3, S));
+        gstart.push_back(a);
+        CK(schur_two(a, r2, r2, m, w, r2, r2 + w, w, m - w, S, (int)g));
+        for (int64_t i = 0; i < gn; ++i) {
+            const int64_t j = a2 + i;
+            const int64_t c0 = rb + (bb * i / gn) * nb, c1 = rb + (bb * (i + 1) / gn) * nb;
+            CK(diag_async(j, 4));
+            CK(schur(a, rb, c0, mb, c1 - c0, S, (int)g));
+            CK(wait_diag(j));
+            CK(solves(j, S));
+            CK(region_update(j, a2 + gn));
         }
         HIPCK(hipEventRecord(ev(a, 1), S));
+        a = a2;
+        g = gn;
     }
     HIPCK(launch_max_abs(c->prec, c->C, ldc, (int)c->n, (int)c->n, 1, c->red + R_MAXU, c->stream));
     ev_end(c, EV_FAC);
@@ -1064,7 +1093,7 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         float t0 = 0.f;
         if (hipEventElapsedTime(&t0, c->ev_step[6 * b + 2], c->ev_step[6 * b + 3]) == hipSuccess) ms_p += t0;
     }
-    for (int64_t a = 0; a + 2 < nblk; a += 2) {
+    for (int64_t a : gstart) {
         float t1 = 0.f;
         if (hipEventElapsedTime(&t1, c->ev_step[6 * a], c->ev_step[6 * a + 1]) == hipSuccess) {
             ms_s += t1;
