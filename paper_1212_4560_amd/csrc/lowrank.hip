@@ -31,24 +31,6 @@ struct LrState {
     double tail;   // ||remaining columns||_F when stopped
 };
 
-// sum of squares of A in per-block partials (fixed order)
-__global__ void __launch_bounds__(256) sumsq_part_kernel(int m, int n, const double* __restrict__ A, long long lda,
-                                                         double* __restrict__ part) {
-    __shared__ double red[256];
-    double acc = 0.0;
-    for (int i = blockIdx.x; i < m; i += gridDim.x) {
-        const double* a = A + (long long)i * lda;
-        for (int j = threadIdx.x; j < n; j += 256) acc = fma(a[j], a[j], acc);
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
 // out[0] = sum of the np partials (one block, fixed order)
 __global__ void __launch_bounds__(256) sum_kernel(int np, const double* __restrict__ part, double* __restrict__ out) {
     __shared__ double red[256];
@@ -84,11 +66,14 @@ __global__ void toeplitz_expand_kernel(int m, int k, const double* __restrict__ 
 //   EPI 1: residual: the tile of R - A B is squared and summed into part[block], and A B is
 //          stored into D (ld ldd) when D is not null.
 // Workgroup: WGM x WGN waves.
-template <bool AT, bool BT, int EPI, int WGM, int WGN, int NT = 4>
+//   SQ (EPI 0, with the whole of N in one tile column, so each element of A is loaded once
+//       over the grid): the squares of the A entries the workgroup multiplies are summed into
+//       sq[blockIdx.y * gridDim.x + blockIdx.x] (the Frobenius norm of A in the same pass).
+template <bool AT, bool BT, int EPI, int WGM, int WGN, int NT = 4, int DEPTH = 2, bool SQ = false>
 __global__ void __launch_bounds__(64 * WGM * WGN, NT >= 4 ? 1 : 2)   // two waves per SIMD where they fit
 lr_mfma_kernel(int M, int N, int K, int kchunk, const double* __restrict__ A, long long lda,
                const double* __restrict__ B, long long ldb, double* __restrict__ D, long long ldd,
-               const double* __restrict__ R, long long ldr, double* __restrict__ part) {
+               const double* __restrict__ R, long long ldr, double* __restrict__ part, double* __restrict__ sq) {
     // NT: 16-column MFMA tiles per wave (a wave covers 64 x 16 NT outputs)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -104,7 +89,8 @@ lr_mfma_kernel(int M, int N, int K, int kchunk, const double* __restrict__ A, lo
     // Rows of A past M and columns of B past N are read at clamped indices and feed only
     // outputs that are not stored.  Full 8-deep chunks use plain base-plus-offset loads; a
     // final partial chunk clamps k on A and relies on B being zero past K (the caller pads B).
-    double ra[2][4][2], rb[2][NT][2];
+    // DEPTH register buffers: DEPTH - 1 chunks of loads in flight while one is multiplied
+    double ra[DEPTH][4][2], rb[DEPTH][NT][2];
     int ic[4], jc[NT];
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) ic[mi] = min(m0 + mi * 16 + lr, M - 1);
@@ -156,7 +142,8 @@ lr_mfma_kernel(int M, int N, int K, int kchunk, const double* __restrict__ A, lo
             for (int ni = 0; ni < NT; ++ni) rb[0][ni][s] = BT ? B[(long long)jc[ni] * ldb + k] : B[(long long)k * ldb + jc[ni]];
         }
     };
-    auto mma = [&](int buf) {
+    double ss = 0.0;   // SQ: sum of squares of the A entries of this lane (unclamped only)
+    auto mma = [&](int buf, bool tail = false, int koff = 0) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -164,6 +151,16 @@ lr_mfma_kernel(int M, int N, int K, int kchunk, const double* __restrict__ A, lo
 #pragma unroll
                 for (int ni = 0; ni < NT; ++ni)
                     acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[buf][mi][s], rb[buf][ni][s], acc[mi][ni], 0, 0, 0);
+        if (SQ) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) {
+                    const bool ok = m0 + mi * 16 + lr < M && (!tail || kl + koff + s < ke);
+                    const double x = ra[buf][mi][s];
+                    ss = ok ? fma(x, x, ss) : ss;
+                }
+        }
     };
     const bool live = m0 < M && n0 < N;
     // EPI 1: the tile of R is loaded first, so that its latency hides behind the products
@@ -181,35 +178,72 @@ lr_mfma_kernel(int M, int N, int K, int kchunk, const double* __restrict__ A, lo
     }
     if (live) {
         // full chunks: branch-free steady state (the waits before each MFMA then cover only
-        // its own buffer), two register buffers alternating
+        // its own buffer), DEPTH register buffers in rotation: buffer b % DEPTH holds chunk b
         const int nf = (ke - kb) / 8;
-        if (nf > 0) load(0, 0);
-        int c = 0;
-        for (; c + 3 <= nf; c += 2) {
-            load(1, (c + 1) * 8);
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_sched_barrier(0);
-            mma(0);
-            __builtin_amdgcn_sched_barrier(0);
-            load(0, (c + 2) * 8);
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_sched_barrier(0);
-            mma(1);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (c + 2 == nf) {
-            load(1, (c + 1) * 8);
-            mma(0);
-            mma(1);
-        } else if (c + 1 == nf) {
-            mma(0);
+        if constexpr (DEPTH == 2) {
+            if (nf > 0) load(0, 0);
+            int c = 0;
+            for (; c + 3 <= nf; c += 2) {
+                load(1, (c + 1) * 8);
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                mma(0);
+                __builtin_amdgcn_sched_barrier(0);
+                load(0, (c + 2) * 8);
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                mma(1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (c + 2 == nf) {
+                load(1, (c + 1) * 8);
+                mma(0);
+                mma(1);
+            } else if (c + 1 == nf) {
+                mma(0);
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b + 1 < DEPTH; ++b)
+                if (b < nf) load(b, b * 8);
+            int c = 0;
+            for (; c + 2 * DEPTH - 1 <= nf; c += DEPTH) {
+#pragma unroll
+                for (int b = 0; b < DEPTH; ++b) {
+                    load((b + DEPTH - 1) % DEPTH, (c + b + DEPTH - 1) * 8);
+                    asm volatile("" ::: "memory");
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma(b);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // the last (fewer than 2 DEPTH - 1) chunks, each load only if its chunk exists
+#pragma unroll
+            for (int t = 0; t < 2 * DEPTH - 2; ++t) {
+                if (c + t < nf) {
+                    if (c + t + DEPTH - 1 < nf) load((t + DEPTH - 1) % DEPTH, (c + t + DEPTH - 1) * 8);
+                    mma(t % DEPTH);
+                }
+            }
         }
         if ((ke - kb) % 8) {
             load_tail(nf * 8);
-            mma(0);
+            mma(0, true, nf * 8);
         }
     }
     if (EPI == 0) {
+        if (SQ) {
+            __shared__ double sqs[WGM * WGN];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off);
+            if (lane == 0) sqs[wave] = ss;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+                for (int w = 0; w < WGM * WGN; ++w) t += sqs[w];
+                sq[(long long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+            }
+        }
         if (!live) return;
         double* Dp = D + (long long)blockIdx.y * M * ldd;
 #pragma unroll
@@ -417,9 +451,11 @@ __global__ void lr_init_kernel(int k, int* perm, LrState* st) {
 
 // D (M x 64, ld 64) = op(A) (M x K) * B (K x 64, ld 64) on the matrix cores, split over K so that
 // about 1024 workgroups run; partials in `part` (ks x M x 64), then their fixed-order sum.
+// With sq (AT only): the sum of squares of A's entries in *nsq per-workgroup partials at sq
+// (at most 16 ceil(M / 256)).
 template <bool AT>
 hipError_t skinny_mfma(int M, int K, int N, const double* A, long long lda, const double* B, double* D, double* part,
-                       long long part_cap, hipStream_t s) {
+                       long long part_cap, hipStream_t s, double* sq = nullptr, int* nsq = nullptr) {
     // N <= 64 columns of B and D (ld 64) in 16-column MFMA tiles
     const int tiles = (M + 255) / 256;
     long long ks = std::max(1, std::min(16, (1024 + tiles - 1) / tiles));
@@ -430,9 +466,14 @@ hipError_t skinny_mfma(int M, int K, int N, const double* A, long long lda, cons
     ks = (K + kchunk - 1) / kchunk;
     const int nt = (N + 15) / 16;
 #define LR_SKINNY(NTV)                                                                                              \
-    hipLaunchKernelGGL((lr_mfma_kernel<AT, false, 0, 4, 1, NTV>), dim3(tiles, (unsigned)ks), dim3(256), 0, s, M, N, K, \
-                       kchunk, A, lda, B, (long long)LR_MAXK, part, (long long)LR_MAXK, (const double*)nullptr, 0LL,  \
-                       (double*)nullptr)
+    if (AT && sq)                                                                                                   \
+        hipLaunchKernelGGL((lr_mfma_kernel<AT, false, 0, 4, 1, NTV, (NTV <= 2 ? 4 : 2), true>),                     \
+                           dim3(tiles, (unsigned)ks), dim3(256), 0, s, M, N, K, kchunk, A, lda, B, (long long)LR_MAXK, \
+                           part, (long long)LR_MAXK, (const double*)nullptr, 0LL, (double*)nullptr, sq);            \
+    else                                                                                                            \
+        hipLaunchKernelGGL((lr_mfma_kernel<AT, false, 0, 4, 1, NTV, (NTV <= 2 ? 4 : 2)>), dim3(tiles, (unsigned)ks), \
+                           dim3(256), 0, s, M, N, K, kchunk, A, lda, B, (long long)LR_MAXK, part, (long long)LR_MAXK, \
+                           (const double*)nullptr, 0LL, (double*)nullptr, (double*)nullptr)
     switch (nt) {
         case 1: LR_SKINNY(1); break;
         case 2: LR_SKINNY(2); break;
@@ -442,6 +483,7 @@ hipError_t skinny_mfma(int M, int K, int N, const double* A, long long lda, cons
 #undef LR_SKINNY
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (nsq) *nsq = tiles * (int)ks;
     return launch_splitk_reduce_f64(M, N, (int)ks, part, LR_MAXK, (long long)M * LR_MAXK, 1.0, 0.0, nullptr, 0, D,
                                     LR_MAXK, s);
 }
@@ -613,7 +655,7 @@ extern "C" int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, 
     const int np = (N + CG_ROWS - 1) / CG_ROWS;
     const int rt_m = (M + 127) / 128, rt_n = (N + 63) / 64;   // residual: 128 x 64 workgroup tiles
     const long long nres = (long long)rt_m * rt_n;
-    const int nsq = std::min(M, 2048);
+    const long long nsq = 16LL * ((N + 255) / 256);   // sum-of-squares partials of the sketch
     // G64 and T64 are B operands: rows padded with zeros to a multiple of 16
     const size_t Mp = ((size_t)M + 15) / 16 * 16, Np = ((size_t)N + 15) / 16 * 16;
     if (!sc.get(&G64, Mp * LR_MAXK) || !sc.get(&T64, Np * LR_MAXK) || !sc.get(&W64, (size_t)M * LR_MAXK) ||
@@ -636,10 +678,7 @@ extern "C" int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, 
     } eg{ev};
     auto blocks = [](long long tot) { return dim3((unsigned)((tot + 255) / 256)); };
     LR_HIP(hipEventRecord(ev[0], s));
-    // ||A||_F^2
-    hipLaunchKernelGGL(sumsq_part_kernel, dim3(nsq), dim3(256), 0, s, M, N, A, (long long)lda, rpart);
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, nsq, rpart, scal);
-    // Stage 1: T' = A^T G (64 columns, zero beyond rho_+)
+    // Stage 1: T' = A^T G (64 columns, zero beyond rho_+), and ||A||_F^2 from the same pass
     const double* Gs = G;
     long long ldgs = ldg;
     if (mult == GENP_G_TOEPLITZ) {
@@ -651,7 +690,9 @@ extern "C" int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, 
     hipLaunchKernelGGL(pad_cols_kernel, blocks((long long)M * LR_MAXK), dim3(256), 0, s, M, K, Gs, ldgs, G64);
     LR_HIP(hipMemsetAsync(T64, 0, Np * LR_MAXK * sizeof(double), s));
     LR_HIP(hipMemsetAsync(W64, 0, (size_t)M * LR_MAXK * sizeof(double), s));
-    LR_HIP(skinny_mfma<true>(N, M, K, A, lda, G64, T64, part, part_cap, s));
+    int nsqp = 0;
+    LR_HIP(skinny_mfma<true>(N, M, K, A, lda, G64, T64, part, part_cap, s, rpart, &nsqp));
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, nsqp, rpart, scal);
     LR_HIP(hipEventRecord(ev[1], s));
     // Stage 2: pivoted Gram-Schmidt, each projection applied twice
     hipLaunchKernelGGL(lr_init_kernel, dim3(1), dim3(LR_MAXK), 0, s, K, perm, st);
@@ -678,7 +719,8 @@ extern "C" int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, 
         const int ntn = (N + 63) / 64;
         const unsigned g = (unsigned)((long long)((M + 127) / 128) * ntn);
         hipLaunchKernelGGL((lr_mfma_kernel<false, true, 1, 2, 2, 2>), dim3(g, 1), dim3(256), 0, s, M, N, kres, kres, W64,
-                           (long long)LR_MAXK, T64, (long long)LR_MAXK, Ahat, (long long)ldah, A, (long long)lda, rpart);
+                           (long long)LR_MAXK, T64, (long long)LR_MAXK, Ahat, (long long)ldah, A, (long long)lda, rpart,
+                           (double*)nullptr);
     }
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, (int)nres, rpart, scal + 1);   // nres = rt_m * rt_n
     hipLaunchKernelGGL(copy_cols_kernel, blocks((long long)N * K), dim3(256), 0, s, N, K, T64, T, (long long)ldt);

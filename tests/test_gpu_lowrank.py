@@ -128,6 +128,7 @@ def test_fullsize_n16384():
     print(f"  rank {r['rank']}, ms {info['ms_total']:.2f} (sketch {info['ms_sketch']:.2f}, basis "
           f"{info['ms_basis']:.2f}, project {info['ms_project']:.2f}, resid {info['ms_resid']:.2f})", flush=True)
     assert r["rank"] == q and not info["failed"]
+    assert np.isclose(info["a_fro"], float(torch.linalg.norm(A)), rtol=1e-12)
     T = host(r["T"])
     assert np.allclose(T.T @ T, np.eye(q), atol=1e-13)
     I = g.integers(0, n, 64)
