@@ -288,14 +288,23 @@ lr_mfma_kernel(int M, int N, int K, int kchunk, const double* __restrict__ A, lo
 // A workgroup owns 64 rows; thread (ty, c) handles column c of rows ty, ty + 4, ...  Every
 // workgroup reduces the previous launch's per-workgroup partials itself, in the same fixed
 // order, so all of them take the same pivot and stop decisions.
-constexpr int CG_ROWS = 256;
+constexpr int CG_ROWS = 64;   // rows per workgroup (at most 256)
 
 // sum over the np per-workgroup partials of column c, four threads per column, fixed order
 __device__ inline void cg_reduce(int np, const double* __restrict__ part, double* out /* LDS[64] */,
                                  double* scratch /* LDS[4][64] */) {
     const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
     double s = 0.0;
-    for (int p = q; p < np; p += 4) s += part[(long long)p * LR_MAXK + c];
+    int p = q;
+    // partials q, q + 4, q + 8, ... summed in that order, eight loads in flight at a time
+    for (; p + 28 < np; p += 32) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = part[(long long)(p + 4 * i) * LR_MAXK + c];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += v[i];
+    }
+    for (; p < np; p += 4) s += part[(long long)p * LR_MAXK + c];
     scratch[q * LR_MAXK + c] = s;
     __syncthreads();
     if (q == 0) out[c] = (scratch[c] + scratch[LR_MAXK + c]) + (scratch[2 * LR_MAXK + c] + scratch[3 * LR_MAXK + c]);
@@ -367,7 +376,7 @@ __global__ void __launch_bounds__(256) cg_step_a_kernel(int n, int np, int k, in
     const double scale = 1.0 / sqrt(nrm[p]);
     // swap and scale this workgroup's rows (one thread per row)
     const int r = blockIdx.x * CG_ROWS + threadIdx.x;
-    if (r < n) {
+    if (threadIdx.x < CG_ROWS && r < n) {
         double* row = T + (long long)r * LR_MAXK;
         const double a = row[p], b = row[k];
         row[k] = a * scale;
