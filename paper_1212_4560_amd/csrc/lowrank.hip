@@ -512,10 +512,27 @@ struct NrOut {
     double cond_at_rank, cond_above;
 };
 
+// Sum over the 64 lanes (all active) with DPP moves, the same in every lane: shifts by 1, 2, 4, 8
+// inside each row of 16 lanes (a lane with no source adds 0) leave each row's sum in its lane
+// 15; the row broadcasts of lanes 15 and 31 then carry the totals into lane 63, which is read.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_or_zero(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ inline double wave_sum64(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_or_zero<0x111, 0xf>(v);
+    v += dpp_or_zero<0x112, 0xf>(v);
+    v += dpp_or_zero<0x114, 0xf>(v);
+    v += dpp_or_zero<0x118, 0xf>(v);
+    v += dpp_or_zero<0x142, 0xa>(v);
+    v += dpp_or_zero<0x143, 0xc>(v);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // eigenvalues < x of the tridiagonal (al[0..k), be[0..k-1)) from the pivots of T - x I
