@@ -269,6 +269,9 @@ gemm_f64_kernel(GemmF64Args g) {
 // without staging through LDS.  The loop body has no branches, so the waits the compiler
 // places before each MFMA only cover the buffer that MFMA reads.
 //
+// DEPTH register buffers rotate: C = A G (K = n) keeps two chunks of loads in flight (three
+// buffers, 248 VGPRs; 0.7 % faster than two at n = 16384), the Schur updates (K <= 768) one.
+//
 // WMW = 4 (8 waves, one workgroup per CU) keeps the waves that share a CU's matrix units in
 // one workgroup.  With two 4-wave workgroups per CU the older one takes the units first, the
 // two drift apart along K, and the workgroups of a tile-row stop meeting in L2: for C = A G
@@ -282,7 +285,7 @@ typedef const double __attribute__((address_space(1)))* gcd_ptr;   // global (no
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef const f64x2 __attribute__((address_space(1)))* gcd2_ptr;
 
-template <bool TOEP, int WMW>
+template <bool TOEP, int WMW, int DEPTH = 2>
 __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
     constexpr int BMt = 64 * WMW;
     constexpr int KS = 2;   // k values per lane group per chunk; chunk depth 4 * KS = 8
@@ -325,7 +328,7 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double ra[2][4][KS], rb[2][4][KS];
+    double ra[DEPTH][4][KS], rb[DEPTH][4][KS];
     auto load = [&](int buf, int k0) {
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi) {
@@ -351,24 +354,55 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
     // The empty asm statements keep the compiler from sinking each batch of loads down to
     // its first use; the scheduling barriers keep the MFMAs from moving above the loads.
     const int nk = g.K / (4 * KS);   // even
-    load(0, 0);
-    for (int c = 0; c < nk - 2; c += 2) {
-        load(1, (c + 1) * 4 * KS);
+    if constexpr (DEPTH == 3) {
+        // three buffers in rotation (buffer c % 3 holds chunk c): two chunks of loads in flight
+        load(0, 0);
+        load(1, 4 * KS);
+        int c = 0;
+        for (; c + 5 <= nk; c += 3) {
+            load(2, (c + 2) * 4 * KS);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(0, (c + 3) * 4 * KS);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(1);
+            __builtin_amdgcn_sched_barrier(0);
+            load(1, (c + 4) * 4 * KS);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (c + t < nk) {
+                if (c + t + 2 < nk) load((t + 2) % 3, (c + t + 2) * 4 * KS);
+                mma(t % 3);
+            }
+        }
+    } else {
+        load(0, 0);
+        for (int c = 0; c < nk - 2; c += 2) {
+            load(1, (c + 1) * 4 * KS);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(0, (c + 2) * 4 * KS);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        load(1, (nk - 1) * 4 * KS);
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         mma(0);
         __builtin_amdgcn_sched_barrier(0);
-        load(0, (c + 2) * 4 * KS);
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
-        mma(1);
-        __builtin_amdgcn_sched_barrier(0);
     }
-    load(1, (nk - 1) * 4 * KS);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    mma(0);
-    __builtin_amdgcn_sched_barrier(0);
     // Epilogue: D = alpha acc + beta Cin, one 16-row strip at a time, with the loads of the
     // next strip of Cin in flight while a strip is stored: the first strip's loads go out
     // before the last chunk's MFMAs, into the registers the first buffer has freed.  Each
@@ -385,7 +419,7 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
     if (rd) load_c(0, 0);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    mma(1);
+    if constexpr (DEPTH == 2) mma(1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
@@ -403,7 +437,7 @@ __device__ __forceinline__ void gemm_regs_body(const GemmF64Args& g) {
 }
 
 // C = A G with the Toeplitz G generated from its parameters
-__global__ void __launch_bounds__(512, 1) gemm_ag_toep_kernel(GemmF64Args g) { gemm_regs_body<true, 4>(g); }
+__global__ void __launch_bounds__(512, 1) gemm_ag_toep_kernel(GemmF64Args g) { gemm_regs_body<true, 4, 3>(g); }
 
 // D = alpha A B + beta Cin, A and B row-major (the Schur complement updates), 128 x 128
 // workgroups.  (256 x 128 workgroups run a lone update 6 % faster at M = N = 15872, but
