@@ -240,3 +240,21 @@ def test_ties_follow_the_interchange_order():
     res = obg.block_ge(C, nb)
     assert np.array_equal(host(s.row_perm()).astype(np.int64), res.perm)
     assert np.array_equal(host(s.work()), res.LU)
+
+
+@pytest.mark.parametrize("n,nb", [(1, 64), (5, 64), (65, 64), (130, 128)])
+def test_tiny_and_ragged_block_pivots(n, nb):
+    """Fewer rows than one block, one row past a block, a ragged last block: the interchanges
+    stay inside the valid rows (the padding is never chosen) and the solution is exact to
+    rounding."""
+    g = np.random.default_rng(300 + n)
+    C = g.standard_normal((n, n))
+    b = g.standard_normal((n, 1))
+    s = genp.Solver(n, "f64", nb)
+    s.precondition(dev(C))
+    assert s.factor(0.0, block=True) == 0
+    res = obg.block_ge(C, nb)
+    _check_factors(s, C, res, nb)
+    X = s.solve(dev(b))
+    s.refine(dev(b), X, 2)
+    assert np.max(og.backward_error_inf(C, host(X), b)) <= 1e-14
