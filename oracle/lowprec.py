@@ -11,8 +11,14 @@ used here are:
 * a product of BF16 operands is exact in FP64 (8-bit significands), so
   ``product_of_rounded`` gives the exact value the MFMA sums approximate.
 
+* the 2-word BF16 form splits an FP32 value x into hi = bf16(x) and
+  lo = bf16(x - hi) (x - hi is exact in FP32: hi shares x's leading bits) and
+  takes a product of split operands as hi_a hi_b + hi_a lo_b + lo_a hi_b,
+  dropping lo_a lo_b; ``product_bf16x3`` gives the exact value of those three
+  terms.
+
 ``genp_blocked_lowprec`` is an FP32 block elimination with optionally
-BF16-rounded Schur-update operands.  It mirrors the kind of factorization the
+BF16-rounded (or 2-word BF16) Schur-update operands.  It mirrors the kind of factorization the
 mixed form computes, not its bits: parity unpinned for intermediate bits (the
 MFMA accumulation order is not specified anywhere); tests use it only for
 statistics (growth, factor residual) and bounds.
@@ -54,9 +60,26 @@ def product_of_rounded(A, B, rounder) -> np.ndarray:
     return rounder(A) @ rounder(B)
 
 
-def genp_blocked_lowprec(C, nb: int, bf16_update: bool = False):
+def split_bf16x2(x):
+    """(hi, lo) with hi = bf16(fp32(x)) and lo = bf16(fp32(x) - hi), as float64 values."""
+    x32 = round_fp32(x)
+    hi = round_bf16(x32)
+    lo = round_bf16(x32 - hi)
+    return hi, lo
+
+
+def product_bf16x3(A, B) -> np.ndarray:
+    """hi_A hi_B + hi_A lo_B + lo_A hi_B in FP64: the three products the 2-word BF16
+    form accumulates (each term exact in FP64)."""
+    ha, la = split_bf16x2(A)
+    hb, lb = split_bf16x2(B)
+    return ha @ hb + (ha @ lb + la @ hb)
+
+
+def genp_blocked_lowprec(C, nb: int, bf16_update: bool = False, bf16x3_update: bool = False):
     """FP32 block GENP; with bf16_update the Schur-update operands L21 and U12
-    are rounded to BF16 before the FP32 product (parity unpinned: statistics only)."""
+    are rounded to BF16 before the FP32 product, with bf16x3_update the update is the
+    2-word BF16 product (parity unpinned: statistics only)."""
     from scipy.linalg import solve_triangular
 
     LU = np.array(C, dtype=np.float32, copy=True)
@@ -74,6 +97,9 @@ def genp_blocked_lowprec(C, nb: int, bf16_update: bool = False):
             LU[k:e, e:] = solve_triangular(L11, LU[k:e, e:], lower=True,
                                            unit_diagonal=True).astype(np.float32)
             L21, U12 = LU[e:, k:e], LU[k:e, e:]
+            if bf16x3_update:
+                LU[e:, e:] -= product_bf16x3(L21, U12).astype(np.float32)
+                continue
             if bf16_update:
                 L21 = round_bf16(L21).astype(np.float32)
                 U12 = round_bf16(U12).astype(np.float32)

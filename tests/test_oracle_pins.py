@@ -630,3 +630,40 @@ def test_left_and_two_sided_multipliers_solve_the_system():
     Hm = g.standard_normal((m, m))
     res, LU, info = og.genp_solve(w.A, w.B, np.eye(m), refine_steps=2, tol=1e-14, pivot_tol=m * og.U64, H=Hm)
     assert info.breakdown_col == 0 and res.eta_hist[-1] <= 1e-14
+
+
+def test_bf16x2_split_pieces_and_error():
+    # hi and lo are BF16 values; hi + lo reproduces fp32(x) to 2^-16 relative (two 8-bit
+    # significands); the three-term product misses only lo_a lo_b and the split errors
+    g = np.random.default_rng(41)
+    x = g.standard_normal(4000) * np.exp(g.uniform(-20, 20, 4000))
+    hi, lo = lowprec.split_bf16x2(x)
+    assert np.array_equal(lowprec.round_bf16(hi), hi) and np.array_equal(lowprec.round_bf16(lo), lo)
+    x32 = lowprec.round_fp32(x)
+    assert np.all(np.abs(x32 - hi) <= 2.0 ** -8 * np.abs(x32))
+    assert np.all(np.abs(x32 - (hi + lo)) <= 2.0 ** -16 * np.abs(x32))
+    A, B = g.standard_normal((60, 70)), g.standard_normal((70, 50))
+    P = lowprec.product_bf16x3(A, B)
+    ref = lowprec.round_fp32(A) @ lowprec.round_fp32(B)
+    scale = np.abs(A) @ np.abs(B)
+    assert np.all(np.abs(P - ref) <= 3 * 2.0 ** -16 * scale)
+    # and it is a much better product than single BF16 operands
+    single = lowprec.product_of_rounded(A, B, lowprec.round_bf16)
+    assert np.max(np.abs(P - ref)) < 1e-2 * np.max(np.abs(single - ref))
+
+
+def test_bf16x3_mirror_factor_residual_between_bf16_and_fp32():
+    g = np.random.default_rng(42)
+    n = 192
+    A, G = g.standard_normal((n, n)), g.standard_normal((n, n))
+    C = og.precondition(A, G)
+
+    def resid(LU):
+        L, U = og.unpack(LU)
+        return np.linalg.norm(C - L @ U) / np.linalg.norm(np.abs(L) @ np.abs(U))
+
+    r32 = resid(lowprec.genp_blocked_lowprec(C, 64))
+    r16 = resid(lowprec.genp_blocked_lowprec(C, 64, bf16_update=True))
+    r3 = resid(lowprec.genp_blocked_lowprec(C, 64, bf16x3_update=True))
+    # two BF16 words carry about 16 significand bits: between FP32 (24) and one BF16 word (8)
+    assert r32 < r3 < r16
