@@ -55,13 +55,13 @@ def traffic_if_current(n: int):
 
 
 def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
-    """The precision form on the same inputs: FP32 and BF16-operand factors with FP64
-    GMRES-IR (restart 50, at most 2 outer steps).  One warm-up, one timed run each."""
+    """The precision form on the same inputs: FP32, BF16-operand and 2-word BF16 factors with
+    FP64 GMRES-IR (restart 50, at most 2 outer steps).  One warm-up, one timed run each."""
     import torch
     from paper_1212_4560_amd import genp
     res = []
     n, k = w.n, w.nrhs
-    for prec in ("f32", "bf16"):
+    for prec in ("f32", "bf16", "bf16x3"):
         s = genp.Solver(n, prec, args.nb)
         X = torch.empty((n, k), dtype=torch.float64, device="cuda")
         stream = torch.cuda.current_stream()

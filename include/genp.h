@@ -49,8 +49,11 @@ typedef struct genp_ctx genp_ctx;
 enum {
     GENP_F64 = 0,   /* FP64 MFMA product and factorization                        */
     GENP_F32 = 1,   /* FP32 MFMA product and factorization, FP32 storage           */
-    GENP_BF16 = 2   /* BF16 operands with FP32 accumulation for A G and the Schur  */
+    GENP_BF16 = 2,  /* BF16 operands with FP32 accumulation for A G and the Schur  */
                     /* updates; panel and triangular blocks in FP32; FP32 storage  */
+    GENP_BF16X3 = 3 /* as GENP_BF16 with 2-word BF16 operands: x = hi + lo,         */
+                    /* hi = bf16(x), lo = bf16(x - hi); a b = hi hi + hi lo + lo hi */
+                    /* (three BF16 MFMA products, about 16 significand bits)        */
 };
 
 /* Kind of multiplier passed to genp_precondition. */
@@ -124,7 +127,7 @@ typedef struct {
 /*
  * Create a context for n x n systems on the current HIP device.
  *   n        >= 1.
- *   prec     GENP_F64 / GENP_F32 / GENP_BF16.
+ *   prec     GENP_F64 / GENP_F32 / GENP_BF16 / GENP_BF16X3.
  *   nb       panel width of the blocked elimination: 64, 128 or 256 (0 = default 256).
  *   stream   hipStream_t to order all work on (NULL = the null stream).
  * Allocates the working matrix (padded to a multiple of nb) and scratch.

@@ -17,7 +17,7 @@ enum OpMode : int {
 };
 
 // Working precisions (mirror of the public enum).
-enum : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+enum : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3 };
 
 // Per-panel pivot statistics written by the diagonal-block kernels.
 struct PanelStats {
@@ -74,7 +74,8 @@ struct GemmLpArgs {
     float alpha, beta;
     const float* Cin; long long ldci;
     float* D; long long ldd;
-    int bf16;                            // 1: round operands to BF16, BF16 MFMA, FP32 accumulate
+    int bf16;                            // 1: round operands to BF16, BF16 MFMA, FP32 accumulate;
+                                         // 2: 2-word BF16 operands, three BF16 MFMA products
 };
 hipError_t launch_gemm_lp(const GemmLpArgs& a, int tile, hipStream_t s);
 

@@ -1,6 +1,9 @@
 // GEMM into FP32 storage on the CDNA matrix cores, for the precision form of
-// the method: C = A G and the Schur updates in FP32 (v_mfma_f32_16x16x4_f32) or
-// with BF16 operands and FP32 accumulation (v_mfma_f32_16x16x32_bf16).
+// the method: C = A G and the Schur updates in FP32 (v_mfma_f32_16x16x4_f32), with
+// BF16 operands and FP32 accumulation (v_mfma_f32_16x16x32_bf16), or with 2-word BF16
+// operands: x = hi + lo, hi = bf16(x), lo = bf16(x - hi) (exact in FP32: hi shares x's
+// leading bits), and a b taken as hi_a hi_b + hi_a lo_b + lo_a hi_b, three BF16 MFMAs
+// per tile (about 16 significand bits instead of 8).
 //
 // D(fp32) = alpha * op(A) op(B) + beta * Cin(fp32).  Operands are FP64 (the
 // caller's A, G or Toeplitz parameters) or FP32 (the working matrix); the
@@ -34,6 +37,8 @@ __device__ inline float ld_op(const void* X, long long ld, int i, int k, int row
     return F64 ? (float)((const double*)X)[idx] : ((const float*)X)[idx];
 }
 
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
 template <bool F64>
 __device__ inline float ld_lin(const void* X, long long idx) {
     return F64 ? (float)((const double*)X)[idx] : ((const float*)X)[idx];
@@ -41,8 +46,10 @@ __device__ inline float ld_lin(const void* X, long long idx) {
 
 // BF16: tiles in LDS as bf16 with k contiguous (As[i][k], Bs[j][k]) so a lane reads
 // its 8 consecutive k values with one 16-byte load.  FP32: As[k][i], Bs[k][j].
-template <int WM, int WN, int AMODE, int BMODE, bool AF64, bool BF64, bool BF16>
-__global__ void __launch_bounds__(64 * WM * WN, 2)
+// X3 (with BF16): 2-word operands, the lo words in their own LDS tiles.
+// One workgroup per CU with X3 (its three products and lo tiles need more than half the registers).
+template <int WM, int WN, int AMODE, int BMODE, bool AF64, bool BF64, bool BF16, bool X3 = false>
+__global__ void __launch_bounds__(64 * WM * WN, X3 ? 1 : 2)
 gemm_lp_kernel(GemmLpArgs g) {
     constexpr int T = 64 * WM * WN;
     constexpr int BMt = 64 * WM, BNt = 64 * WN;
@@ -55,6 +62,8 @@ gemm_lp_kernel(GemmLpArgs g) {
     using ET = typename std::conditional<BF16, unsigned short, float>::type;
     __shared__ __attribute__((aligned(16))) ET As[2][A_SZ];
     __shared__ __attribute__((aligned(16))) ET Bs[2][B_SZ];
+    __shared__ __attribute__((aligned(16))) ET As_lo[X3 ? 2 : 1][X3 ? A_SZ : 8];
+    __shared__ __attribute__((aligned(16))) ET Bs_lo[X3 ? 2 : 1][X3 ? B_SZ : 8];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -103,9 +112,14 @@ gemm_lp_kernel(GemmLpArgs g) {
             rb[r] = v;
         }
     };
-    auto put = [&](ET* arr, int idx, float v) {
-        if constexpr (BF16) arr[idx] = f32_to_bf16_rne(v);
-        else arr[idx] = v;
+    auto put = [&](ET* arr, ET* arr_lo, int idx, float v) {
+        if constexpr (BF16) {
+            const unsigned short h = f32_to_bf16_rne(v);
+            arr[idx] = h;
+            if constexpr (X3) arr_lo[idx] = f32_to_bf16_rne(v - bf16_to_f32(h));
+        } else {
+            arr[idx] = v;
+        }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
@@ -114,7 +128,7 @@ gemm_lp_kernel(GemmLpArgs g) {
             int i, k;
             if (AMODE == OP_N) { i = e / BKL; k = e % BKL; }
             else { k = e / BMt; i = e % BMt; }
-            put(As[buf], BF16 ? i * A_LD + k : k * A_LD + i, ra[r]);
+            put(As[buf], As_lo[X3 ? buf : 0], BF16 ? i * A_LD + k : k * A_LD + i, ra[r]);
         }
 #pragma unroll
         for (int r = 0; r < LBB; ++r) {
@@ -122,7 +136,7 @@ gemm_lp_kernel(GemmLpArgs g) {
             int k, j;
             if (BMODE == OP_T) { j = e / BKL; k = e % BKL; }
             else { k = e / BNt; j = e % BNt; }
-            put(Bs[buf], BF16 ? j * B_LD + k : k * B_LD + j, rb[r]);
+            put(Bs[buf], Bs_lo[X3 ? buf : 0], BF16 ? j * B_LD + k : k * B_LD + j, rb[r]);
         }
     };
 
@@ -159,6 +173,30 @@ gemm_lp_kernel(GemmLpArgs g) {
 #pragma unroll
                     for (int ni = 0; ni < 4; ++ni)
                         acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mi], bfr[ni], acc[mi][ni], 0, 0, 0);
+                if constexpr (X3) {
+                    // hi_a lo_b, then lo_a hi_b
+                    bf16x8 xf[4];
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni) {
+                        const int j = wn * 64 + ni * 16 + lr;
+                        xf[ni] = *reinterpret_cast<const bf16x8*>(&Bs_lo[cur][j * B_LD + lq * 8]);
+                    }
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 4; ++ni)
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mi], xf[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi) {
+                        const int i = wm * 64 + mi * 16 + lr;
+                        xf[mi] = *reinterpret_cast<const bf16x8*>(&As_lo[cur][i * A_LD + lq * 8]);
+                    }
+#pragma unroll
+                    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 4; ++ni)
+                            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf[mi], bfr[ni], acc[mi][ni], 0, 0, 0);
+                }
             } else {
 #pragma unroll
                 for (int kk = 0; kk < BKL; kk += 4) {
@@ -210,22 +248,22 @@ gemm_lp_kernel(GemmLpArgs g) {
     }
 }
 
-template <int AM, int BMd, bool AF64, bool BF64, bool BF16>
+template <int AM, int BMd, bool AF64, bool BF64, bool BF16, bool X3>
 hipError_t launch_t(const GemmLpArgs& a, hipStream_t s) {
     const int ntm = (a.M + 127) / 128, ntn = (a.N + 127) / 128;
-    hipLaunchKernelGGL((gemm_lp_kernel<2, 2, AM, BMd, AF64, BF64, BF16>), dim3(ntm * ntn), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_lp_kernel<2, 2, AM, BMd, AF64, BF64, BF16, X3>), dim3(ntm * ntn), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <bool BF16>
+template <bool BF16, bool X3 = false>
 hipError_t dispatch(const GemmLpArgs& a, hipStream_t s) {
     // the combinations the path uses: A G (FP64 A, dense or Toeplitz FP64 G) and the
     // Schur update (FP32 L21, FP32 U12)
-    if (a.amode == OP_N && a.a_f64 && a.bmode == OP_N && a.b_f64) return launch_t<OP_N, OP_N, true, true, BF16>(a, s);
+    if (a.amode == OP_N && a.a_f64 && a.bmode == OP_N && a.b_f64) return launch_t<OP_N, OP_N, true, true, BF16, X3>(a, s);
     if (a.amode == OP_N && a.a_f64 && a.bmode == OP_TOEP && a.b_f64)
-        return launch_t<OP_N, OP_TOEP, true, true, BF16>(a, s);
+        return launch_t<OP_N, OP_TOEP, true, true, BF16, X3>(a, s);
     if (a.amode == OP_N && !a.a_f64 && a.bmode == OP_N && !a.b_f64)
-        return launch_t<OP_N, OP_N, false, false, BF16>(a, s);
+        return launch_t<OP_N, OP_N, false, false, BF16, X3>(a, s);
     return hipErrorInvalidValue;
 }
 
@@ -234,5 +272,6 @@ hipError_t dispatch(const GemmLpArgs& a, hipStream_t s) {
 hipError_t launch_gemm_lp(const GemmLpArgs& a, int tile, hipStream_t s) {
     (void)tile;
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    if (a.bf16 == 2) return dispatch<true, true>(a, s);
     return a.bf16 ? dispatch<true>(a, s) : dispatch<false>(a, s);
 }

@@ -605,7 +605,7 @@ int right_product(genp_ctx* c, const double* A, int64_t lda) {
     g.beta = 0.f;
     g.D = (float*)c->C;
     g.ldd = c->ldc;
-    g.bf16 = c->prec == GENP_BF16;
+    g.bf16 = c->prec == GENP_BF16 ? 1 : c->prec == GENP_BF16X3 ? 2 : 0;
     HIPCK(launch_gemm_lp(g, 0, c->stream));
     return GENP_OK;
 }
@@ -687,7 +687,7 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
     if (!out) return GENP_EINVAL;
     *out = nullptr;
     if (n < 1 || n > (1 << 20)) return GENP_EINVAL;
-    if (prec != GENP_F64 && prec != GENP_F32 && prec != GENP_BF16) return GENP_EINVAL;
+    if (prec != GENP_F64 && prec != GENP_F32 && prec != GENP_BF16 && prec != GENP_BF16X3) return GENP_EINVAL;
     if (nb == 0) nb = 256;
     if (nb != 64 && nb != 128 && nb != 256) return GENP_EINVAL;
     int dev = 0, cnt = 0;
@@ -954,7 +954,7 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
             g.ldci = ldc;
             g.D = (float*)at(r0, c0);
             g.ldd = ldc;
-            g.bf16 = c->prec == GENP_BF16;
+            g.bf16 = c->prec == GENP_BF16 ? 1 : c->prec == GENP_BF16X3 ? 2 : 0;
             HIPCK(launch_gemm_lp(g, 0, st));
             return GENP_OK;
         }

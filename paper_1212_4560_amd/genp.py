@@ -22,14 +22,14 @@ from typing import Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgenp.so")
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, BF16X3 = 0, 1, 2, 3
 G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT, G_HOUSEHOLDER = 0, 1, 2, 3, 4
 SOLVER_LUIR, SOLVER_GMRES = 0, 1
 OK, BREAKDOWN, ENOCONV = 0, 1, 2
 EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP, ESINGULAR = -1, -2, -3, -4, -5, -6
 ETA_HIST = 64
 
-PRECS = {"f64": F64, "f32": F32, "bf16": BF16}
+PRECS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
 SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 
 # the entry points declared in include/genp.h

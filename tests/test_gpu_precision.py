@@ -5,8 +5,12 @@ Bounds from the arithmetic (u32 = 2^-24, u_bf16 = 2^-9):
   |C_gpu - Ahat Ghat| <= (n + 1) u32 |Ahat||Ghat| entrywise, where Ahat Ghat is the
   product of the rounded operands computed by the oracle in FP64 (BF16 x BF16
   products are exact in FP32).
-* factors: growth-normalized residual ||C - LU||_F / || |L||U| ||_F <= 4 n u32 (FP32)
-  or <= 8 u_bf16 (BF16 Schur operands), and within 10x of the oracle's mirror.
+* 2-word BF16: the product is hi hi + hi lo + lo hi (each operand x = hi + lo), three FP32
+  accumulations per k: |C_gpu - P| <= (3n + 1) u32 (|hi_A| + |lo_A|)(|hi_G| + |lo_G|), P the
+  oracle's exact three-term product.
+* factors: growth-normalized residual ||C - LU||_F / || |L||U| ||_F <= 4 n u32 (FP32),
+  <= 8 u_bf16 (BF16 Schur operands) or <= 8 * 2^-16 (2-word BF16), and within 10x of the
+  oracle's mirror.
 * after FP64 refinement: eta_inf <= 1e-14 computed by the oracle from the GPU's x.
 """
 import numpy as np
@@ -36,7 +40,7 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("n,mult", [(1, "dense"), (64, "dense"), (200, "dense"), (517, "toeplitz"),
                                     (300, "toeplitz")])
 def test_lowprec_precondition_entrywise(prec, n, mult):
@@ -51,13 +55,20 @@ def test_lowprec_precondition_entrywise(prec, n, mult):
     s = genp.Solver(n, prec, 64)
     s.precondition(dev(A), G=dev(G) if p is None else None, p=dev(p) if p is not None else None)
     C = host(s.work())
-    r = ROUND[prec]
-    Ce = lpo.product_of_rounded(A, G, r)
-    bound = (n + 1) * U32 * (np.abs(r(A)) @ np.abs(r(G)))
+    if prec == "bf16x3":
+        Ce = lpo.product_bf16x3(A, G)
+        ha, la = lpo.split_bf16x2(A)
+        hg, lg = lpo.split_bf16x2(G)
+        bound = (3 * n + 1) * U32 * ((np.abs(ha) + np.abs(la)) @ (np.abs(hg) + np.abs(lg)))
+    else:
+        r = ROUND[prec]
+        Ce = lpo.product_of_rounded(A, G, r)
+        bound = (n + 1) * U32 * (np.abs(r(A)) @ np.abs(r(G)))
     assert np.all(np.abs(C - Ce) <= bound)
 
 
-@pytest.mark.parametrize("prec,nb", [("f32", 64), ("f32", 128), ("bf16", 128), ("bf16", 256)])
+@pytest.mark.parametrize("prec,nb", [("f32", 64), ("f32", 128), ("bf16", 128), ("bf16", 256), ("bf16x3", 128),
+                                     ("bf16x3", 256)])
 def test_lowprec_factor_residual(prec, nb):
     n = 600
     print(f"factor {prec} nb={nb}", flush=True)
@@ -69,11 +80,11 @@ def test_lowprec_factor_residual(prec, nb):
     LU = host(s.work())
     L, U = og.unpack(LU)
     rel = np.linalg.norm(C - L @ U) / np.linalg.norm(np.abs(L) @ np.abs(U))
-    LUo = lpo.genp_blocked_lowprec(C, nb, bf16_update=(prec == "bf16"))
+    LUo = lpo.genp_blocked_lowprec(C, nb, bf16_update=(prec == "bf16"), bf16x3_update=(prec == "bf16x3"))
     Lo, Uo = og.unpack(LUo)
     rel_o = np.linalg.norm(C - Lo @ Uo) / np.linalg.norm(np.abs(Lo) @ np.abs(Uo))
     print(f"  growth-normalized residual gpu {rel:.2e} mirror {rel_o:.2e}", flush=True)
-    assert rel <= (4 * n * U32 if prec == "f32" else 8 * UBF)
+    assert rel <= {"f32": 4 * n * U32, "bf16": 8 * UBF, "bf16x3": 8 * 2.0 ** -16}[prec]
     assert rel <= 10 * max(rel_o, n * U32)
 
 
@@ -81,6 +92,10 @@ def test_lowprec_factor_residual(prec, nb):
     ("f32", "luir", 10.0, wl.MULT_DENSE),
     ("f32", "luir", 1e2, wl.MULT_TOEPLITZ),
     ("f32", "gmres", 1e4, wl.MULT_DENSE),
+    # 2-word BF16 factors: about 16 bits, so LU-IR contracts only slowly once kappa(C) passes
+    # ~1e4 (eta 5e-2 -> 3e-3 in 12 steps at n = 512, s <= 10, dense G); GMRES-IR converges
+    ("bf16x3", "gmres", 10.0, wl.MULT_DENSE),
+    ("bf16x3", "gmres", 1e2, wl.MULT_TOEPLITZ),
 ])
 def test_lowprec_refinement_reaches_fp64_accuracy(prec, solver, smax, mult):
     n, k = 512, 2
