@@ -90,6 +90,56 @@ def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
     return res
 
 
+def multi_rhs_measure(w, args) -> dict:
+    """The FP64 path on the benchmark's A and multiplier with 64 right-hand sides (64 seeded
+    N(0,1) columns; the many-RHS substitutions and recovery).  One warm-up, then `steps` timed
+    whole-path steps."""
+    import numpy as np
+    import torch
+    from paper_1212_4560_amd import genp
+    n, k = w.A.shape[0], 64
+    g = np.random.default_rng(w.seed + 64)
+    B = torch.from_numpy(g.standard_normal((n, k))).to("cuda")
+    X = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    s = genp.Solver(n, "f64", args.nb, stream=stream)
+
+    def step():
+        s.precondition(w.A, G=w.G, p=w.p)
+        if s.factor(0.0):
+            raise RuntimeError("64 right-hand sides: breakdown")
+        s.solve(B, X)
+        s.refine(B, X, args.max_refine, args.tol, args.solver)
+        return s.info()
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    e0.record(stream)
+    for _ in range(args.steps):
+        infos.append(step())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    last = infos[-1]
+    eta_orc = None
+    if not args.no_host_check:
+        from oracle import genp as og
+        eta_orc = float(np.max(og.backward_error_inf(w.A.cpu().numpy(), X.cpu().numpy(), B.cpu().numpy())))
+    flops = method_flops(n, k, max(i["iters"] for i in infos))
+    res = {"n": n, "nrhs": k, "ms_per_step": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+           "stage_ms": {"precondition": round(last["ms_precond"], 3), "factor": round(last["ms_factor"], 3),
+                        "solve": round(last["ms_solve"], 3), "refine": round(last["ms_refine"], 3)},
+           "refine_steps": [i["iters"] for i in infos], "eta_lib": max(i["eta"] for i in infos),
+           "eta_oracle": eta_orc}
+    log(f"[bench] 64 rhs: {ms:.1f} ms per step (solve {last['ms_solve']:.2f} ms, refine {last['ms_refine']:.2f} ms), "
+        f"eta {res['eta_lib']:.2e}")
+    del s, X, B
+    torch.cuda.empty_cache()
+    return res
+
+
 def block_ge_measure(w, args, f64_ms: float) -> dict:
     """The benchmark workload factored by block Gaussian elimination with explicit block
     pivots (Theorem 2.2): row interchanges inside each nb x nb diagonal block.  One warm-up,
@@ -391,6 +441,8 @@ def main() -> int:
     ap.add_argument("--no-circulant", action="store_true",
                     help="skip the structured-multiplier comparisons (circulant by FFT, Householder)")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank approximation measurement")
+    ap.add_argument("--no-multi-rhs", action="store_true",
+                    help="skip the 64-right-hand-side measurement")
     ap.add_argument("--no-block-ge", action="store_true",
                     help="skip the block Gaussian elimination (explicit block pivots) measurement")
     ap.add_argument("--table-7-2", type=int, default=0, metavar="TRIALS",
@@ -520,6 +572,8 @@ def main() -> int:
         out["mixed"] = mixed_comparison(w, args, ms_per_step, value)
     if not args.no_block_ge and args.prec == "f64":
         out["block_ge"] = block_ge_measure(w, args, ms_per_step)
+    if not args.no_multi_rhs and args.prec == "f64":
+        out["rhs64"] = multi_rhs_measure(w, args)
     if not args.no_circulant and args.prec == "f64":
         del w
         torch.cuda.empty_cache()

@@ -180,3 +180,23 @@ def test_fullsize_n8192_differentiation_form():
     err_a = np.max(np.abs(dAs - dAo[I, J])) / np.max(np.abs(dAo))
     print(f"  backward: kappa {kappa:.2e} rel err dB {err_b:.2e} dA {err_a:.2e}", flush=True)
     assert err_b <= 10 * kappa * 1e-15 and err_a <= 10 * kappa * 1e-15
+
+
+@pytest.mark.parametrize("name", ["c4a_n16384_haar1e6_toeplitz", "c4b_n16384_haar1e4_dense"])
+def test_fullsize_n16384_64_rhs(name):
+    """n = 16384, FP64, 64 right-hand sides (the many-RHS solves: block substitutions with
+    the off-diagonal blocks on the matrix cores, split-K recovery): every column's backward
+    error after refinement, computed by the oracle from the full A on the host."""
+    print(f"full size {name}: building inputs", flush=True)
+    w = wl.make(name, device="cuda")
+    n, k = w.n, w.nrhs
+    assert k == 64
+    s = genp.Solver(n, "f64", 256)
+    s.precondition(w.A, G=w.G, p=w.p)
+    assert s.factor(0.0) == 0
+    X = s.solve(w.B)
+    st, eta = s.refine(w.B, X, 2, 1e-14)
+    assert st == genp.OK
+    eta_o = og.backward_error_inf(host(w.A), host(X), host(w.B))
+    print(f"  eta library max {max(eta):.2e} oracle max {eta_o.max():.2e}", flush=True)
+    assert np.all(eta_o <= 1e-14)
