@@ -573,6 +573,12 @@ __global__ void __launch_bounds__(64) nr_search_kernel(int lo, int hi, const dou
     const int lane = threadIdx.x;
     for (int e = lane; e < LR_MAXK * LR_MAXK; e += 64) Ss[e / LR_MAXK][e % LR_MAXK] = S[e];
     __syncthreads();
+    // this lane's row of the Gram matrix in registers for all tests: the Lanczos vector is zero
+    // past s, so the product over all 64 columns equals the product with the leading s x s block
+    // (only the leading hi x hi block of S is defined: the rest is read as zero)
+    double srow[LR_MAXK];
+#pragma unroll
+    for (int j = 0; j < LR_MAXK; ++j) srow[j] = (j < hi && lane < hi) ? Ss[lane][j] : 0.0;
     int tests = 0;
     double cond_rank = -1.0, cond_above = -1.0;   // -1: not tested
     while (lo < hi) {
@@ -586,9 +592,11 @@ __global__ void __launch_bounds__(64) nr_search_kernel(int lo, int hi, const dou
         for (; k < NR_STEPS * s; ++k) {
             vs[lane] = v;
             __syncthreads();
-            double w = 0.0;
-            if (on)
-                for (int j = 0; j < s; ++j) w = fma(Ss[lane][j], vs[j], w);
+            // four independent partial sums over the 64 columns (v is zero past s)
+            double w4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < LR_MAXK; ++j) w4[j & 3] = fma(srow[j], vs[j], w4[j & 3]);
+            double w = on ? (w4[0] + w4[1]) + (w4[2] + w4[3]) : 0.0;
             __syncthreads();
             w -= b * vp;
             const double a = wave_sum64(v * w);
