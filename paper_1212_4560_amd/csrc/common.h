@@ -165,10 +165,11 @@ hipError_t launch_panel_trsm(int f32, const void* D, long long ldd, int nb, void
 // Whole triangular solve T X = B (T = the n_pad x n_pad factor as in launch_trsm's kinds,
 // except TRSM_RIGHT_U) for 1..4 right-hand sides, one launch per bs-row block.
 // The same solve (T = the n_pad x n_pad factor, kinds as above except TRSM_RIGHT_U) in one
-// launch of n_pad / 64 workgroups chained through flags in sync (n_pad / 64 + 2 words,
-// device memory; word 1 is a sticky error word the caller clears once and checks).
+// launch of n_pad / 64 workgroups chained through the solved values published in pub
+// (n_pad * nr 8-byte words of device memory) and a ticket in sync (2 words of device memory;
+// word 1 is a sticky error word the caller clears once and checks).
 hipError_t launch_trsv_chain(int kind, int t_f32, const void* T, long long ldt, int n_pad, double* X, long long ldx,
-                             int nr, unsigned* sync, hipStream_t s);
+                             int nr, unsigned* sync, unsigned long long* pub, hipStream_t s);
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
                             long long ldx, int nr, hipStream_t s);
 hipError_t launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,

@@ -87,8 +87,10 @@ struct genp_ctx {
     std::vector<hipEvent_t> ev_step;
     hipStream_t side = nullptr;        // look-ahead stream for the next panel (default priority)
     bool lookahead = true;
-    // chained triangular solves (<= 4 right-hand sides): ticket, sticky error word, one flag per 64 rows
+    // chained triangular solves (<= 4 right-hand sides): ticket and sticky error word; the
+    // solved values as published along the chain (n_pad x 4)
     unsigned* tsync = nullptr;
+    unsigned long long* tpub = nullptr;
     bool trsv_chain = true;
     bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
     // steps per group of the factorization: g_big while the trailing matrix has at least
@@ -218,8 +220,8 @@ int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
     if (k <= 4) {
         // few right-hand sides: one chained launch per triangle (or one launch per 128-row block)
         if (c->trsv_chain) {
-            HIPCK(launch_trsv_chain(TRSM_L_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->stream));
-            HIPCK(launch_trsv_chain(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->stream));
+            HIPCK(launch_trsv_chain(TRSM_L_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub, c->stream));
+            HIPCK(launch_trsv_chain(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub, c->stream));
             return GENP_OK;
         }
         const int bs = nb >= 128 ? 128 : 64;
@@ -268,9 +270,9 @@ int lu_solve_trans_core(genp_ctx* c, double* Z, int64_t ldz, int k) {
     const char* Cb = (const char*)c->C;
     if (k <= 4) {
         if (c->trsv_chain) {
-            HIPCK(launch_trsv_chain(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->stream));
+            HIPCK(launch_trsv_chain(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub, c->stream));
             HIPCK(launch_trsv_chain(TRSM_LT_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync,
-                                    c->stream));
+                                    c->tpub, c->stream));
             return GENP_OK;
         }
         const int bs = nb >= 128 ? 128 : 64;
@@ -709,8 +711,9 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
     bool ok = hipMalloc(&c->C, (size_t)c->n_pad * c->ldc * esize(prec)) == hipSuccess &&
               hipMalloc(&c->stats, nblk * sizeof(PanelStats)) == hipSuccess &&
               hipMalloc(&c->red, (R_COLS + 3 * 256) * sizeof(unsigned long long)) == hipSuccess &&
-              hipMalloc(&c->tsync, (c->n_pad / 64 + 2) * sizeof(unsigned)) == hipSuccess &&
-              hipMemset(c->tsync, 0, (c->n_pad / 64 + 2) * sizeof(unsigned)) == hipSuccess;
+              hipMalloc(&c->tsync, 2 * sizeof(unsigned)) == hipSuccess &&
+              hipMemset(c->tsync, 0, 2 * sizeof(unsigned)) == hipSuccess &&
+              hipMalloc(&c->tpub, (size_t)c->n_pad * 4 * sizeof(unsigned long long)) == hipSuccess;
     for (int e = 0; ok && e < EV_N; ++e)
         ok = hipEventCreate(&c->ev0[e]) == hipSuccess && hipEventCreate(&c->ev1[e]) == hipSuccess;
     for (int e = 0; ok && e < 2; ++e) ok = hipEventCreate(&c->ev_ag[e]) == hipSuccess;
@@ -761,6 +764,7 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->stats);
     hipFree(c->red);
     hipFree(c->tsync);
+    hipFree(c->tpub);
     hipFree(c->perm);
     for (Mult* m : {&c->mr, &c->ml}) {
         hipFree(m->p);

@@ -414,14 +414,20 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
 // order) wait for its published solution x_p, accumulate T(t, p) x_p (the 64 x 64
 // block is prefetched one step ahead through registers into LDS); then substitute
 // with the diagonal block (one wave, readlane broadcast), store x_t, and publish it.
-// Publication: the writer's release fence at device scope, then a flag; the reader
-// polls the flag, then acquires.  sync[0]: ticket, sync[1]: sticky error word (a
-// wait exceeded spin_limit polls: the result is invalid), sync[2 + b]: flag of
-// block b.  The caller clears sync[0] and the flags before every launch.
+// Publication: each solved value is its own flag.  pub (n_pad x NR, row-major) holds
+// a signalling-NaN bit pattern (kUnset) before the launch; the writer stores x_t into
+// it with device-scope relaxed atomic stores, and a reader polls the values it needs
+// with device-scope relaxed atomic loads until none is kUnset.  Arithmetic never
+// produces kUnset (a NaN result is quiet), and each 8-byte value is written and read
+// whole, so no fence or separate flag sits on the chain.  sync[0]: ticket, sync[1]:
+// sticky error word (a wait exceeded spin_limit polls: the result is invalid).  The
+// caller resets sync[0] and pub before every launch.
+constexpr unsigned long long kUnset = 0x7ff4a5a5a5a5a5a5ull;
+
 template <bool LOWER, bool UNIT, bool TT, int NR, typename TF>
 __global__ void __launch_bounds__(256)
 trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, long long ldx,
-                  unsigned* sync, unsigned spin_limit) {
+                  unsigned* sync, unsigned long long* pub, unsigned spin_limit) {
     constexpr int BS = 64;
     __shared__ double Td[BS][BS + 1];
     __shared__ double To[2][BS][BS + 1];
@@ -462,6 +468,16 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         load_blk(t, order(0), vn);
         store_blk(To[0], vn);
     }
+    __syncthreads();
+    // wave 0's row of the diagonal block and its pivot's reciprocal, read before the waits
+    // so that only the substitution itself follows the last one
+    double trow[BS];
+    double rd = 1.0;
+    if (wave == 0) {
+        if (!UNIT) rd = 1.0 / Td[lane][lane];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) trow[i] = Td[lane][i];
+    }
     const int ri = tid >> 2, part = tid & 3;   // row and column quarter of the block products
     double acc[NR];
 #pragma unroll
@@ -475,19 +491,19 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         const int p = order(s_);
         const int buf = s_ & 1;
         if (s_ + 1 < q) load_blk(t, order(s_ + 1), vn);
-        if (tid == 0) {
+        if (tid < BS * NR) {
+            unsigned long long* src = pub + (long long)p * BS * NR + tid;
+            unsigned long long v;
             unsigned it = 0;
-            while (__hip_atomic_load(&sync[2 + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            while ((v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kUnset) {
                 if (++it > spin_limit) {
                     __hip_atomic_fetch_or(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
             }
+            xs[tid / NR][tid % NR] = __longlong_as_double((long long)v);
         }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (tid < BS * NR) xs[tid / NR][tid % NR] = X[((long long)p * BS + tid / NR) * ldx + tid % NR];
         __syncthreads();
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
@@ -512,11 +528,6 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         double z[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) z[c] = zs[lane][c];
-        const double rd = UNIT ? 1.0 : 1.0 / Td[lane][lane];
-        // this lane's row of the diagonal block in registers: the sweep then reads no LDS
-        double trow[BS];
-#pragma unroll
-        for (int i = 0; i < BS; ++i) trow[i] = Td[lane][i];
 #pragma unroll
         for (int u = 0; u < BS; ++u) {
             const int i = LOWER ? u : BS - 1 - u;
@@ -532,17 +543,18 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
             }
         }
 #pragma unroll
+        for (int c = 0; c < NR; ++c)
+            __hip_atomic_store(pub + (r0 + lane) * NR + c, (unsigned long long)__double_as_longlong(z[c]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
         for (int c = 0; c < NR; ++c) X[(r0 + lane) * ldx + c] = z[c];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&sync[2 + t], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void trsv_chain_reset_kernel(unsigned* sync, int nblk) {
+__global__ void trsv_chain_reset_kernel(unsigned* sync, unsigned long long* pub, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) sync[0] = 0u;
-    if (i < nblk) sync[2 + i] = 0u;
+    if (i < count) pub[i] = kUnset;
 }
 
 template <bool LOWER, bool UNIT, bool TT, bool XT, typename TF, typename TX>
@@ -638,14 +650,15 @@ namespace {
 
 template <bool LOWER, bool UNIT, bool TT, typename TF>
 hipError_t chain_go(const void* T, long long ldt, int nblk, double* X, long long ldx, int nr, unsigned* sync,
-                    hipStream_t s) {
+                    unsigned long long* pub, hipStream_t s) {
     constexpr unsigned kSpin = 1u << 20;   // polls (about 1 s in all): a safety limit a running chain never reaches
-    hipLaunchKernelGGL(trsv_chain_reset_kernel, dim3((nblk + 255) / 256), dim3(256), 0, s, sync, nblk);
+    const int count = nblk * 64 * nr;
+    hipLaunchKernelGGL(trsv_chain_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, sync, pub, count);
     switch (nr) {
 #define GENP_CHAIN_CASE(NR)                                                                                      \
     case NR:                                                                                                     \
         hipLaunchKernelGGL((trsv_chain_kernel<LOWER, UNIT, TT, NR, TF>), dim3(nblk), dim3(256), 0, s, (const TF*)T, \
-                           ldt, nblk, X, ldx, sync, kSpin);                                                      \
+                           ldt, nblk, X, ldx, sync, pub, kSpin);                                                      \
         break;
         GENP_CHAIN_CASE(1)
         GENP_CHAIN_CASE(2)
@@ -659,12 +672,12 @@ hipError_t chain_go(const void* T, long long ldt, int nblk, double* X, long long
 
 template <typename TF>
 hipError_t chain_kind(int kind, const void* T, long long ldt, int nblk, double* X, long long ldx, int nr,
-                      unsigned* sync, hipStream_t s) {
+                      unsigned* sync, unsigned long long* pub, hipStream_t s) {
     switch (kind) {
-        case TRSM_L_UNIT: return chain_go<true, true, false, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
-        case TRSM_U: return chain_go<false, false, false, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
-        case TRSM_UT: return chain_go<true, false, true, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
-        case TRSM_LT_UNIT: return chain_go<false, true, true, TF>(T, ldt, nblk, X, ldx, nr, sync, s);
+        case TRSM_L_UNIT: return chain_go<true, true, false, TF>(T, ldt, nblk, X, ldx, nr, sync, pub, s);
+        case TRSM_U: return chain_go<false, false, false, TF>(T, ldt, nblk, X, ldx, nr, sync, pub, s);
+        case TRSM_UT: return chain_go<true, false, true, TF>(T, ldt, nblk, X, ldx, nr, sync, pub, s);
+        case TRSM_LT_UNIT: return chain_go<false, true, true, TF>(T, ldt, nblk, X, ldx, nr, sync, pub, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -672,11 +685,11 @@ hipError_t chain_kind(int kind, const void* T, long long ldt, int nblk, double* 
 }  // namespace
 
 hipError_t launch_trsv_chain(int kind, int t_f32, const void* T, long long ldt, int n_pad, double* X, long long ldx,
-                             int nr, unsigned* sync, hipStream_t s) {
+                             int nr, unsigned* sync, unsigned long long* pub, hipStream_t s) {
     if (nr < 1 || nr > 4 || n_pad % 64) return hipErrorInvalidValue;
     const int nblk = n_pad / 64;
-    return t_f32 ? chain_kind<float>(kind, T, ldt, nblk, X, ldx, nr, sync, s)
-                 : chain_kind<double>(kind, T, ldt, nblk, X, ldx, nr, sync, s);
+    return t_f32 ? chain_kind<float>(kind, T, ldt, nblk, X, ldx, nr, sync, pub, s)
+                 : chain_kind<double>(kind, T, ldt, nblk, X, ldx, nr, sync, pub, s);
 }
 
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
