@@ -76,6 +76,8 @@ __global__ void max_abs_kernel(const T* __restrict__ X, long long ldx, int rows,
 }
 
 // max_i sum_j |A(i, j)| (the infinity norm): one wave per row, one atomic per row.
+// VEC: rows 16-byte aligned, pairs of entries loaded as one 16-byte load (checked by the launcher).
+template <bool VEC>
 __global__ void row_abs_sum_max_kernel(const double* __restrict__ A, long long lda, int n,
                                        unsigned long long* out) {
     const int lane = threadIdx.x & 63;
@@ -84,6 +86,28 @@ __global__ void row_abs_sum_max_kernel(const double* __restrict__ A, long long l
     const double* r = A + (long long)row * lda;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int k = lane;
+    if constexpr (VEC) {
+        const double2* r2 = reinterpret_cast<const double2*>(r);
+        const int n2 = n >> 1;
+        int k2 = lane;
+        for (; k2 + 448 < n2; k2 += 512) {
+            double2 a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = r2[k2 + 64 * u];
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                s0 += fabs(a[u].x);
+                s1 += fabs(a[u].y);
+                s2 += fabs(a[u + 1].x);
+                s3 += fabs(a[u + 1].y);
+            }
+        }
+        for (; k2 < n2; k2 += 64) {
+            s0 += fabs(r2[k2].x);
+            s1 += fabs(r2[k2].y);
+        }
+        k = (n & 1) ? ((lane == 0) ? n - 1 : n) : n;
+    }
     for (; k + 192 < n; k += 256) {
         s0 += fabs(r[k]);
         s1 += fabs(r[k + 64]);
@@ -164,7 +188,7 @@ __global__ void fill2d_kernel(double v, double* __restrict__ x, long long ldx, i
 }
 
 // Row mode: one wave per output row, NR right-hand sides (NR <= 4).
-template <int NR, int AMODE, typename TA>
+template <int NR, int AMODE, typename TA, bool VEC = false>
 __global__ void __launch_bounds__(256)
 gemv_row_kernel(int M, int K, double alpha, const TA* __restrict__ A, long long lda,
                 const double* __restrict__ X, long long ldx, double beta, const double* Yin,
@@ -177,6 +201,37 @@ gemv_row_kernel(int M, int K, double alpha, const TA* __restrict__ A, long long 
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
     const TA* ar = (AMODE == OP_TOEP) ? A + (long long)row + lda - 1 : A + (long long)row * lda;
     int k = lane;
+    if constexpr (VEC) {
+        // pairs of entries as one 16-byte load, eight loads in flight per lane; the row
+        // start is 16-byte aligned (checked by the launcher)
+        const double2* ar2 = reinterpret_cast<const double2*>(ar);
+        const int K2 = K >> 1;
+        int k2 = lane;
+        for (; k2 + 448 < K2; k2 += 512) {
+            double2 a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = ar2[k2 + 64 * u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const long long kk = 2LL * (k2 + 64 * u);
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    acc[c] = fma(a[u].x, X[kk * ldx + c], acc[c]);
+                    acc[c] = fma(a[u].y, X[(kk + 1) * ldx + c], acc[c]);
+                }
+            }
+        }
+        for (; k2 < K2; k2 += 64) {
+            const double2 a = ar2[k2];
+            const long long kk = 2LL * k2;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                acc[c] = fma(a.x, X[kk * ldx + c], acc[c]);
+                acc[c] = fma(a.y, X[(kk + 1) * ldx + c], acc[c]);
+            }
+        }
+        k = (K & 1) ? ((lane == 0) ? K - 1 : K) : K;   // the odd last entry, if any, on lane 0
+    }
     for (; k + 192 < K; k += 256) {
         double a[4];
 #pragma unroll
@@ -247,8 +302,13 @@ hipError_t gemv_dispatch_t(int M, int K, double alpha, const TA* A, long long ld
         hipLaunchKernelGGL((gemv_col_kernel<NR, TA>), dim3((M + 255) / 256), dim3(256), 0, s, M, K,
                            alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
     } else if (amode == OP_N) {
-        hipLaunchKernelGGL((gemv_row_kernel<NR, OP_N, TA>), dim3((M + 3) / 4), dim3(256), 0, s, M, K,
-                           alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
+        const bool vec = std::is_same<TA, double>::value && ((uintptr_t)A % 16 == 0) && (lda % 2 == 0);
+        if (vec)
+            hipLaunchKernelGGL((gemv_row_kernel<NR, OP_N, TA, true>), dim3((M + 3) / 4), dim3(256), 0, s, M, K,
+                               alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
+        else
+            hipLaunchKernelGGL((gemv_row_kernel<NR, OP_N, TA>), dim3((M + 3) / 4), dim3(256), 0, s, M, K,
+                               alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
     } else {
         hipLaunchKernelGGL((gemv_row_kernel<NR, OP_TOEP, TA>), dim3((M + 3) / 4), dim3(256), 0, s, M,
                            K, alpha, A, lda, X, ldx, beta, Yin, ldyi, Y, ldy);
@@ -420,7 +480,10 @@ hipError_t launch_max_abs(int prec, const void* X, long long ldx, int rows, int 
 
 hipError_t launch_row_abs_sum_max(const double* A, long long lda, int n, unsigned long long* out,
                                   hipStream_t s) {
-    hipLaunchKernelGGL(row_abs_sum_max_kernel, dim3((n + 3) / 4), dim3(256), 0, s, A, lda, n, out);
+    if (((uintptr_t)A % 16 == 0) && (lda % 2 == 0))
+        hipLaunchKernelGGL(row_abs_sum_max_kernel<true>, dim3((n + 3) / 4), dim3(256), 0, s, A, lda, n, out);
+    else
+        hipLaunchKernelGGL(row_abs_sum_max_kernel<false>, dim3((n + 3) / 4), dim3(256), 0, s, A, lda, n, out);
     return hipGetLastError();
 }
 
