@@ -170,6 +170,10 @@ hipError_t launch_panel_trsm(int f32, const void* D, long long ldd, int nb, void
 // word 1 is a sticky error word the caller clears once and checks).
 hipError_t launch_trsv_chain(int kind, int t_f32, const void* T, long long ldt, int n_pad, double* X, long long ldx,
                              int nr, unsigned* sync, unsigned long long* pub, hipStream_t s);
+// The same chained solve for 1..64 right-hand sides (MFMA block products; pub holds n_pad * 64
+// 8-byte words).
+hipError_t launch_trsm_chain(int kind, int t_f32, const void* T, long long ldt, int n_pad, double* X, long long ldx,
+                             int ncols, unsigned* sync, unsigned long long* pub, hipStream_t s);
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,
                             long long ldx, int nr, hipStream_t s);
 hipError_t launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,

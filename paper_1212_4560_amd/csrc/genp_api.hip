@@ -87,8 +87,8 @@ struct genp_ctx {
     std::vector<hipEvent_t> ev_step;
     hipStream_t side = nullptr;        // look-ahead stream for the next panel (default priority)
     bool lookahead = true;
-    // chained triangular solves (<= 4 right-hand sides): ticket and sticky error word; the
-    // solved values as published along the chain (n_pad x 4)
+    // chained triangular solves (<= 64 right-hand sides): ticket and sticky error word; the
+    // solved values as published along the chain (n_pad x 64)
     unsigned* tsync = nullptr;
     unsigned long long* tpub = nullptr;
     bool trsv_chain = true;
@@ -229,6 +229,12 @@ int lu_solve_inplace(genp_ctx* c, double* Z, int64_t ldz, int k) {
         HIPCK(launch_trsv_full(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
         return GENP_OK;
     }
+    if (k <= 64 && c->trsv_chain) {
+        // up to 64 right-hand sides: one chained launch per triangle, MFMA block products
+        HIPCK(launch_trsm_chain(TRSM_L_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub, c->stream));
+        HIPCK(launch_trsm_chain(TRSM_U, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub, c->stream));
+        return GENP_OK;
+    }
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t r0 = b * nb;
         HIPCK(launch_trsm(TRSM_L_UNIT, f32, 0, Cb + (r0 * c->ldc + r0) * es, c->ldc, (int)nb, Z + r0 * ldz,
@@ -278,6 +284,12 @@ int lu_solve_trans_core(genp_ctx* c, double* Z, int64_t ldz, int k) {
         const int bs = nb >= 128 ? 128 : 64;
         HIPCK(launch_trsv_full(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
         HIPCK(launch_trsv_full(TRSM_LT_UNIT, f32, c->C, c->ldc, (int)c->n_pad, bs, Z, ldz, k, c->stream));
+        return GENP_OK;
+    }
+    if (k <= 64 && c->trsv_chain) {
+        HIPCK(launch_trsm_chain(TRSM_UT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub, c->stream));
+        HIPCK(launch_trsm_chain(TRSM_LT_UNIT, f32, c->C, c->ldc, (int)c->n_pad, Z, ldz, k, c->tsync, c->tpub,
+                                c->stream));
         return GENP_OK;
     }
     // U^T is lower triangular: forward substitution
@@ -713,7 +725,7 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
               hipMalloc(&c->red, (R_COLS + 3 * 256) * sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc(&c->tsync, 2 * sizeof(unsigned)) == hipSuccess &&
               hipMemset(c->tsync, 0, 2 * sizeof(unsigned)) == hipSuccess &&
-              hipMalloc(&c->tpub, (size_t)c->n_pad * 4 * sizeof(unsigned long long)) == hipSuccess;
+              hipMalloc(&c->tpub, (size_t)c->n_pad * 64 * sizeof(unsigned long long)) == hipSuccess;
     for (int e = 0; ok && e < EV_N; ++e)
         ok = hipEventCreate(&c->ev0[e]) == hipSuccess && hipEventCreate(&c->ev1[e]) == hipSuccess;
     for (int e = 0; ok && e < 2; ++e) ok = hipEventCreate(&c->ev_ag[e]) == hipSuccess;

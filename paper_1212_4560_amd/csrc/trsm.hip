@@ -551,6 +551,143 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     }
 }
 
+// Whole triangular solve T X = B for 5..64 right-hand sides in ONE launch: the many-column
+// form of trsv_chain_kernel, with the same ticket order and the same publication (every solved
+// value its own flag; pub is n_pad x 64, row-major).  64-row blocks, 256 threads; wave w owns
+// columns 16 w .. 16 w + 15 and keeps the block's 64 x 16 slab of Y in four MFMA accumulators
+// (tile b: lane l, element r = Y(16 b + l / 16 + 4 r, 16 w + l % 16)), so element u of tile b
+// is the B operand of v_mfma_f64_16x16x4_f64 for rows 16 b + 4 u .. + 3.  For every earlier
+// block p in solve order, T(t, p) is staged through LDS (prefetched one block ahead through
+// registers) and the values of X_p are polled straight into B operands, one 16-row tile of p
+// at a time in the order p solves its tiles: the product with a block overlaps the end of
+// that block's own solve.  Then the diagonal block is solved in place in the accumulators,
+// tile by tile (substitution with a cross-lane broadcast of each solved row, forward or
+// backward, then the MFMA update of the tiles still to be solved), and each tile is
+// published as soon as it is final.
+template <bool LOWER, bool UNIT, bool TT, typename TF>
+__global__ void __launch_bounds__(256)
+trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, long long ldx, int ncols,
+                  unsigned* sync, unsigned long long* pub, unsigned spin_limit) {
+    constexpr int BS = 64;
+    __shared__ double Td[BS][BS + 1];
+    __shared__ double To[2][BS][BS + 1];
+    __shared__ int s_q;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int cc = w * 16 + lr;
+    const bool cok = cc < ncols;
+    if (tid == 0) s_q = (int)atomicAdd(&sync[0], 1u);
+    __syncthreads();
+    const int q = s_q;
+    const int t = LOWER ? q : nblk - 1 - q;
+    const long long r0 = (long long)t * BS;
+    auto load_blk = [&](int rb, int cb, double (&v)[16]) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
+            const int i = TT ? (e & 63) : (e >> 6), j = TT ? (e >> 6) : (e & 63);
+            v[k] = (double)T[tat<TT>((long long)rb * BS + i, (long long)cb * BS + j, ldt)];
+        }
+    };
+    auto store_blk = [&](double (*dst)[BS + 1], const double (&v)[16]) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
+            const int i = TT ? (e & 63) : (e >> 6), j = TT ? (e >> 6) : (e & 63);
+            dst[i][j] = v[k];
+        }
+    };
+    auto order = [&](int s_) { return LOWER ? s_ : nblk - 1 - s_; };
+    auto tord = [](int j) { return LOWER ? j : 3 - j; };   // tiles of a block in solve order
+    {
+        double v[16];
+        load_blk(t, t, v);
+        store_blk(Td, v);
+    }
+    double vn[16];
+    if (q > 0) {
+        load_blk(t, order(0), vn);
+        store_blk(To[0], vn);
+    }
+    f64x4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[b][r] = cok ? X[(r0 + 16 * b + lq + 4 * r) * ldx + cc] : 0.0;
+    __syncthreads();
+    for (int s_ = 0; s_ < q; ++s_) {
+        const int p = order(s_);
+        const int buf = s_ & 1;
+        if (s_ + 1 < q) load_blk(t, order(s_ + 1), vn);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pb = tord(j);
+            double bq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bq[u] = 0.0;
+                if (cok) {
+                    unsigned long long* src = pub + ((long long)p * BS + 16 * pb + 4 * u + lq) * 64 + cc;
+                    unsigned long long v;
+                    unsigned it = 0;
+                    while ((v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kUnset) {
+                        if (++it > spin_limit) {
+                            __hip_atomic_fetch_or(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    bq[u] = __longlong_as_double((long long)v);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-To[buf][16 * b + lr][16 * pb + 4 * u + lq], bq[u],
+                                                                  acc[b], 0, 0, 0);
+        }
+        if (s_ + 1 < q) store_blk(To[buf ^ 1], vn);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int b = tord(jb);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int sr = LOWER ? j : 15 - j;
+            double v = acc[b][sr >> 2];
+            if (!UNIT) v = v / Td[16 * b + sr][16 * b + sr];
+            const double ys = __shfl(v, (sr & 3) * 16 + lr, 64);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = lq + 4 * r;
+                const double nv = fma(-Td[16 * b + i][16 * b + sr], ys, acc[b][r]);
+                const bool upd = LOWER ? i > sr : i < sr;
+                acc[b][r] = upd ? nv : ((i == sr) ? ys : acc[b][r]);
+            }
+        }
+        if (cok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = r0 + 16 * b + lq + 4 * r;
+                __hip_atomic_store(pub + row * 64 + cc, (unsigned long long)__double_as_longlong(acc[b][r]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[(r0 + 16 * b + lq + 4 * r) * ldx + cc] = acc[b][r];
+        }
+#pragma unroll
+        for (int jj = jb + 1; jj < 4; ++jj) {
+            const int bb = tord(jj);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc[bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Td[16 * bb + lr][16 * b + 4 * u + lq], acc[b][u],
+                                                               acc[bb], 0, 0, 0);
+        }
+    }
+}
+
 __global__ void trsv_chain_reset_kernel(unsigned* sync, unsigned long long* pub, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) sync[0] = 0u;
@@ -670,6 +807,29 @@ hipError_t chain_go(const void* T, long long ldt, int nblk, double* X, long long
     return hipGetLastError();
 }
 
+template <bool LOWER, bool UNIT, bool TT, typename TF>
+hipError_t mchain_go(const void* T, long long ldt, int nblk, double* X, long long ldx, int ncols, unsigned* sync,
+                     unsigned long long* pub, hipStream_t s) {
+    constexpr unsigned kSpin = 1u << 20;
+    const int count = nblk * 64 * 64;
+    hipLaunchKernelGGL(trsv_chain_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, sync, pub, count);
+    hipLaunchKernelGGL((trsm_chain_kernel<LOWER, UNIT, TT, TF>), dim3(nblk), dim3(256), 0, s, (const TF*)T, ldt,
+                       nblk, X, ldx, ncols, sync, pub, kSpin);
+    return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t mchain_kind(int kind, const void* T, long long ldt, int nblk, double* X, long long ldx, int ncols,
+                       unsigned* sync, unsigned long long* pub, hipStream_t s) {
+    switch (kind) {
+        case TRSM_L_UNIT: return mchain_go<true, true, false, TF>(T, ldt, nblk, X, ldx, ncols, sync, pub, s);
+        case TRSM_U: return mchain_go<false, false, false, TF>(T, ldt, nblk, X, ldx, ncols, sync, pub, s);
+        case TRSM_UT: return mchain_go<true, false, true, TF>(T, ldt, nblk, X, ldx, ncols, sync, pub, s);
+        case TRSM_LT_UNIT: return mchain_go<false, true, true, TF>(T, ldt, nblk, X, ldx, ncols, sync, pub, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename TF>
 hipError_t chain_kind(int kind, const void* T, long long ldt, int nblk, double* X, long long ldx, int nr,
                       unsigned* sync, unsigned long long* pub, hipStream_t s) {
@@ -690,6 +850,14 @@ hipError_t launch_trsv_chain(int kind, int t_f32, const void* T, long long ldt, 
     const int nblk = n_pad / 64;
     return t_f32 ? chain_kind<float>(kind, T, ldt, nblk, X, ldx, nr, sync, pub, s)
                  : chain_kind<double>(kind, T, ldt, nblk, X, ldx, nr, sync, pub, s);
+}
+
+hipError_t launch_trsm_chain(int kind, int t_f32, const void* T, long long ldt, int n_pad, double* X, long long ldx,
+                             int ncols, unsigned* sync, unsigned long long* pub, hipStream_t s) {
+    if (ncols < 1 || ncols > 64 || n_pad % 64) return hipErrorInvalidValue;
+    const int nblk = n_pad / 64;
+    return t_f32 ? mchain_kind<float>(kind, T, ldt, nblk, X, ldx, ncols, sync, pub, s)
+                 : mchain_kind<double>(kind, T, ldt, nblk, X, ldx, ncols, sync, pub, s);
 }
 
 hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, int n_pad, int bs, double* X,

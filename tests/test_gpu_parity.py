@@ -361,10 +361,11 @@ def test_breakdown_in_the_second_half_of_a_diagonal_block(monkeypatch, mode):
     assert inf["min_abs_piv"] >= 5e-3 * inf["max_abs_c"]
 
 
-@pytest.mark.parametrize("nrhs", [1, 2, 3, 4])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5, 17, 64])
 def test_chained_triangular_solves_match_per_block_solves(monkeypatch, nrhs):
     """The single-launch solves (forward/backward for the solution, transposed for the
-    adjoint) against the one-launch-per-block solves, for 1..4 right-hand sides.  Both are
+    adjoint) against the one-launch-per-block solves, for 1..4 right-hand sides (VALU
+    chain) and 5..64 (MFMA chain; the block path is the diagonal-block TRSM and GEMM).  Both are
     substitution with the sums accumulated in a different order, so both must be backward
     stable: eta_inf of X for A X = B and of dB for A^T dB = W small (no refinement here) and
     within 10x of each other; the solutions themselves differ by the factors' conditioning
