@@ -130,7 +130,8 @@ typedef struct {
  *   prec     GENP_F64 / GENP_F32 / GENP_BF16 / GENP_BF16X3.
  *   nb       panel width of the blocked elimination: 64, 128 or 256 (0 = default 256).
  *   stream   hipStream_t to order all work on (NULL = the null stream).
- * Allocates the working matrix (padded to a multiple of nb) and scratch.
+ * Allocates the working matrix (padded to a multiple of nb) and scratch (among it
+ * 512 n_pad bytes for the values published along the chained substitutions).
  * Errors: GENP_EINVAL, GENP_EDEVICE (no gfx950 device), GENP_ENOMEM.
  */
 int genp_create(genp_ctx** ctx, int64_t n, int prec, int nb, void* stream);
