@@ -116,6 +116,35 @@ def test_lowprec_refinement_reaches_fp64_accuracy(prec, solver, smax, mult):
     assert np.all(eta_o <= 1e-14)
 
 
+def test_fp32_factors_many_rhs_refine_to_fp64_accuracy():
+    """FP32 factors and 24 right-hand sides: every substitution of the solve and of LU-IR goes
+    through the chained many-column solve reading an FP32 factor.  The unrefined solve equals
+    the oracle's FP64 substitution with the same (FP32-stored) factors up to rounding, and
+    LU-IR takes all 24 columns to the FP64 backward-error bar (the oracle's measure).  The
+    matrix is the one of the two-column FP32 LU-IR case (kappa(C) ~ 3e5)."""
+    n, k = 512, 24
+    print(f"refine f32 luir n={n} k={k}", flush=True)
+    w = wl.haar_logspaced(n, 10.0, wl.MULT_DENSE, nrhs=k, seed=11)
+    s = genp.Solver(n, "f32", 128)
+    s.precondition(dev(w.A), G=dev(w.G))
+    assert s.factor() == 0
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    X0 = host(X).copy()
+    LUg = host(s.work()).astype(np.float64)
+    Xs = og.solve(LUg, w.G, w.B)
+    print(f"  unrefined vs oracle substitution: {np.max(np.abs(X0 - Xs)) / np.max(np.abs(Xs)):.2e}", flush=True)
+    assert np.max(np.abs(X0 - Xs)) <= 1e-8 * np.max(np.abs(Xs))
+    st, eta = s.refine(Bd, X, max_iter=20, tol=1e-14, solver="luir")
+    Xh = host(X)
+    eta_o = og.backward_error_inf(w.A, Xh, w.B)
+    info = s.info()
+    print(f"  status {st} outer {info['iters']} eta {max(eta):.2e} oracle {eta_o.max():.2e} "
+          f"hist {['%.1e' % e for e in info['eta_hist']]}", flush=True)
+    assert st == genp.OK
+    assert eta_o.shape == (k,) and np.all(eta_o <= 1e-14)
+
+
 def test_lowprec_adjoint_with_refinement():
     """FP32 factors, adjoint refined against A^T: dB, dA match the oracle's FP64 gradient."""
     n, k = 256, 4
