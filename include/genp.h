@@ -232,12 +232,14 @@ int genp_row_perm(const genp_ctx* ctx, int32_t* perm);
  * X = G U^{-1} L^{-1} B for nrhs right-hand sides (B: n x nrhs, ldb >= nrhs;
  * X: n x nrhs, ldx >= nrhs; X may equal B).  FP64 arithmetic over the stored
  * factors.  Requires a successful genp_factor.  Stream-ordered, does not
- * synchronize.  With nrhs <= 4 each triangular solve is one launch whose
+ * synchronize.  With nrhs <= 64 each triangular solve is one launch whose
  * workgroups wait on each other with a bounded spin; the bound is a safety limit
  * that a running solve never reaches, and if it were ever exceeded the next
  * genp_refine or genp_get_info returns GENP_EDEVICE (the solutions computed since
- * are then invalid).  Environment GENP_TRSV=step selects one launch per 128-row
- * block instead.
+ * are then invalid).  More than 64 right-hand sides are solved block by block
+ * (diagonal-block solve, then a product per block).  Environment GENP_TRSV=step
+ * selects one launch per 128-row block (nrhs <= 4) or the block-by-block solve
+ * (5 <= nrhs <= 64) instead.
  */
 int genp_solve(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
                double* X, int64_t ldx);
