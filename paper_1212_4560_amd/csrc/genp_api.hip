@@ -182,7 +182,7 @@ int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_
         g.ldci = ldyi;
         g.a_f32 = a_f32;
         const int ntm = (M + 127) / 128;
-        int ks = std::max(1, std::min(KSPLIT_MAX, (512 + ntm - 1) / ntm));
+        int ks = std::max(1, std::min(KSPLIT_MAX, (1024 + ntm - 1) / ntm));
         ks = std::min(ks, std::max(1, K / 64));
         if (ks > 1 && (int64_t)M * kc * ks > c->n_pad * c->kcap * KSPLIT_MAX) ks = 1;
         if (ks == 1) {
