@@ -24,7 +24,9 @@
 // accumulators; the diagonal block is solved by substitution (one lane per
 // right-hand side), the update of the blocks below by v_mfma_f64_16x16x4_f64.
 //
-// trsv_step_kernel (1..4 right-hand sides, whole triangular factor): see below.
+// trsv_step_kernel (1..4 right-hand sides, one launch per block), trsv_chain_kernel
+// (1..4, the whole triangle in one launch) and trsm_chain_kernel (5..64, the whole
+// triangle in one launch, MFMA block products): see below.
 #include "common.h"
 
 #include <type_traits>
