@@ -503,6 +503,9 @@ def main() -> int:
             raise RuntimeError(f"breakdown at column {bk}")
         s.solve(w.B, X)
         st, eta = s.refine(w.B, X, args.max_refine, args.tol, args.solver)
+        if st != genp.OK or not max(eta) <= args.tol:
+            # the metric is defined at backward error <= tol: a step that misses it does not count
+            raise RuntimeError(f"refinement status {st}, eta {max(eta):.3e} above {args.tol:g}")
         inf = s.info()
         return inf
 

@@ -229,14 +229,16 @@ int genp_block_pivots(const genp_ctx* ctx, double* out, int64_t ldo);
 int genp_row_perm(const genp_ctx* ctx, int32_t* perm);
 
 /*
- * X = G U^{-1} L^{-1} B for nrhs right-hand sides (B: n x nrhs, ldb >= nrhs;
- * X: n x nrhs, ldx >= nrhs; X may equal B).  FP64 arithmetic over the stored
+ * X = G U^{-1} L^{-1} B for nrhs right-hand sides (section 1.1: the system
+ * C y = b of the preconditioned matrix C = A G is solved by the two triangular
+ * substitutions of GENP, and x = G y solves A x = b).  B: n x nrhs, ldb >= nrhs;
+ * X: n x nrhs, ldx >= nrhs; X may equal B.  FP64 arithmetic over the stored
  * factors.  Requires a successful genp_factor.  Stream-ordered, does not
  * synchronize.  With nrhs <= 64 each triangular solve is one launch whose
  * workgroups wait on each other with a bounded spin; the bound is a safety limit
  * that a running solve never reaches, and if it were ever exceeded the next
- * genp_refine or genp_get_info returns GENP_EDEVICE (the solutions computed since
- * are then invalid).  More than 64 right-hand sides are solved block by block
+ * genp_refine or genp_get_info returns GENP_EDEVICE once (the solutions computed
+ * since are then invalid; the error word is cleared when it is reported).  More than 64 right-hand sides are solved block by block
  * (diagonal-block solve, then a product per block).  Environment GENP_TRSV=step
  * selects one launch per 128-row block (nrhs <= 4) or the block-by-block solve
  * (5 <= nrhs <= 64) instead.
@@ -259,7 +261,9 @@ int genp_refine(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
                 double* eta_out);
 
 /*
- * Adjoint of X = A^{-1} B for the loss sum(W .* X): dB = A^{-T} W computed
+ * Not in the paper: the differentiation of its solve.  For X = A^{-1} B and a
+ * loss with gradient W = dL/dX, dL = <A^{-T} W, dB> - <A^{-T} W X^T, dA>, so the
+ * adjoint of the loss sum(W .* X) is dB = A^{-T} W and dA = -dB X^T.  dB is computed
  * from the stored factors as L^{-T} U^{-T} (G^T W), followed by refine_iters
  * FP64 refinement steps against A^T; if dA is not NULL, dA = -dB X^T
  * (n x n, ldda >= n).  W, X: n x nrhs (ldw, ldx >= nrhs); dB: n x nrhs.

@@ -18,10 +18,12 @@ used here are:
   terms.
 
 ``genp_blocked_lowprec`` is an FP32 block elimination with optionally
-BF16-rounded (or 2-word BF16) Schur-update operands.  It mirrors the kind of factorization the
-mixed form computes, not its bits: parity unpinned for intermediate bits (the
-MFMA accumulation order is not specified anywhere); tests use it only for
-statistics (growth, factor residual) and bounds.
+BF16-rounded (or 2-word BF16) Schur-update operands.  It is pinned exactly on a
+matrix built from its factors, where one block step's update is exact in FP32
+when (and only when) its operands are rounded as stated.  On general inputs it
+mirrors the kind of factorization the mixed form computes, not its bits (the
+MFMA accumulation order is not specified anywhere), so tests compare the
+library with it through statistics (growth, factor residual) and bounds.
 """
 from __future__ import annotations
 
@@ -78,8 +80,8 @@ def product_bf16x3(A, B) -> np.ndarray:
 
 def genp_blocked_lowprec(C, nb: int, bf16_update: bool = False, bf16x3_update: bool = False):
     """FP32 block GENP; with bf16_update the Schur-update operands L21 and U12
-    are rounded to BF16 before the FP32 product, with bf16x3_update the update is the
-    2-word BF16 product (parity unpinned: statistics only)."""
+    are rounded to BF16 before the FP32 product (the stored factors keep their FP32
+    values), with bf16x3_update the update is the 2-word BF16 product."""
     from scipy.linalg import solve_triangular
 
     LU = np.array(C, dtype=np.float32, copy=True)

@@ -83,8 +83,3 @@ def projection_residual(A: np.ndarray, T: np.ndarray, orthogonal: bool = True, o
     P = T @ T.T if orthogonal else T @ np.linalg.solve(T.T @ T, T.T)
     return float(np.linalg.norm(A - A @ P, ord))
 
-
-def lsq_basis_residual(B: np.ndarray, Tq: np.ndarray) -> float:
-    """rn(1) of Table 7.2: ||B Y - T_q|| with Y the least-squares solution of B Y = T_q."""
-    Y, *_ = np.linalg.lstsq(B, Tq, rcond=None)
-    return float(np.linalg.norm(B @ Y - Tq, 2))

@@ -1197,13 +1197,17 @@ int genp_solve(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* 
 }
 
 // The chained solves record a wait that exceeded its safety limit in a sticky word;
-// the synchronizing calls report it (the solutions computed since are invalid).
+// the next synchronizing call reports it once (the solutions computed since are invalid)
+// and clears it, so later calls report only new overruns.
 static int chain_status(genp_ctx* c) {
     if (!c->trsv_chain) return GENP_OK;
     unsigned err = 0;
     HIPCK(hipMemcpyAsync(&err, c->tsync + 1, sizeof err, hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
-    return err ? GENP_EDEVICE : GENP_OK;
+    if (!err) return GENP_OK;
+    HIPCK(hipMemsetAsync(c->tsync + 1, 0, sizeof(unsigned), c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return GENP_EDEVICE;
 }
 
 int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, int max_iter,
