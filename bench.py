@@ -10,8 +10,9 @@ on the GPU before the timed region.
 
 Prints ONE JSON line.  GFLOP/s counts the method's algorithmic flops
 2n^3 + (2/3 n^3 - n^2/2 - n/6) + 4 n^2 k + it * 6 n^2 k.
-Beside the headline it reports, as context, the precision form (FP32 / BF16
-factors with FP64 GMRES refinement) and the same recipe with a Gaussian
+Beside the headline it reports, as context, the precision form (FP32 / BF16 /
+2-word BF16 factors with FP64 GMRES refinement) against FP64 over smax in
+1e1 .. 1e6 (`mixed_sweep`), and the same recipe with a Gaussian
 circulant multiplier applied by FFT and with a +-1 Householder-type multiplier
 (time to solution, not GFLOP/s: these products take O(n^2 log n) and O(n^2)
 work instead of 2n^3).
@@ -54,40 +55,73 @@ def traffic_if_current(n: int):
     return rec.get("traffic_bytes")
 
 
-def mixed_comparison(w, args, f64_ms: float, f64_gflops: float) -> list:
-    """The precision form on the same inputs: FP32, BF16-operand and 2-word BF16 factors with
-    FP64 GMRES-IR (restart 50, at most 2 outer steps).  One warm-up, one timed run each."""
+SWEEP_SMAX = (1e1, 1e2, 1e4, 1e6)
+
+
+def mixed_sweep(args, n: int) -> list:
+    """The precision form against FP64 over kappa(A): the benchmark recipe (Haar U, V, Toeplitz G
+    and b of seed 3) with smax in SWEEP_SMAX.  Per smax: the FP64 path on that matrix (one warm-up,
+    one timed step, LU-IR), then each precision form (FP32, BF16 operands, 2-word BF16): C = A G and
+    the LU in that precision, the substitutions and FP64 GMRES-IR (cycles of --sweep-restart steps,
+    at most --sweep-cap inner steps) until eta <= tol, timed as one step after a warm-up of the
+    product and factorization.  Outside the timed region: the kappa_1 estimate of the factored
+    matrix (genp_condest) and the oracle's eta of every returned x."""
+    import numpy as np
     import torch
-    from paper_1212_4560_amd import genp
-    res = []
-    n, k = w.n, w.nrhs
-    for prec in ("f32", "bf16", "bf16x3"):
-        s = genp.Solver(n, prec, args.nb)
-        X = torch.empty((n, k), dtype=torch.float64, device="cuda")
-        stream = torch.cuda.current_stream()
-        for rep in range(2):
+    from oracle import genp as og
+    from paper_1212_4560_amd import genp, workloads as wl
+    stream = torch.cuda.current_stream()
+    out = []
+    for w in wl.haar_family(n, SWEEP_SMAX, wl.MULT_TOEPLITZ, nrhs=1, seed=3):
+        Ah = w.A.cpu().numpy()
+        Bh = w.B.cpu().numpy()
+        X = torch.empty((n, 1), dtype=torch.float64, device="cuda")
+        f64_ms = None
+        for prec in ("f64", "f32", "bf16", "bf16x3"):
+            s = genp.Solver(n, prec, args.nb, stream=stream)
+            s.precondition(w.A, p=w.p)
+            s.factor(0.0)                     # warm-up of the product and factorization kernels
+            torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            s.precondition(w.A, G=w.G, p=w.p)
+            s.precondition(w.A, p=w.p)
             bk = s.factor(0.0)
-            st, eta = (None, [float("nan")])
+            st, eta = genp.BREAKDOWN, [float("nan")]
             if not bk:
                 s.solve(w.B, X)
-                st, eta = s.refine(w.B, X, 2, args.tol, "gmres")
+                if prec == "f64":
+                    st, eta = s.refine(w.B, X, args.max_refine, args.tol, "luir")
+                else:
+                    st, eta = s.refine(w.B, X, 10 ** 6, args.tol, "gmres", restart=args.sweep_restart,
+                                       max_inner=args.sweep_cap)
             e1.record(stream)
             torch.cuda.synchronize()
-        inf = s.info()
-        ms = e0.elapsed_time(e1)
-        ok = bool(st == genp.OK and max(eta) <= args.tol)
-        res.append({"prec": prec, "solver": "gmres", "ms": round(ms, 2), "eta": max(eta),
-                    "reached_tol": ok, "outer": inf["iters"], "inner": inf["inner_iters"],
-                    "ms_precond": round(inf["ms_precond"], 2), "ms_factor": round(inf["ms_factor"], 2),
-                    "ms_refine": round(inf["ms_refine"], 2), "growth": inf["growth"],
-                    "speedup_vs_f64": round(f64_ms / ms, 3)})
-        log(f"[bench] mixed {prec}: {ms:.1f} ms, eta {max(eta):.2e}, outer {inf['iters']} inner "
-            f"{inf['inner_iters']}, reached tol: {ok}")
-        del s
-    return res
+            ms = e0.elapsed_time(e1)
+            inf = s.info()
+            kap = s.condest()["kappa1"] if not bk else float("nan")
+            eta_o = float(np.max(og.backward_error_inf(Ah, X.cpu().numpy(), Bh))) if not bk else float("nan")
+            ok = bool(st == genp.OK and eta_o <= args.tol)
+            if prec == "f64":
+                f64_ms = ms
+            cell = {"smax": w.smax, "prec": prec, "ms": round(ms, 2), "status": int(st), "reached_tol": ok,
+                    "eta_lib": max(eta), "eta_oracle": eta_o, "outer": inf["iters"], "inner": inf["inner_iters"],
+                    "kappa1_est": kap, "kappa1_u": kap * {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -9,
+                                                          "bf16x3": 2.0 ** -17}[prec],
+                    "growth": inf["growth"], "ms_precond": round(inf["ms_precond"], 2),
+                    "ms_factor": round(inf["ms_factor"], 2), "ms_solve": round(inf["ms_solve"], 2),
+                    "ms_refine": round(inf["ms_refine"], 2),
+                    "speedup_vs_f64": round(f64_ms / ms, 3) if f64_ms else None}
+            if prec != "f64":
+                cell["solver"] = f"gmres(restart {args.sweep_restart}, cap {args.sweep_cap})"
+            out.append(cell)
+            log(f"[sweep] smax {w.smax:.0e} {prec}: {ms:.1f} ms (precond {inf['ms_precond']:.1f}, factor "
+                f"{inf['ms_factor']:.1f}, refine {inf['ms_refine']:.1f}), status {st}, eta {eta_o:.2e}, outer "
+                f"{inf['iters']} inner {inf['inner_iters']}, kappa1 est {kap:.2e}, growth {inf['growth']:.2e}, "
+                f"speedup {cell['speedup_vs_f64']}")
+            del s
+        del Ah, X
+        torch.cuda.empty_cache()
+    return out
 
 
 def multi_rhs_measure(w, args) -> dict:
@@ -432,7 +466,9 @@ def main() -> int:
     ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--solver", default="luir", choices=["luir", "gmres"])
     ap.add_argument("--cpu-sample-n", type=int, default=12288)
-    ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form comparison")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form sweep")
+    ap.add_argument("--sweep-restart", type=int, default=100, help="GMRES cycle length in the precision-form sweep")
+    ap.add_argument("--sweep-cap", type=int, default=1000, help="inner GMRES steps at most per sweep cell")
     ap.add_argument("--gaussian-inputs", action="store_true",
                     help="counter runs: A ~ N(0,1) of the same shape instead of the Haar construction "
                          "(no QR; the kernels' memory traffic does not depend on the values)")
@@ -572,7 +608,7 @@ def main() -> int:
         torch.cuda.synchronize()
     roof["traffic"] = traffic_if_current(n)
     if not args.no_mixed and args.prec == "f64":
-        out["mixed"] = mixed_comparison(w, args, ms_per_step, value)
+        out["mixed_sweep"] = mixed_sweep(args, n)
     if not args.no_block_ge and args.prec == "f64":
         out["block_ge"] = block_ge_measure(w, args, ms_per_step)
     if not args.no_multi_rhs and args.prec == "f64":

@@ -122,6 +122,15 @@ typedef struct {
     double cond_h;              /* the same for H                                            */
     int32_t block_ge;           /* 1 after genp_factor_block, 0 after genp_factor             */
     int64_t row_swaps;          /* genp_factor_block: rows r with perm[r] != r (0 for GENP)   */
+    double ms_condest;          /* HIP-event time of the last genp_condest                    */
+    double cond1_c;             /* last genp_condest: norm1_c * norm1_inv (NaN before one)     */
+    double norm1_c;             /*   its estimate of ||C||_1, C = H A G from the FP64 A        */
+    double norm1_inv;           /*   its estimate of ||(L U)^{-1}||_1 from the stored factors  */
+    int32_t bwd_iters;          /* last genp_solve_backward(_ex): refinement steps taken       */
+    int32_t bwd_inner_iters;    /*   its GMRES inner iterations                                */
+    double bwd_eta;             /*   its final max_j eta_j against A^T (norm ||A||_1)          */
+    double anorm_1;             /* ||A||_1 (computed by the first adjoint solve after a
+                                   genp_precondition; NaN before)                             */
 } genp_info;
 
 /*
@@ -253,12 +262,45 @@ int genp_solve(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
  * factors for the correction.  Stops when max_j eta_j <= tol or after
  * max_iter outer steps, where eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf +
  * ||b_j||_inf).  eta_out (nullable, host, nrhs doubles) receives the final
- * eta_j.  Returns GENP_OK or GENP_ENOCONV (X holds the best iterate).
+ * eta_j.  Returns GENP_OK (eta <= tol, or tol = 0) or GENP_ENOCONV (X holds
+ * the best iterate).  GMRES runs one cycle of at most 50 steps per column and
+ * outer step, to a residual reduction of 1e-10 (genp_refine_ex sets these).
  * Synchronizes the stream.
  */
 int genp_refine(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
                 double* X, int64_t ldx, int max_iter, double tol, int solver,
                 double* eta_out);
+
+/* Options of genp_refine_ex and genp_solve_backward_ex. */
+#define GENP_GMRES_MAX_RESTART 1024
+typedef struct {
+    int32_t solver;       /* GENP_SOLVER_LUIR or GENP_SOLVER_GMRES                               */
+    int32_t max_outer;    /* corrections (outer steps) at most, >= 0                               */
+    int32_t restart;      /* GMRES: steps of one cycle (one cycle per column and outer step),
+                             1 .. GENP_GMRES_MAX_RESTART; 0 = 50                                   */
+    int32_t max_inner;    /* GMRES: inner steps summed over all cycles at most (0 = no cap); the
+                             last cycle is shortened to fit                                         */
+    double tol;           /* stop once max_j eta_j <= tol (0: run the steps, no target)             */
+    double inner_rtol;    /* GMRES: a cycle stops once its residual 2-norm has dropped by this
+                             factor (0 = 1e-10)                                                      */
+} genp_refine_opts;
+
+/*
+ * genp_refine with every option: LU-IR (section 7.1) or FP64 GMRES-IR for the correction
+ * equation A d = r, right-preconditioned by M^{-1} = G (LU)^{-1} H (the factors' inverse, so
+ * that A M^{-1} = I for exact factors).  Each outer step computes R = B - A X in FP64 from the
+ * original A, then the correction (LU-IR: D = M^{-1} R; GMRES: one cycle of at most
+ * o->restart steps per column, classical Gram-Schmidt applied twice, within the o->max_inner
+ * budget), X += D.  Stops at max_j eta_j <= o->tol, after o->max_outer steps, when the budget
+ * is spent, or when a step raised eta (it is undone; X holds the best iterate).  Returns GENP_OK
+ * (eta <= tol, or tol = 0) or GENP_ENOCONV; eta_out (nullable, host, nrhs doubles) receives the
+ * final eta_j; genp_info records the steps, the inner steps and the eta history.
+ * Errors: GENP_EINVAL (bad options or arguments), GENP_ESTATE, GENP_ENOMEM (the Krylov basis,
+ * (restart + 1) n_pad doubles, is allocated on first use of a larger restart), GENP_EDEVICE.
+ * Synchronizes the stream.
+ */
+int genp_refine_ex(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                   const genp_refine_opts* opts, double* eta_out);
 
 /*
  * Not in the paper: the differentiation of its solve.  For X = A^{-1} B and a
@@ -273,6 +315,33 @@ int genp_solve_backward(genp_ctx* ctx, const double* W, int64_t ldw,
                         const double* X, int64_t ldx, int64_t nrhs,
                         double* dB, int64_t lddb, double* dA, int64_t ldda,
                         int refine_iters);
+
+/*
+ * genp_solve_backward with the refinement of dB against A^T chosen by opts (as for
+ * genp_refine_ex, with A^T in place of A, M^{-T} = H^T (LU)^{-T} G^T as the preconditioner and
+ * eta_j = ||w_j - A^T db_j||_inf / (||A||_1 ||db_j||_inf + ||w_j||_inf)).  genp_solve_backward is
+ * this call with LU-IR, refine_iters steps and tol = 0.  Returns GENP_OK or GENP_ENOCONV (dB
+ * holds the best iterate, dA is formed from it); eta_out (nullable, host, nrhs doubles) receives
+ * the final eta_j; genp_info records bwd_iters, bwd_inner_iters and bwd_eta.  Synchronizes
+ * the stream.
+ */
+int genp_solve_backward_ex(genp_ctx* ctx, const double* W, int64_t ldw, const double* X, int64_t ldx,
+                           int64_t nrhs, double* dB, int64_t lddb, double* dA, int64_t ldda,
+                           const genp_refine_opts* opts, double* eta_out);
+
+/*
+ * Condition estimate of the factored matrix, kappa_1 ~ ||C||_1 ||(L U)^{-1}||_1, by the
+ * Hager-Higham 1-norm estimator (Higham, ACM TOMS 14 (1988), Algorithm 4.1: at most five
+ * products with the transposed operator, then the alternating-sign vector): ||C||_1 from
+ * products with C = H A G and C^T computed from the FP64 A and the multipliers, and
+ * ||(L U)^{-1}||_1 from substitutions with the stored factors (in the working precision, so for
+ * FP32 / BF16 contexts it is the inverse of the low-precision factors that refinement uses).
+ * Each estimate is a lower bound of the norm it estimates (rarely below a third of it).  This is
+ * what section 4 bounds (the conditioning of A G given that of A and G, Theorem 4.1 and
+ * Corollary 4.1).  kappa, norm_c, norm_inv: host, nullable.  Requires a successful factorization
+ * (else GENP_ESTATE).  Synchronizes the stream.
+ */
+int genp_condest(genp_ctx* ctx, double* kappa, double* norm_c, double* norm_inv);
 
 /* Copy diagnostics (host struct).  Synchronizes the stream. */
 int genp_get_info(const genp_ctx* ctx, genp_info* info);

@@ -179,3 +179,20 @@ hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, i
 hipError_t launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,
                                   hipStream_t s);
 hipError_t launch_scale2d(double alpha, double* X, long long ldx, int rows, int cols, hipStream_t s);
+
+// Vector kernels of GMRES and of the 1-norm estimator (krylov.hip).
+// out[i] = V_i . w for i < j1, V_i = V + i * ldv (n entries each); fixed reduction order.
+hipError_t launch_multidot(int n, int j1, const double* V, long long ldv, const double* w, double* out,
+                           hipStream_t s);
+// out[0] = ||y||_1, out[1] = 1 if sign(y) == xi elementwise (sign(0) = +1) else 0; then xi = sign(y).
+hipError_t launch_cest_sign(int n, const double* y, double* xi, double* out, hipStream_t s);
+// out[0] = ||z||_inf, out[1] = first index attaining it, out[2] = z[jlast] (or -1 when jlast < 0).
+hipError_t launch_cest_argmax(int n, const double* z, int jlast, double* out, hipStream_t s);
+// x_i = (-1)^i (1 + i / (n - 1)), i < n.
+hipError_t launch_cest_alt(int n, double* x, hipStream_t s);
+// x = e_j (length n).
+hipError_t launch_unit_vector(int n, int j, double* x, hipStream_t s);
+// ||A||_1 = max_j sum_i |A(i, j)| of an n x n FP64 matrix into *out (bits of a non-negative
+// double, atomicMax: zero it first); part: scratch of part_cap doubles (at least n).
+hipError_t launch_col_abs_sum_max(const double* A, long long lda, int n, double* part, long long part_cap,
+                                  unsigned long long* out, hipStream_t s);

@@ -29,10 +29,10 @@
 namespace {
 
 enum { ST_CREATED = 0, ST_PRECOND = 1, ST_FACTORED = 2, ST_BROKEN = 3 };
-enum { EV_PRE = 0, EV_FAC = 1, EV_SOL = 2, EV_REF = 3, EV_BWD = 4, EV_N = 5 };
+enum { EV_PRE = 0, EV_FAC = 1, EV_SOL = 2, EV_REF = 3, EV_BWD = 4, EV_CEST = 5, EV_N = 6 };
 
 // device reduction slots (bit patterns of non-negative doubles)
-enum { R_MAXC = 0, R_MAXU = 1, R_ANORM = 2, R_COLS = 8 };   // R_COLS: 3 * 256 per-column maxima
+enum { R_MAXC = 0, R_MAXU = 1, R_ANORM = 2, R_ANORM1 = 3, R_COLS = 8 };   // R_COLS: 3 * 256 per-column maxima
 
 // One multiplier (right G or left H) as the library keeps it.
 struct Mult {
@@ -71,12 +71,17 @@ struct genp_ctx {
     double* R = nullptr;       // n_pad x kcap
     double* Dx = nullptr;      // n_pad x kcap
     double* part = nullptr;    // split-K partials: KSPLIT_MAX x n_pad x kcap
-    // GMRES-IR: Krylov basis (restart + 1 vectors of n_pad), two n_pad work vectors, dot partials
-    int gm_restart = 50;
+    // GMRES-IR: Krylov basis (gm_cap + 1 vectors of n_pad), the Gram-Schmidt coefficients of
+    // one Arnoldi step (2 (gm_cap + 2) doubles), three n_pad work vectors
+    int gm_cap = 0;
     double* gm_V = nullptr;
     double* gm_w = nullptr;
     double* gm_z = nullptr;
+    double* gm_r = nullptr;
     double* gm_h = nullptr;
+    // 1-norm estimator: four n_pad vectors, then 8 scalars
+    double* cest = nullptr;
+    double anorm1 = -1.0;              // ||A||_1 (= ||A^T||_inf), < 0 until the adjoint needs it
     int state = ST_CREATED;
     genp_info info{};
     hipEvent_t ev0[EV_N]{}, ev1[EV_N]{};
@@ -366,9 +371,10 @@ int solve_into(genp_ctx* c, const double* Bin, int64_t ldb, int k, double* X, in
     return apply_mult(c, c->mr, 0, k, 1.0, Z, ldz, 0.0, nullptr, 0, X, ldx);
 }
 
-// eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf), host result.
+// eta_j = ||r_j||_inf / (anorm ||x_j||_inf + ||b_j||_inf), host result (anorm = ||A||_inf, or
+// ||A^T||_inf = ||A||_1 for the transposed system).
 int backward_error(genp_ctx* c, const double* R, int64_t ldr, const double* X, int64_t ldx,
-                   const double* B, int64_t ldb, int k, std::vector<double>& eta) {
+                   const double* B, int64_t ldb, int k, std::vector<double>& eta, double anorm) {
     unsigned long long* cols = c->red + R_COLS;
     HIPCK(hipMemsetAsync(cols, 0, sizeof(unsigned long long) * 3 * 256, c->stream));
     HIPCK(launch_col_abs_max(R, ldr, (int)c->n, k, cols, c->stream));
@@ -381,7 +387,7 @@ int backward_error(genp_ctx* c, const double* R, int64_t ldr, const double* X, i
     eta.resize(k);
     for (int j = 0; j < k; ++j) {
         const double r = bits_to_double(h[j]), x = bits_to_double(h[256 + j]), b = bits_to_double(h[512 + j]);
-        const double den = c->anorm * x + b;
+        const double den = anorm * x + b;
         eta[j] = (den > 0) ? r / den : (r > 0 ? INFINITY : 0.0);
         if (isnan(r) || isnan(x)) eta[j] = NAN;
     }
@@ -403,76 +409,93 @@ double max_of(const std::vector<double>& v) {
 // built from the stored (possibly low-precision) factors.  Classical Gram-Schmidt
 // applied twice on the device; Hessenberg QR by Givens rotations on the host.
 
-int ensure_gmres(genp_ctx* c) {
-    if (c->gm_V) return GENP_OK;
+int ensure_gmres(genp_ctx* c, int m) {
     const size_t np = (size_t)c->n_pad;
-    if (hipMalloc(&c->gm_V, (c->gm_restart + 1) * np * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->gm_w, np * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->gm_z, np * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->gm_h, 2 * (c->gm_restart + 2) * sizeof(double)) != hipSuccess)
-        return GENP_ENOMEM;
-    return GENP_OK;
-}
-
-// out (j+1 doubles, host) = V[0..j] . w ; V rows of length n (stride n_pad)
-int multidot(genp_ctx* c, int j1, const double* w, double* out) {
-    const int n = (int)c->n;
-    HIPCK(launch_gemv_f64(j1, n, 1, 1.0, c->gm_V, c->n_pad, OP_N, 0, w, 1, 0.0, nullptr, 1, c->gm_h, 1, c->stream));
-    HIPCK(hipMemcpyAsync(out, c->gm_h, j1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCK(hipStreamSynchronize(c->stream));
-    return GENP_OK;
-}
-
-// w -= V[0..j]^T h  (h on the host, copied to the device)
-int sub_combination(genp_ctx* c, int j1, const double* h, double* w, double sign) {
-    HIPCK(hipMemcpyAsync(c->gm_h, h, j1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCK(launch_gemv_f64((int)c->n, j1, 1, sign, c->gm_V, c->n_pad, OP_T, 0, c->gm_h, 1, 1.0, w, 1, w, 1,
-                          c->stream));
-    return GENP_OK;
-}
-
-// z = M^{-1} v = G U^{-1} L^{-1} v (n rows)
-int precond(genp_ctx* c, const double* v, double* z) { return solve_into(c, v, 1, 1, z, 1); }
-
-// one restart cycle on column r (n, stride 1) -> correction d (n); returns inner iterations
-int gmres_cycle(genp_ctx* c, const double* r, double* d, double tol_rel, int* iters_out) {
-    const int n = (int)c->n, m = c->gm_restart;
-    double beta;
-    {
-        double t;
-        HIPCK(hipMemcpyAsync(c->gm_V, r, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        CK(multidot(c, 1, c->gm_V, &t));
-        beta = sqrt(t);
+    if (!c->gm_w) {
+        if (hipMalloc(&c->gm_w, np * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->gm_z, np * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->gm_r, np * sizeof(double)) != hipSuccess)
+            return GENP_ENOMEM;
     }
+    if (m > c->gm_cap) {
+        hipFree(c->gm_V);
+        hipFree(c->gm_h);
+        c->gm_V = c->gm_h = nullptr;
+        c->gm_cap = 0;
+        if (hipMalloc(&c->gm_V, (size_t)(m + 1) * np * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->gm_h, 2 * (size_t)(m + 2) * sizeof(double)) != hipSuccess)
+            return GENP_ENOMEM;
+        c->gm_cap = m;
+    }
+    return GENP_OK;
+}
+
+// X (n x k) = H^T U^{-T} L^{-T} G^T Bin (the transposed solve: C^T = G^T A^T H^T), Z as workspace.
+int solve_t_into(genp_ctx* c, const double* Bin, int64_t ldb, int k, double* X, int64_t ldx) {
+    double* Z = c->Z;
+    const int64_t ldz = k;
+    if (c->n_pad > c->n)
+        HIPCK(launch_fill2d(0.0, Z + c->n * ldz, ldz, (int)(c->n_pad - c->n), k, c->stream));
+    CK(apply_mult(c, c->mr, 1, k, 1.0, Bin, ldb, 0.0, nullptr, 0, Z, ldz));
+    CK(lu_solve_trans_inplace(c, Z, ldz, k));
+    return apply_mult(c, c->ml, 1, k, 1.0, Z, ldz, 0.0, nullptr, 0, X, ldx);
+}
+
+// z = M^{-1} v with M^{-1} = G (LU)^{-1} H, or its transpose for the adjoint system (n rows)
+int precond(genp_ctx* c, bool trans, const double* v, double* z) {
+    return trans ? solve_t_into(c, v, 1, 1, z, 1) : solve_into(c, v, 1, 1, z, 1);
+}
+
+// w = A z, or A^T z (n rows, FP64)
+int op_a(genp_ctx* c, bool trans, const double* z, double* w) {
+    const int n = (int)c->n;
+    return skinny(c, n, n, 1, 1.0, c->A, c->lda, trans ? OP_T : OP_N, 0, z, 1, 0.0, nullptr, 1, w, 1);
+}
+
+// One cycle of at most m steps of FP64 GMRES for Op d = r (Op = A, or A^T when trans), right-
+// preconditioned by M^{-1}, from d = 0: Arnoldi with classical Gram-Schmidt applied twice, the
+// products and the new basis vector on the device, the Hessenberg matrix and its Givens
+// rotations on the host (one round trip per step).  r (n doubles) is read before anything is
+// written; d receives the correction.  Stops early once the rotated residual norm is
+// <= tol_rel ||r||_2.  *iters_out = steps taken.
+int gmres_cycle(genp_ctx* c, bool trans, int m, const double* r, double* d, double tol_rel, int* iters_out) {
+    const int n = (int)c->n;
+    const int64_t np = c->n_pad;
+    double* V = c->gm_V;
+    double* hd = c->gm_h;               // device: h (m + 2), then the second pass h2 (m + 2)
+    double* hd2 = hd + (m + 2);
     *iters_out = 0;
-    if (!(beta > 0)) {
+    HIPCK(hipMemcpyAsync(V, r, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCK(launch_multidot(n, 1, V, np, V, hd, c->stream));
+    double beta = 0.0;
+    HIPCK(hipMemcpyAsync(&beta, hd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    beta = sqrt(beta);
+    if (!(beta > 0) || !std::isfinite(beta)) {
         HIPCK(launch_fill2d(0.0, d, 1, n, 1, c->stream));
         return GENP_OK;
     }
-    HIPCK(launch_scale2d(1.0 / beta, c->gm_V, 1, n, 1, c->stream));   // v0 = r / beta
-    std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), h(m + 1), h2(m + 1);
+    HIPCK(launch_scale2d(1.0 / beta, V, 1, n, 1, c->stream));   // v_0 = r / beta
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), hh(2 * (m + 2));
     g[0] = beta;
     int k = 0;
     for (; k < m; ++k) {
-        double* vk = c->gm_V + (size_t)k * c->n_pad;
-        double* vk1 = c->gm_V + (size_t)(k + 1) * c->n_pad;
-        CK(precond(c, vk, c->gm_z));
-        // w = A z
-        CK(skinny(c, n, n, 1, 1.0, c->A, c->lda, OP_N, 0, c->gm_z, 1, 0.0, nullptr, 1, c->gm_w, 1));
-        CK(multidot(c, k + 1, c->gm_w, h.data()));
-        CK(sub_combination(c, k + 1, h.data(), c->gm_w, -1.0));
-        CK(multidot(c, k + 1, c->gm_w, h2.data()));
-        CK(sub_combination(c, k + 1, h2.data(), c->gm_w, -1.0));
-        for (int i = 0; i <= k; ++i) h[i] += h2[i];
-        // ||w||: copy w into v_{k+1} and dot it with itself
-        HIPCK(hipMemcpyAsync(vk1, c->gm_w, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        double nn;
-        HIPCK(launch_gemv_f64(1, n, 1, 1.0, vk1, c->n_pad, OP_N, 0, c->gm_w, 1, 0.0, nullptr, 1, c->gm_h, 1,
-                              c->stream));
-        HIPCK(hipMemcpyAsync(&nn, c->gm_h, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        double* vk = V + (size_t)k * np;
+        double* vk1 = V + (size_t)(k + 1) * np;
+        CK(precond(c, trans, vk, c->gm_z));
+        CK(op_a(c, trans, c->gm_z, vk1));                       // w, built in place of v_{k+1}
+        // w -= V h, h = V^T w; twice (the second pass restores orthogonality lost in the first)
+        HIPCK(launch_multidot(n, k + 1, V, np, vk1, hd, c->stream));
+        HIPCK(launch_gemv_f64(n, k + 1, 1, -1.0, V, np, OP_T, 0, hd, 1, 1.0, vk1, 1, vk1, 1, c->stream));
+        HIPCK(launch_multidot(n, k + 1, V, np, vk1, hd2, c->stream));
+        HIPCK(launch_gemv_f64(n, k + 1, 1, -1.0, V, np, OP_T, 0, hd2, 1, 1.0, vk1, 1, vk1, 1, c->stream));
+        HIPCK(launch_multidot(n, 1, vk1, np, vk1, hd2 + k + 1, c->stream));   // ||w||^2
+        HIPCK(hipMemcpyAsync(hh.data(), hd, 2 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCK(hipStreamSynchronize(c->stream));
-        const double hk1 = sqrt(nn);
-        // apply the previous rotations to the new column, then a new rotation
+        std::vector<double> h(k + 2);
+        for (int i = 0; i <= k; ++i) h[i] = hh[i] + hh[(m + 2) + i];
+        const double hk1 = sqrt(hh[(m + 2) + k + 1]);
+        // the earlier rotations on the new column, then a new one that zeroes h[k+1]
         for (int i = 0; i < k; ++i) {
             const double a = cs[i] * h[i] + sn[i] * h[i + 1];
             h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
@@ -484,26 +507,31 @@ int gmres_cycle(genp_ctx* c, const double* r, double* d, double tol_rel, int* it
         h[k] = den;
         g[k + 1] = -sn[k] * g[k];
         g[k] = cs[k] * g[k];
-        for (int i = 0; i <= k; ++i) H[i * m + k] = h[i];
-        const bool done = fabs(g[k + 1]) <= tol_rel * beta || !(hk1 > 0) || !isfinite(hk1);
-        if (!done) HIPCK(launch_scale2d(1.0 / hk1, vk1, 1, n, 1, c->stream));
+        for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = h[i];
+        const bool done = fabs(g[k + 1]) <= tol_rel * beta || !(hk1 > 0) || !std::isfinite(hk1);
         if (done) {
             ++k;
             break;
         }
+        HIPCK(launch_scale2d(1.0 / hk1, vk1, 1, n, 1, c->stream));
     }
     *iters_out = k;
     // y = R^{-1} g (upper triangular k x k), u = V y, d = M^{-1} u
-    std::vector<double> y(k, 0.0);
+    std::vector<double> y(std::max(k, 1), 0.0);
     for (int i = k - 1; i >= 0; --i) {
         double v = g[i];
-        for (int t = i + 1; t < k; ++t) v -= H[i * m + t] * y[t];
-        y[i] = (H[i * m + i] != 0.0) ? v / H[i * m + i] : 0.0;
+        for (int t = i + 1; t < k; ++t) v -= H[(size_t)i * m + t] * y[t];
+        y[i] = (H[(size_t)i * m + i] != 0.0) ? v / H[(size_t)i * m + i] : 0.0;
     }
-    HIPCK(launch_fill2d(0.0, c->gm_w, 1, n, 1, c->stream));
-    if (k > 0) CK(sub_combination(c, k, y.data(), c->gm_w, 1.0));
-    CK(precond(c, c->gm_w, d));
-    return GENP_OK;
+    if (k > 0) {
+        HIPCK(hipMemcpyAsync(hd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCK(launch_gemv_f64(n, k, 1, 1.0, V, np, OP_T, 0, hd, 1, 0.0, nullptr, 1, c->gm_w, 1, c->stream));
+    } else {
+        HIPCK(launch_fill2d(0.0, c->gm_w, 1, n, 1, c->stream));
+    }
+    // the host vector y must outlive the copy above
+    HIPCK(hipStreamSynchronize(c->stream));
+    return precond(c, trans, c->gm_w, d);
 }
 
 int check_ctx(const genp_ctx* c) {
@@ -795,7 +823,9 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->gm_V);
     hipFree(c->gm_w);
     hipFree(c->gm_z);
+    hipFree(c->gm_r);
     hipFree(c->gm_h);
+    hipFree(c->cest);
     for (int e = 0; e < EV_N; ++e) {
         if (c->ev0[e]) hipEventDestroy(c->ev0[e]);
         if (c->ev1[e]) hipEventDestroy(c->ev1[e]);
@@ -827,6 +857,9 @@ int genp_precondition2(genp_ctx* c, const double* A, int64_t lda, int left, cons
     c->state = ST_CREATED;
     c->A = A;
     c->lda = lda;
+    c->anorm1 = -1.0;
+    c->info.anorm_1 = std::numeric_limits<double>::quiet_NaN();
+    c->info.cond1_c = c->info.norm1_c = c->info.norm1_inv = std::numeric_limits<double>::quiet_NaN();
     if (right == GENP_G_HOUSEHOLDER || left == GENP_G_HOUSEHOLDER) CK(ensure_rhs(c, 4));
     ev_begin(c, EV_PRE);
     CK(set_mult(c, c->mr, right, G, ldg));
@@ -1210,56 +1243,65 @@ static int chain_status(genp_ctx* c) {
     return GENP_EDEVICE;
 }
 
-int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, int max_iter,
-                double tol, int solver, double* eta_out) {
-    CK(check_ctx(c));
-    if (c->state != ST_FACTORED) return GENP_ESTATE;
-    if (!B || !X || nrhs < 1 || nrhs > 256 || ldb < nrhs || ldx < nrhs || max_iter < 0 || !(tol >= 0))
-        return GENP_EINVAL;
-    if (solver != GENP_SOLVER_LUIR && solver != GENP_SOLVER_GMRES) return GENP_EINVAL;
-    CK(ensure_rhs(c, nrhs));
-    if (solver == GENP_SOLVER_GMRES) CK(ensure_gmres(c));
-    int inner_total = 0;
-    const int k = (int)nrhs;
+}  // extern "C"
+
+namespace {
+
+// Refinement of X (n x k) against Op = A (or A^T when trans) and the right-hand sides B, in FP64:
+// R = B - Op X, then the correction D = M^{-1} R (LU-IR, section 7.1) or, per column, one GMRES
+// cycle for Op d = r right-preconditioned by M^{-1}; X += D.  Stops when max_j eta_j <= tol, after
+// o.max_outer corrections, once the GMRES budget o.max_inner is spent, or when a correction made
+// eta worse (it is undone: X is the best iterate).  Status: GENP_OK when eta <= tol, or when
+// tol = 0 (the steps were asked for, not a target); else GENP_ENOCONV.
+int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
+                const genp_refine_opts& o, std::vector<double>& eta, int* iters_out, int* inner_out,
+                double* hist, int* n_hist) {
     const int n = (int)c->n;
-    ev_begin(c, EV_REF);
-    std::vector<double> eta;
-    c->info.n_eta = 0;
+    const double anorm = trans ? c->anorm1 : c->anorm;
+    const int restart = o.restart > 0 ? o.restart : 50;
+    const double rtol = o.inner_rtol > 0 ? o.inner_rtol : 1e-10;
+    const int aop = trans ? OP_T : OP_N;
+    int inner_total = 0;
     double best = INFINITY;
     int it = 0;
     int status = GENP_OK;
+    *n_hist = 0;
     for (;;) {
-        // R = B - A X
-        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, OP_N, 0, X, ldx, 1.0, B, ldb, c->R, k));
-        CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta));
+        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
+        CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
         const double e = max_of(eta);
-        if (c->info.n_eta < GENP_ETA_HIST) c->info.eta_hist[c->info.n_eta++] = e;
-        if (!(e <= best)) {
-            if (it > 0) {
-                // the last correction made things worse (or produced NaN): undo it
-                HIPCK(launch_axpy2d(-1.0, c->Dx, k, X, ldx, n, k, c->stream));
-                CK(skinny(c, n, n, k, -1.0, c->A, c->lda, OP_N, 0, X, ldx, 1.0, B, ldb, c->R, k));
-                CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta));
-                status = GENP_ENOCONV;
-                break;
-            }
-        }
-        best = std::min(best, e);
-        if (e <= tol) break;
-        if (it >= max_iter) {
-            status = (tol > 0) ? GENP_ENOCONV : GENP_OK;
+        if (*n_hist < GENP_ETA_HIST) hist[(*n_hist)++] = e;
+        if (!(e <= best) && it > 0) {
+            // the last correction made things worse (or produced NaN): undo it
+            HIPCK(launch_axpy2d(-1.0, c->Dx, k, X, ldx, n, k, c->stream));
+            CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
+            CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
+            status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
             break;
         }
-        if (solver == GENP_SOLVER_LUIR) {
-            // Dx = G (LU)^{-1} R ; X += Dx
-            CK(solve_into(c, c->R, k, k, c->Dx, k));
+        best = std::min(best, e);
+        if (e <= o.tol) break;
+        const bool budget = o.solver == GENP_SOLVER_GMRES && o.max_inner > 0 && inner_total >= o.max_inner;
+        if (it >= o.max_outer || budget) {
+            status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
+            break;
+        }
+        if (o.solver == GENP_SOLVER_LUIR) {
+            // Dx = M^{-1} R
+            if (trans) CK(solve_t_into(c, c->R, k, k, c->Dx, k));
+            else CK(solve_into(c, c->R, k, k, c->Dx, k));
         } else {
-            // Dx_j = GMRES(A d = r_j, right preconditioner G (LU)^{-1}), column by column
             for (int j = 0; j < k; ++j) {
-                HIPCK(launch_copy2d(c->R + j, k, c->gm_z, 1, n, 1, c->stream));
-                HIPCK(hipMemcpyAsync(c->Z, c->gm_z, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                int m = restart;
+                if (o.max_inner > 0) m = std::min(m, o.max_inner - inner_total);
+                if (m <= 0) {
+                    // budget spent: the remaining columns take no correction this step
+                    HIPCK(launch_fill2d(0.0, c->Dx + j, k, n, 1, c->stream));
+                    continue;
+                }
+                HIPCK(launch_copy2d(c->R + j, k, c->gm_r, 1, n, 1, c->stream));
                 int its = 0;
-                CK(gmres_cycle(c, c->Z, c->gm_z, 1e-10, &its));
+                CK(gmres_cycle(c, trans, m, c->gm_r, c->gm_z, rtol, &its));
                 inner_total += its;
                 HIPCK(launch_copy2d(c->gm_z, 1, c->Dx + j, k, n, 1, c->stream));
             }
@@ -1267,44 +1309,49 @@ int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double*
         HIPCK(launch_axpy2d(1.0, c->Dx, k, X, ldx, n, k, c->stream));
         ++it;
     }
-    ev_end(c, EV_REF);
-    HIPCK(hipStreamSynchronize(c->stream));
-    CK(chain_status(c));
-    c->info.iters = it;
-    c->info.inner_iters = inner_total;
-    c->info.eta = max_of(eta);
-    if (eta_out)
-        for (int j = 0; j < k; ++j) eta_out[j] = eta[j];
+    *iters_out = it;
+    *inner_out = inner_total;
     return status;
 }
 
-int genp_solve_backward(genp_ctx* c, const double* W, int64_t ldw, const double* X, int64_t ldx, int64_t nrhs,
-                        double* dB, int64_t lddb, double* dA, int64_t ldda, int refine_iters) {
-    CK(check_ctx(c));
-    if (c->state != ST_FACTORED) return GENP_ESTATE;
-    if (!W || !X || !dB || nrhs < 1 || nrhs > 256 || ldw < nrhs || ldx < nrhs || lddb < nrhs ||
-        refine_iters < 0 || (dA && ldda < c->n))
+int check_opts(const genp_refine_opts* o) {
+    if (!o) return GENP_EINVAL;
+    if (o->solver != GENP_SOLVER_LUIR && o->solver != GENP_SOLVER_GMRES) return GENP_EINVAL;
+    if (o->max_outer < 0 || o->max_inner < 0 || o->restart < 0 || o->restart > GENP_GMRES_MAX_RESTART ||
+        !(o->tol >= 0) || !(o->inner_rtol >= 0))
         return GENP_EINVAL;
-    CK(ensure_rhs(c, nrhs));
+    return GENP_OK;
+}
+
+// ||A||_1 of the borrowed A, once per precondition (the norm in the adjoint system's eta).
+int ensure_anorm1(genp_ctx* c) {
+    if (c->anorm1 >= 0.0) return GENP_OK;
+    unsigned long long* slot = c->red + R_ANORM1;
+    HIPCK(hipMemsetAsync(slot, 0, sizeof(unsigned long long), c->stream));
+    HIPCK(launch_col_abs_sum_max(c->A, c->lda, (int)c->n, c->part, (long long)KSPLIT_MAX * c->n_pad * c->kcap, slot,
+                                 c->stream));
+    unsigned long long h = 0;
+    HIPCK(hipMemcpyAsync(&h, slot, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->anorm1 = bits_to_double(h);
+    return GENP_OK;
+}
+
+// dB = A^{-T} W (= H^T L^{-T} U^{-T} G^T W from the factors), refined against A^T per o, and
+// dA = -dB X^T when dA is not NULL.
+int backward_impl(genp_ctx* c, const double* W, int64_t ldw, const double* X, int64_t ldx, int64_t nrhs, double* dB,
+                  int64_t lddb, double* dA, int64_t ldda, const genp_refine_opts& o, double* eta_out) {
     const int k = (int)nrhs, n = (int)c->n;
+    CK(ensure_rhs(c, nrhs));
+    if (o.solver == GENP_SOLVER_GMRES) CK(ensure_gmres(c, o.restart > 0 ? o.restart : 50));
+    CK(ensure_anorm1(c));
     ev_begin(c, EV_BWD);
-    // dB = H^T L^{-T} U^{-T} G^T W ; then refinement against A^T
-    for (int step = 0; step <= refine_iters; ++step) {
-        const double* rhs = W;
-        int64_t ldr = ldw;
-        if (step > 0) {
-            // R = W - A^T dB
-            CK(skinny(c, n, n, k, -1.0, c->A, c->lda, OP_T, 0, dB, lddb, 1.0, W, ldw, c->R, k));
-            rhs = c->R;
-            ldr = k;
-        }
-        // Z = G^T rhs (rows n..n_pad zero)
-        if (c->n_pad > c->n) HIPCK(launch_fill2d(0.0, c->Z + (int64_t)n * k, k, (int)(c->n_pad - n), k, c->stream));
-        CK(apply_mult(c, c->mr, 1, k, 1.0, rhs, ldr, 0.0, nullptr, 0, c->Z, k));
-        CK(lu_solve_trans_inplace(c, c->Z, k, k));
-        // dB (+)= H^T Z
-        CK(apply_mult(c, c->ml, 1, k, 1.0, c->Z, k, step == 0 ? 0.0 : 1.0, dB, lddb, dB, lddb));
-    }
+    CK(solve_t_into(c, W, ldw, k, dB, lddb));
+    std::vector<double> eta;
+    int it = 0, inner = 0, nh = 0;
+    double hist[GENP_ETA_HIST];
+    const int status = refine_core(c, true, W, ldw, k, dB, lddb, o, eta, &it, &inner, hist, &nh);
+    if (status < 0) return status;
     if (dA) {
         // dA = -dB X^T
         GemmF64Args g{};
@@ -1324,6 +1371,190 @@ int genp_solve_backward(genp_ctx* c, const double* W, int64_t ldw, const double*
         HIPCK(launch_gemm_f64(g, 0, c->stream));
     }
     ev_end(c, EV_BWD);
+    HIPCK(hipStreamSynchronize(c->stream));
+    CK(chain_status(c));
+    c->info.bwd_iters = it;
+    c->info.bwd_inner_iters = inner;
+    c->info.bwd_eta = max_of(eta);
+    c->info.anorm_1 = c->anorm1;
+    if (eta_out)
+        for (int j = 0; j < k; ++j) eta_out[j] = eta[j];
+    return status;
+}
+
+int refine_impl(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                const genp_refine_opts& o, double* eta_out) {
+    CK(ensure_rhs(c, nrhs));
+    if (o.solver == GENP_SOLVER_GMRES) CK(ensure_gmres(c, o.restart > 0 ? o.restart : 50));
+    const int k = (int)nrhs;
+    ev_begin(c, EV_REF);
+    std::vector<double> eta;
+    int it = 0, inner = 0, nh = 0;
+    const int status = refine_core(c, false, B, ldb, k, X, ldx, o, eta, &it, &inner, c->info.eta_hist, &nh);
+    c->info.n_eta = nh;
+    if (status < 0) return status;
+    ev_end(c, EV_REF);
+    HIPCK(hipStreamSynchronize(c->stream));
+    CK(chain_status(c));
+    c->info.iters = it;
+    c->info.inner_iters = inner;
+    c->info.eta = max_of(eta);
+    if (eta_out)
+        for (int j = 0; j < k; ++j) eta_out[j] = eta[j];
+    return status;
+}
+
+// Hager-Higham estimate of ||B||_1 for an n x n operator given by y = B x (apply) and
+// y = B^T x (apply_t) on n_pad-vectors with zero padding (Higham 1988, Algorithm 4.1; at most
+// five products with B^T).  On the cycling exit the larger of the last two values is kept
+// (both are lower bounds of ||B||_1).
+template <class F, class FT>
+int hager_norm1(genp_ctx* c, F apply, FT apply_t, double* est_out) {
+    const int n = (int)c->n;
+    const int64_t np = c->n_pad;
+    double* x = c->cest;
+    double* y = x + np;
+    double* xi = y + np;
+    double* z = xi + np;
+    double* sc = z + np;
+    double hsc[3];
+    auto fetch = [&](int cnt) -> int {
+        HIPCK(hipMemcpyAsync(hsc, sc, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(hipStreamSynchronize(c->stream));
+        return GENP_OK;
+    };
+    HIPCK(launch_fill2d(0.0, x, 1, (int)(4 * np), 1, c->stream));
+    HIPCK(launch_fill2d(1.0 / n, x, 1, n, 1, c->stream));
+    CK(apply(x, y));
+    HIPCK(launch_cest_sign(n, y, xi, sc, c->stream));
+    CK(fetch(2));
+    double est = hsc[0];
+    if (n == 1) {
+        *est_out = est;
+        return GENP_OK;
+    }
+    CK(apply_t(xi, z));
+    HIPCK(launch_cest_argmax(n, z, -1, sc, c->stream));
+    CK(fetch(2));
+    int j = (int)hsc[1];
+    for (int iter = 2;; ++iter) {
+        HIPCK(launch_unit_vector(n, j, x, c->stream));
+        CK(apply(x, y));
+        HIPCK(launch_cest_sign(n, y, xi, sc, c->stream));
+        CK(fetch(2));
+        const double est_old = est;
+        est = hsc[0];
+        if (hsc[1] != 0.0 || est <= est_old) {   // repeated sign vector, or no increase
+            est = std::max(est, est_old);
+            break;
+        }
+        CK(apply_t(xi, z));
+        HIPCK(launch_cest_argmax(n, z, j, sc, c->stream));
+        CK(fetch(3));
+        const int jlast = j;
+        j = (int)hsc[1];
+        (void)jlast;
+        if (hsc[2] == hsc[0] || iter >= 5) break;
+    }
+    HIPCK(launch_cest_alt(n, x, c->stream));
+    CK(apply(x, y));
+    HIPCK(launch_cest_sign(n, y, xi, sc, c->stream));
+    CK(fetch(1));
+    const double alt = 2.0 * hsc[0] / (3.0 * n);
+    *est_out = std::max(est, alt);
+    return GENP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int genp_refine(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, int max_iter,
+                double tol, int solver, double* eta_out) {
+    genp_refine_opts o{};
+    o.solver = solver;
+    o.max_outer = max_iter;
+    o.restart = 50;
+    o.max_inner = 0;
+    o.tol = tol;
+    o.inner_rtol = 1e-10;
+    return genp_refine_ex(c, B, ldb, nrhs, X, ldx, &o, eta_out);
+}
+
+int genp_refine_ex(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                   const genp_refine_opts* o, double* eta_out) {
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    if (!B || !X || nrhs < 1 || nrhs > 256 || ldb < nrhs || ldx < nrhs) return GENP_EINVAL;
+    CK(check_opts(o));
+    return refine_impl(c, B, ldb, nrhs, X, ldx, *o, eta_out);
+}
+
+int genp_solve_backward(genp_ctx* c, const double* W, int64_t ldw, const double* X, int64_t ldx, int64_t nrhs,
+                        double* dB, int64_t lddb, double* dA, int64_t ldda, int refine_iters) {
+    if (refine_iters < 0) return GENP_EINVAL;
+    genp_refine_opts o{};
+    o.solver = GENP_SOLVER_LUIR;
+    o.max_outer = refine_iters;
+    o.tol = 0.0;
+    return genp_solve_backward_ex(c, W, ldw, X, ldx, nrhs, dB, lddb, dA, ldda, &o, nullptr);
+}
+
+int genp_solve_backward_ex(genp_ctx* c, const double* W, int64_t ldw, const double* X, int64_t ldx, int64_t nrhs,
+                           double* dB, int64_t lddb, double* dA, int64_t ldda, const genp_refine_opts* o,
+                           double* eta_out) {
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    if (!W || !X || !dB || nrhs < 1 || nrhs > 256 || ldw < nrhs || ldx < nrhs || lddb < nrhs || (dA && ldda < c->n))
+        return GENP_EINVAL;
+    CK(check_opts(o));
+    return backward_impl(c, W, ldw, X, ldx, nrhs, dB, lddb, dA, ldda, *o, eta_out);
+}
+
+int genp_condest(genp_ctx* c, double* kappa, double* norm_c, double* norm_inv) {
+    CK(check_ctx(c));
+    if (c->state != ST_FACTORED) return GENP_ESTATE;
+    CK(ensure_rhs(c, 4));
+    CK(ensure_gmres(c, 0));
+    if (!c->cest && hipMalloc(&c->cest, (4 * (size_t)c->n_pad + 8) * sizeof(double)) != hipSuccess)
+        return GENP_ENOMEM;
+    const int n = (int)c->n;
+    double* t1 = c->gm_w;
+    double* t2 = c->gm_z;
+    // (L U)^{-1} and its transpose on n_pad vectors (P and P^T included for block elimination)
+    auto inv = [&](const double* x, double* y) -> int {
+        HIPCK(hipMemcpyAsync(y, x, c->n_pad * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        return lu_solve_inplace(c, y, 1, 1);
+    };
+    auto inv_t = [&](const double* x, double* y) -> int {
+        HIPCK(hipMemcpyAsync(y, x, c->n_pad * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        return lu_solve_trans_inplace(c, y, 1, 1);
+    };
+    // C = H A G and C^T = G^T A^T H^T, from the original FP64 A and the multipliers
+    auto fwd = [&](const double* x, double* y) -> int {
+        CK(apply_mult(c, c->mr, 0, 1, 1.0, x, 1, 0.0, nullptr, 0, t1, 1));
+        CK(op_a(c, false, t1, t2));
+        return apply_mult(c, c->ml, 0, 1, 1.0, t2, 1, 0.0, nullptr, 0, y, 1);
+    };
+    auto fwd_t = [&](const double* x, double* y) -> int {
+        CK(apply_mult(c, c->ml, 1, 1, 1.0, x, 1, 0.0, nullptr, 0, t1, 1));
+        CK(op_a(c, true, t1, t2));
+        return apply_mult(c, c->mr, 1, 1, 1.0, t2, 1, 0.0, nullptr, 0, y, 1);
+    };
+    ev_begin(c, EV_CEST);
+    double ni = 0.0, nc = 0.0;
+    CK(hager_norm1(c, inv, inv_t, &ni));
+    CK(hager_norm1(c, fwd, fwd_t, &nc));
+    ev_end(c, EV_CEST);
+    HIPCK(hipStreamSynchronize(c->stream));
+    CK(chain_status(c));
+    (void)n;
+    c->info.norm1_c = nc;
+    c->info.norm1_inv = ni;
+    c->info.cond1_c = nc * ni;
+    if (kappa) *kappa = nc * ni;
+    if (norm_c) *norm_c = nc;
+    if (norm_inv) *norm_inv = ni;
     return GENP_OK;
 }
 
@@ -1335,7 +1566,7 @@ int genp_get_info(const genp_ctx* cc, genp_info* out) {
     CK(chain_status(c));
     float ms;
     double* slots[EV_N] = {&c->info.ms_precond, &c->info.ms_factor, &c->info.ms_solve, &c->info.ms_refine,
-                           &c->info.ms_backward};
+                           &c->info.ms_backward, &c->info.ms_condest};
     for (int e = 0; e < EV_N; ++e)
         if (c->ev_used[e] && hipEventElapsedTime(&ms, c->ev0[e], c->ev1[e]) == hipSuccess) *slots[e] = ms;
     *out = c->info;

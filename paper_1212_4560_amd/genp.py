@@ -5,7 +5,8 @@ memory (tensors) and the stream.  The functions mirror the C ABI of
 ``include/genp.h`` one to one:
 
     genp_create / genp_precondition / genp_factor / genp_solve /
-    genp_refine / genp_solve_backward / genp_get_info / genp_copy_work
+    genp_refine(_ex) / genp_solve_backward(_ex) / genp_condest / genp_get_info /
+    genp_copy_work
 
 plus :func:`solve` (the whole path in one call) and :class:`GenpSolve`, a
 ``torch.autograd.Function`` whose backward is the library's adjoint.
@@ -36,7 +37,9 @@ SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",
            "genp_factor_block", "genp_block_pivots", "genp_row_perm",
            "genp_lowrank", "genp_numerical_rank",
-           "genp_refine", "genp_solve_backward", "genp_get_info", "genp_copy_work", "genp_strerror")
+           "genp_refine", "genp_refine_ex", "genp_solve_backward", "genp_solve_backward_ex", "genp_condest",
+           "genp_get_info", "genp_copy_work", "genp_strerror")
+GMRES_MAX_RESTART = 1024
 
 
 class GenpInfo(ctypes.Structure):
@@ -58,12 +61,29 @@ class GenpInfo(ctypes.Structure):
         ("cond_g", ctypes.c_double),
         ("mult_left", ctypes.c_int32), ("cond_h", ctypes.c_double),
         ("block_ge", ctypes.c_int32), ("row_swaps", ctypes.c_int64),
+        ("ms_condest", ctypes.c_double), ("cond1_c", ctypes.c_double), ("norm1_c", ctypes.c_double),
+        ("norm1_inv", ctypes.c_double),
+        ("bwd_iters", ctypes.c_int32), ("bwd_inner_iters", ctypes.c_int32), ("bwd_eta", ctypes.c_double),
+        ("anorm_1", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "eta_hist"}
         d["eta_hist"] = [self.eta_hist[i] for i in range(self.n_eta)]
         return d
+
+
+class GenpRefineOpts(ctypes.Structure):
+    _fields_ = [
+        ("solver", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("restart", ctypes.c_int32),
+        ("max_inner", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+    ]
+
+
+def refine_opts(max_iter: int = 2, tol: float = 0.0, solver: str = "luir", restart: int = 50,
+                max_inner: int = 0, inner_rtol: float = 1e-10) -> GenpRefineOpts:
+    return GenpRefineOpts(SOLVERS[solver], int(max_iter), int(restart), int(max_inner), float(tol),
+                          float(inner_rtol))
 
 
 class GenpLrInfo(ctypes.Structure):
@@ -124,7 +144,11 @@ def load(path: str = LIB_PATH):
     L.genp_row_perm.argtypes = [vp, vp]
     L.genp_solve.argtypes = [vp, vp, i64, i64, vp, i64]
     L.genp_refine.argtypes = [vp, vp, i64, i64, vp, i64, i32, dbl, i32, ctypes.POINTER(dbl)]
+    L.genp_refine_ex.argtypes = [vp, vp, i64, i64, vp, i64, ctypes.POINTER(GenpRefineOpts), ctypes.POINTER(dbl)]
     L.genp_solve_backward.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp, i64, i32]
+    L.genp_solve_backward_ex.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp, i64,
+                                         ctypes.POINTER(GenpRefineOpts), ctypes.POINTER(dbl)]
+    L.genp_condest.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.genp_get_info.argtypes = [vp, ctypes.POINTER(GenpInfo)]
     L.genp_copy_work.argtypes = [vp, vp, i64]
     L.genp_strerror.argtypes = [i32]
@@ -270,17 +294,30 @@ class Solver:
         _check(load().genp_solve(self._h, b, ldb, k, x, ldx), "genp_solve")
         return X
 
-    def refine(self, B, X, max_iter: int = 2, tol: float = 0.0, solver: str = "luir"):
-        """In-place refinement of X; returns (status, eta per column)."""
+    def refine(self, B, X, max_iter: int = 2, tol: float = 0.0, solver: str = "luir", restart: int = None,
+               max_inner: int = 0, inner_rtol: float = 0.0):
+        """In-place refinement of X; returns (status, eta per column).  Without restart,
+        max_inner or inner_rtol this is genp_refine; with any of them genp_refine_ex."""
         k = B.shape[1]
         b, ldb = _mat(B, "B", self.n, k)
         x, ldx = _mat(X, "X", self.n, k)
         eta = (ctypes.c_double * k)()
-        st = _check(load().genp_refine(self._h, b, ldb, k, x, ldx, int(max_iter), float(tol),
-                                       SOLVERS[solver], eta), "genp_refine", allow=(OK, ENOCONV))
+        if restart is None and not max_inner and not inner_rtol:
+            st = _check(load().genp_refine(self._h, b, ldb, k, x, ldx, int(max_iter), float(tol),
+                                           SOLVERS[solver], eta), "genp_refine", allow=(OK, ENOCONV))
+        else:
+            o = refine_opts(max_iter, tol, solver, restart or 0, max_inner, inner_rtol)
+            st = _check(load().genp_refine_ex(self._h, b, ldb, k, x, ldx, ctypes.byref(o), eta),
+                        "genp_refine_ex", allow=(OK, ENOCONV))
         return st, [eta[i] for i in range(k)]
 
-    def solve_backward(self, W, X, want_dA: bool = True, refine_iters: int = 1):
+    def solve_backward(self, W, X, want_dA: bool = True, refine_iters: int = 1, solver: str = None,
+                       tol: float = 0.0, restart: int = 0, max_inner: int = 0, inner_rtol: float = 0.0,
+                       return_status: bool = False):
+        """dB = A^{-T} W and dA = -dB X^T from the stored factors.  With solver=None this is
+        genp_solve_backward (refine_iters LU-IR steps against A^T); with a solver name,
+        genp_solve_backward_ex (refine_iters outer steps, tol, GMRES restart / budget).
+        Returns (dB, dA), or (dB, dA, status, eta per column) with return_status."""
         import torch
         k = W.shape[1]
         w, ldw = _mat(W, "W", self.n, k)
@@ -292,9 +329,26 @@ class Solver:
         if want_dA:
             dA = torch.empty((self.n, self.n), dtype=torch.float64, device=W.device)
             da, ldda = _mat(dA, "dA", self.n, self.n)
-        _check(load().genp_solve_backward(self._h, w, ldw, x, ldx, k, db, lddb, da, ldda,
-                                          int(refine_iters)), "genp_solve_backward")
+        eta = (ctypes.c_double * k)()
+        if solver is None:
+            st = _check(load().genp_solve_backward(self._h, w, ldw, x, ldx, k, db, lddb, da, ldda,
+                                                   int(refine_iters)), "genp_solve_backward", allow=(OK, ENOCONV))
+            etal = [float("nan")] * k
+        else:
+            o = refine_opts(refine_iters, tol, solver, restart, max_inner, inner_rtol)
+            st = _check(load().genp_solve_backward_ex(self._h, w, ldw, x, ldx, k, db, lddb, da, ldda,
+                                                      ctypes.byref(o), eta), "genp_solve_backward_ex",
+                        allow=(OK, ENOCONV))
+            etal = [eta[i] for i in range(k)]
+        if return_status:
+            return dB, dA, st, etal
         return dB, dA
+
+    def condest(self) -> dict:
+        """Hager-Higham estimates of ||C||_1, ||(LU)^{-1}||_1 and their product (genp_condest)."""
+        kap, nc, ni = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load().genp_condest(self._h, ctypes.byref(kap), ctypes.byref(nc), ctypes.byref(ni)), "genp_condest")
+        return {"kappa1": kap.value, "norm1_c": nc.value, "norm1_inv": ni.value}
 
     def info(self) -> dict:
         inf = GenpInfo()

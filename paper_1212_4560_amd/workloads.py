@@ -251,6 +251,35 @@ def haar_logspaced(n: int, smax: float, mult: str = MULT_DENSE, nrhs: int = 1,
     return Workload("haar_logspaced", n, seed, A, B, mult, G=G, p=p, smax=smax)
 
 
+def haar_family(n: int, smaxes, mult: str = MULT_DENSE, nrhs: int = 1, seed: int = 2, device: str = "cuda"):
+    """The haar_logspaced recipe for several smax at once: one draw of Z_U, Z_V, G and B (the
+    draws of haar_logspaced with this seed), then A = U diag(s) V^T for each smax in turn.
+    Yields one Workload per smax; only the current A is held beside U and V."""
+    import torch
+    dev = torch.device(device)
+    g = np.random.default_rng(seed)
+
+    def q_of(zh):
+        z = torch.from_numpy(zh).to(dev)
+        q, r = torch.linalg.qr(z)
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+
+    U = q_of(g.standard_normal((n, n)))
+    Vt = q_of(g.standard_normal((n, n))).T.contiguous()
+    Gh, ph = _multiplier_draw(g, n, mult)
+    Bh = g.standard_normal((n, nrhs))
+    G = torch.from_numpy(Gh).to(dev) if Gh is not None else None
+    p = torch.from_numpy(ph).to(dev) if ph is not None else None
+    B = torch.from_numpy(Bh).to(dev)
+    for smax in smaxes:
+        st = torch.from_numpy(logspaced_singular_values(n, smax)).to(dev)
+        A = ((U * st[None, :]) @ Vt).contiguous()
+        yield Workload("haar_logspaced", n, seed, A, B, mult, G=G, p=p, smax=float(smax))
+        del A
+
+
 # The five named workloads, with their sizes; `scale_n` lets tests build the
 # same recipe at a size the oracle finishes in seconds.
 NAMED = {

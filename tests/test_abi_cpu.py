@@ -45,7 +45,8 @@ def test_strerror_covers_codes():
 
 
 @pytest.mark.parametrize("cname,pyname", [("genp_info", "GenpInfo"), ("genp_lr_info", "GenpLrInfo"),
-                                          ("genp_nrank_info", "GenpNrankInfo")])
+                                          ("genp_nrank_info", "GenpNrankInfo"),
+                                          ("genp_refine_opts", "GenpRefineOpts")])
 def test_info_struct_layout_matches_header(tmp_path, cname, pyname):
     """The binding's mirrors of the info structs have the C structs' sizes and field offsets."""
     import shutil
@@ -76,7 +77,9 @@ def test_invalid_arguments_rejected_before_device():
     assert L.genp_create(None, 10, 0, 256, None) == genp.EINVAL
     assert L.genp_destroy(None) == genp.OK
     for fn, args in (("genp_factor", (None, 0.0, None)), ("genp_get_info", (None, None)),
-                     ("genp_copy_work", (None, None, 1))):
+                     ("genp_copy_work", (None, None, 1)), ("genp_condest", (None, None, None, None)),
+                     ("genp_refine_ex", (None, None, 1, 1, None, 1, None, None)),
+                     ("genp_solve_backward_ex", (None, None, 1, None, 1, 1, None, 1, None, 1, None, None))):
         assert getattr(L, fn)(*args) == genp.EINVAL
 
 

@@ -27,6 +27,10 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
 def test_fullsize_n16384_toeplitz_sampled():
     print("full size n=16384 Toeplitz: building inputs", flush=True)
     w = wl.make("c3_n16384_haar1e6_toeplitz", device="cuda")
@@ -130,7 +134,6 @@ def test_fullsize_n16384_block_ge_sampled():
 def test_fullsize_n4096_dense_whole_path():
     print("full size n=4096 dense, 16 RHS", flush=True)
     w = wl.make("c2_n4096_haar1e4_dense")
-    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")  # noqa: E731
     s = genp.Solver(w.n, "f64", 256)
     s.precondition(dev(w.A), G=dev(w.G))
     assert s.factor() == 0
@@ -149,15 +152,14 @@ def test_fullsize_n4096_dense_whole_path():
     assert abs(gi["growth"] - info.growth) <= 0.01 * info.growth
 
 
-def test_fullsize_n8192_differentiation_form():
-    """n = 8192, A ~ N(0,1)/sqrt(n) with a rank-8 leading 16 x 16 block, dense G, 64 RHS:
-    forward solve + FP64 refinement, backward adjoint refined against A^T; the gradient of
-    sum(W * X) is checked against the oracle's FP64 gradient (LAPACK solve with A^T).
-    FP64 factors: with FP32 factors kappa(A G) u_32 > 1 at this size and GMRES-IR(50) does
-    not converge (eta 5e-3 after 12800 inner iterations), so the form runs in FP64."""
-    print("full size n=8192 differentiation form", flush=True)
+def test_fullsize_n8192_adjoint_fp64_factors():
+    """The differentiation workload at n = 8192 (A ~ N(0,1)/sqrt(n) with a rank-8 leading
+    16 x 16 block, dense G, 64 RHS) with FP64 factors: forward solve + FP64 refinement, backward
+    adjoint refined against A^T; the gradient of sum(W * X) is checked against the oracle's FP64
+    gradient (LAPACK solve with A^T).  The form as specified, with FP32 factors, is
+    test_differentiation_form_fp32_factors."""
+    print("full size n=8192 adjoint, FP64 factors", flush=True)
     w = wl.make("c5_n8192_scaled_lowrank")
-    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")  # noqa: E731
     s = genp.Solver(w.n, "f64", 256)
     s.precondition(dev(w.A), G=dev(w.G))
     assert s.factor() == 0
@@ -200,3 +202,61 @@ def test_fullsize_n16384_64_rhs(name):
     eta_o = og.backward_error_inf(host(w.A), host(X), host(w.B))
     print(f"  eta library max {max(eta):.2e} oracle max {eta_o.max():.2e}", flush=True)
     assert np.all(eta_o <= 1e-14)
+
+
+@pytest.mark.parametrize("n", [1024, 2048, 4096, 8192])
+def test_differentiation_form_fp32_factors(n):
+    """The differentiation form as specified: FP32 LU of A G, FP64 refinement of the forward
+    solve (GMRES-IR), the adjoint dB = A^{-T} W refined against A^T (GMRES-IR), dA = -dB X^T, on
+    the n = 8192 recipe grown from n = 1024 (64 right-hand sides, W ~ N(0,1)).  kappa(A G) u32
+    exceeds 1 from about n = 2048 on, so within a budget of 100 inner GMRES steps per column
+    and direction the refinement need not reach 1e-14.  Asserted either way: the library's
+    status is honest (GENP_OK only with the oracle's eta <= 1e-14; otherwise GENP_ENOCONV with
+    the library's eta within 5 % of the oracle's for the returned iterate); a converged gradient
+    matches the oracle's FP64 gradient within 10 kappa_inf(A) max(eta, u)."""
+    print(f"differentiation form FP32 factors n={n}", flush=True)
+    w = wl.make("c5_n8192_scaled_lowrank", n=n)
+    k = w.nrhs
+    budget = 100 * k
+    s = genp.Solver(n, "f32", 256)
+    s.precondition(dev(w.A), G=dev(w.G))
+    assert s.factor() == 0
+    ce = s.condest()
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, max_iter=40, tol=1e-14, solver="gmres", restart=50, max_inner=budget)
+    info = s.info()
+    Xh = host(X)
+    eta_o = og.backward_error_inf(w.A, Xh, w.B)
+    print(f"  kappa1(C) est {ce['kappa1']:.2e} (kappa u32 {ce['kappa1'] * 2.0 ** -24:.2e}); forward: status {st} "
+          f"outer {info['iters']} inner {info['inner_iters']} eta lib {max(eta):.2e} oracle {eta_o.max():.2e} "
+          f"({info['ms_refine']:.0f} ms)", flush=True)
+    assert info["inner_iters"] <= budget
+    if st == genp.OK:
+        assert np.all(eta_o <= 1e-14)
+    else:
+        assert st == genp.ENOCONV
+        assert abs(max(eta) - eta_o.max()) <= 0.05 * eta_o.max() + 2.0 ** -51
+    Wd = dev(w.W)
+    dB, dA, stb, etab = s.solve_backward(Wd, X, want_dA=True, refine_iters=40, solver="gmres", tol=1e-14,
+                                         restart=50, max_inner=budget, return_status=True)
+    info = s.info()
+    dBh = host(dB)
+    eta_bo = og.backward_error_inf(np.ascontiguousarray(w.A.T), dBh, w.W)
+    print(f"  backward: status {stb} outer {info['bwd_iters']} inner {info['bwd_inner_iters']} eta lib "
+          f"{max(etab):.2e} oracle {eta_bo.max():.2e} ({info['ms_backward']:.0f} ms)", flush=True)
+    assert info["bwd_inner_iters"] <= budget
+    if stb == genp.OK:
+        assert np.all(eta_bo <= 1e-14)
+    else:
+        assert stb == genp.ENOCONV
+        assert abs(max(etab) - eta_bo.max()) <= 0.05 * eta_bo.max() + 2.0 ** -51
+    if st == genp.OK and stb == genp.OK:
+        dBo, dAo = og.adjoint(w.A, Xh, w.W)
+        kappa = np.linalg.cond(w.A, np.inf)
+        tol = 10 * kappa * max(eta_o.max(), eta_bo.max(), 2.0 ** -53)
+        assert np.max(np.abs(dBh - dBo)) <= tol * np.max(np.abs(dBo))
+        rng = np.random.default_rng(1)
+        I, J = rng.integers(0, n, 64), rng.integers(0, n, 64)
+        dAs = host(dA[torch.as_tensor(I, device="cuda"), torch.as_tensor(J, device="cuda")])
+        assert np.max(np.abs(dAs - dAo[I, J])) <= tol * np.max(np.abs(dAo))
