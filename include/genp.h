@@ -84,7 +84,9 @@ enum {
     GENP_ENOMEM = -3,     /* device allocation failed                                  */
     GENP_ESTATE = -4,     /* call out of order                                         */
     GENP_ENOTSUP = -5,    /* combination not supported by this build                   */
-    GENP_ESINGULAR = -6   /* the multiplier is singular to working precision           */
+    GENP_ESINGULAR = -6,  /* the multiplier is singular to working precision           */
+    GENP_ESCRATCH = -7    /* the problem needs more than the fixed scratch of the
+                             allocation-free entry point holds                          */
 };
 
 #define GENP_ETA_HIST 64
@@ -424,6 +426,24 @@ typedef struct {
 int genp_numerical_rank(const double* A, int64_t m, int64_t n, int64_t lda, const double* G,
                         int64_t ldg, int64_t rho_minus, int64_t rho_plus, double cond_max, double* B,
                         int64_t ldb, genp_nrank_info* info, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): genp_numerical_rank with the same arguments and
+ * results, whose scratch comes from one fixed 64 MiB device array per GPU (held from the first
+ * call on that GPU until the process ends) instead of hipMalloc; it calls no allocating routine.
+ * The scratch holds the m x 64 multiplier and n x 64 sketch (rows padded to 16), the 64 x 64
+ * Gram matrix and at least one n x 64 slice of split-K partials:
+ * 512 (ceil16(m) + ceil16(n) + max(n, 64)) + 33 KiB <= 64 MiB, about m + 2n <= 131000;
+ * larger problems return GENP_ESCRATCH.  Every call on a GPU uses that GPU's one array, which
+ * keeps the last call's contents (each call clears what it reads before writing it): calls that
+ * overlap on one GPU (other host threads, other streams) race and must be serialized by the
+ * caller.  The stage times of info are NaN (no events are created).  Waits for the stream once.
+ * Errors: GENP_EINVAL, GENP_ESCRATCH, GENP_EDEVICE.
+ */
+int genp_numerical_rank_noalloc(const double* A, int64_t m, int64_t n, int64_t lda, const double* G,
+                                int64_t ldg, int64_t rho_minus, int64_t rho_plus, double cond_max, double* B,
+                                int64_t ldb, genp_nrank_info* info, void* stream);
 
 #ifdef __cplusplus
 }

@@ -721,6 +721,7 @@ const char* genp_strerror(int s) {
         case GENP_ESTATE: return "call out of order";
         case GENP_ENOTSUP: return "combination not supported";
         case GENP_ESINGULAR: return "the multiplier is singular to working precision";
+        case GENP_ESCRATCH: return "problem too large for the fixed scratch of the allocation-free entry point";
         default: return "unknown status";
     }
 }

@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 namespace {
@@ -787,53 +788,62 @@ extern "C" int genp_lowrank(const double* A, int64_t m, int64_t n, int64_t lda, 
     return GENP_OK;
 }
 
-extern "C" int genp_numerical_rank(const double* A, int64_t m, int64_t n, int64_t lda, const double* G, int64_t ldg,
-                                   int64_t rho_minus, int64_t rho_plus, double cond_max, double* B, int64_t ldb,
-                                   genp_nrank_info* info, void* stream) {
-    if (!A || !G || !B || !info || m < 1 || n < 1 || lda < n || rho_minus < 0 || rho_plus <= rho_minus ||
-        rho_plus > LR_MAXK || rho_plus > std::min(m, n) || ldg < rho_plus || ldb < rho_plus || !(cond_max >= 1.0) ||
-        m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
-        return GENP_EINVAL;
+namespace {
+
+// Scratch of one numerical-rank call: the padded multiplier and sketch (rows to a multiple of
+// 16, 64 columns), the Gram matrix, the split-K partials and the result record.
+struct NrBufs {
+    double* G64;
+    double* T64;
+    double* Sg;
+    double* part;
+    long long part_cap;
+    NrOut* od;
+};
+
+int nrank_args_ok(const double* A, int64_t m, int64_t n, int64_t lda, const double* G, int64_t ldg,
+                  int64_t rho_minus, int64_t rho_plus, double cond_max, const double* B, int64_t ldb,
+                  const genp_nrank_info* info) {
+    return A && G && B && info && m >= 1 && n >= 1 && lda >= n && rho_minus >= 0 && rho_plus > rho_minus &&
+           rho_plus <= LR_MAXK && rho_plus <= std::min(m, n) && ldg >= rho_plus && ldb >= rho_plus &&
+           cond_max >= 1.0 && m <= (int64_t)1 << 30 && n <= (int64_t)1 << 30;
+}
+
+int gfx950_current() {
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
         strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return GENP_EDEVICE;
-    hipStream_t s = (hipStream_t)stream;
+        return -1;
+    return dev;
+}
+
+// The steps of genp_numerical_rank on the given scratch: B = A^T G (split over K), S = B^T B,
+// the bisection with COND on the device, the copy of B out; one wait at the end.  ev: four
+// events for the stage times, or null (times reported as NaN).
+int nrank_core(const double* A, int64_t m, int64_t n, int64_t lda, const double* G, int64_t ldg, int64_t rho_minus,
+               int64_t rho_plus, double cond_max, double* B, int64_t ldb, genp_nrank_info* info, hipStream_t s,
+               const NrBufs& b, hipEvent_t* ev) {
     const int M = (int)m, N = (int)n, K = (int)rho_plus;
-    const size_t Mp = ((size_t)M + 15) / 16 * 16, Np = ((size_t)N + 15) / 16 * 16;
-    const long long part_cap = 16LL * std::max(M, N) * LR_MAXK;
-    Scratch sc;
-    double *G64 = nullptr, *T64 = nullptr, *Sg = nullptr, *part = nullptr;
-    NrOut* od = nullptr;
-    if (!sc.get(&G64, Mp * LR_MAXK) || !sc.get(&T64, Np * LR_MAXK) || !sc.get(&Sg, (size_t)LR_MAXK * LR_MAXK) ||
-        !sc.get(&part, part_cap) || !sc.get(&od, 1))
-        return GENP_ENOMEM;
-    hipEvent_t ev[4];
-    for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) return GENP_EDEVICE;
-    struct EvGuard {
-        hipEvent_t* e;
-        ~EvGuard() {
-            for (int i = 0; i < 4; ++i) hipEventDestroy(e[i]);
-        }
-    } eg{ev};
+    const int Mp = (M + 15) / 16 * 16, Np = (N + 15) / 16 * 16;
     auto blocks = [](long long tot) { return dim3((unsigned)((tot + 255) / 256)); };
-    LR_HIP(hipEventRecord(ev[0], s));
-    LR_HIP(hipMemsetAsync(G64, 0, Mp * LR_MAXK * sizeof(double), s));
-    LR_HIP(hipMemsetAsync(T64, 0, Np * LR_MAXK * sizeof(double), s));
-    LR_HIP(hipMemsetAsync(Sg, 0, (size_t)LR_MAXK * LR_MAXK * sizeof(double), s));
-    hipLaunchKernelGGL(pad_cols_kernel, blocks((long long)M * LR_MAXK), dim3(256), 0, s, M, K, G, (long long)ldg, G64);
-    LR_HIP(skinny_mfma<true>(N, M, K, A, lda, G64, T64, part, part_cap, s));        // B = A^T G
-    LR_HIP(hipEventRecord(ev[1], s));
-    LR_HIP(skinny_mfma<true>(K, N, K, T64, LR_MAXK, T64, Sg, part, part_cap, s));   // S = B^T B
-    LR_HIP(hipEventRecord(ev[2], s));
-    hipLaunchKernelGGL(nr_search_kernel, dim3(1), dim3(64), 0, s, (int)rho_minus, K, Sg, G64, cond_max, od);
-    hipLaunchKernelGGL(copy_cols_kernel, blocks((long long)N * K), dim3(256), 0, s, N, K, T64, B, (long long)ldb);
+    if (ev) LR_HIP(hipEventRecord(ev[0], s));
+    // zero padding by kernels (also safe where a caller captures the stream into a graph)
+    LR_HIP(launch_fill2d(0.0, b.G64, LR_MAXK, Mp, LR_MAXK, s));
+    LR_HIP(launch_fill2d(0.0, b.T64, LR_MAXK, Np, LR_MAXK, s));
+    LR_HIP(launch_fill2d(0.0, b.Sg, LR_MAXK, LR_MAXK, LR_MAXK, s));
+    hipLaunchKernelGGL(pad_cols_kernel, blocks((long long)M * LR_MAXK), dim3(256), 0, s, M, K, G, (long long)ldg,
+                       b.G64);
+    LR_HIP(skinny_mfma<true>(N, M, K, A, lda, b.G64, b.T64, b.part, b.part_cap, s));        // B = A^T G
+    if (ev) LR_HIP(hipEventRecord(ev[1], s));
+    LR_HIP(skinny_mfma<true>(K, N, K, b.T64, LR_MAXK, b.T64, b.Sg, b.part, b.part_cap, s));   // S = B^T B
+    if (ev) LR_HIP(hipEventRecord(ev[2], s));
+    hipLaunchKernelGGL(nr_search_kernel, dim3(1), dim3(64), 0, s, (int)rho_minus, K, b.Sg, b.G64, cond_max, b.od);
+    hipLaunchKernelGGL(copy_cols_kernel, blocks((long long)N * K), dim3(256), 0, s, N, K, b.T64, B, (long long)ldb);
     LR_HIP(hipGetLastError());
-    LR_HIP(hipEventRecord(ev[3], s));
+    if (ev) LR_HIP(hipEventRecord(ev[3], s));
     NrOut ho;
-    LR_HIP(hipMemcpyAsync(&ho, od, sizeof ho, hipMemcpyDeviceToHost, s));
+    LR_HIP(hipMemcpyAsync(&ho, b.od, sizeof ho, hipMemcpyDeviceToHost, s));
     LR_HIP(hipStreamSynchronize(s));
     *info = genp_nrank_info{};
     info->m = m;
@@ -845,10 +855,112 @@ extern "C" int genp_numerical_rank(const double* A, int64_t m, int64_t n, int64_
     const double nan = __builtin_nan("");
     info->cond_at_rank = ho.cond_at_rank < 0 ? nan : ho.cond_at_rank;
     info->cond_above = ho.cond_above < 0 ? nan : ho.cond_above;
-    float ms = 0.f;
     double* slots[3] = {&info->ms_sketch, &info->ms_gram, &info->ms_search};
-    for (int i = 0; i < 3; ++i)
-        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) *slots[i] = ms;
-    if (hipEventElapsedTime(&ms, ev[0], ev[3]) == hipSuccess) info->ms_total = ms;
+    info->ms_total = nan;
+    for (int i = 0; i < 3; ++i) *slots[i] = nan;
+    if (ev) {
+        float ms = 0.f;
+        for (int i = 0; i < 3; ++i)
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) *slots[i] = ms;
+        if (hipEventElapsedTime(&ms, ev[0], ev[3]) == hipSuccess) info->ms_total = ms;
+    }
     return GENP_OK;
+}
+
+}  // namespace
+
+extern "C" int genp_numerical_rank(const double* A, int64_t m, int64_t n, int64_t lda, const double* G, int64_t ldg,
+                                   int64_t rho_minus, int64_t rho_plus, double cond_max, double* B, int64_t ldb,
+                                   genp_nrank_info* info, void* stream) {
+    if (!nrank_args_ok(A, m, n, lda, G, ldg, rho_minus, rho_plus, cond_max, B, ldb, info)) return GENP_EINVAL;
+    if (gfx950_current() < 0) return GENP_EDEVICE;
+    const int M = (int)m, N = (int)n;
+    const size_t Mp = ((size_t)M + 15) / 16 * 16, Np = ((size_t)N + 15) / 16 * 16;
+    Scratch sc;
+    NrBufs b{};
+    b.part_cap = 16LL * std::max(M, N) * LR_MAXK;
+    if (!sc.get(&b.G64, Mp * LR_MAXK) || !sc.get(&b.T64, Np * LR_MAXK) || !sc.get(&b.Sg, (size_t)LR_MAXK * LR_MAXK) ||
+        !sc.get(&b.part, b.part_cap) || !sc.get(&b.od, 1))
+        return GENP_ENOMEM;
+    hipEvent_t ev[4];
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return GENP_EDEVICE;
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; ++i) hipEventDestroy(e[i]);
+        }
+    } eg{ev};
+    return nrank_core(A, m, n, lda, G, ldg, rho_minus, rho_plus, cond_max, B, ldb, info, (hipStream_t)stream, b, ev);
+}
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free numerical rank: the scratch of genp_numerical_rank taken from one fixed
+// device array instead of hipMalloc.  In host code the array's name is only a stand-in for the
+// symbol; its device address (one per GPU) comes from hipGetSymbolAddress on the first call
+// with that GPU current, and only that address is handed to kernels.
+
+namespace {
+
+constexpr size_t NR_SCRATCH_BYTES = (size_t)64 << 20;   // 64 MiB per GPU
+constexpr int NR_MAX_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NR_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[NR_MAX_DEVICES] = {};
+
+// The device address of `scratch` on device dev (current), looked up once per device.
+void* scratch_on(int dev) {
+    if (dev < 0 || dev >= NR_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_dev[dev] = p;
+    }
+    return g_scratch_dev[dev];
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" int genp_numerical_rank_noalloc(const double* A, int64_t m, int64_t n, int64_t lda, const double* G,
+                                           int64_t ldg, int64_t rho_minus, int64_t rho_plus, double cond_max,
+                                           double* B, int64_t ldb, genp_nrank_info* info, void* stream) {
+    if (!nrank_args_ok(A, m, n, lda, G, ldg, rho_minus, rho_plus, cond_max, B, ldb, info)) return GENP_EINVAL;
+    const int M = (int)m, N = (int)n;
+    const size_t Mp = ((size_t)M + 15) / 16 * 16, Np = ((size_t)N + 15) / 16 * 16;
+    // fixed parts, then the split-K partials (at least one slice of the sketch: N x 64, and of
+    // the Gram matrix: 64 x 64) in what is left
+    const size_t fixed = align256(Mp * LR_MAXK * sizeof(double)) + align256(Np * LR_MAXK * sizeof(double)) +
+                         align256((size_t)LR_MAXK * LR_MAXK * sizeof(double)) + align256(sizeof(NrOut));
+    const size_t part_min = (size_t)std::max(N, LR_MAXK) * LR_MAXK * sizeof(double);
+    if (fixed + part_min > NR_SCRATCH_BYTES) return GENP_ESCRATCH;
+    const int dev = gfx950_current();
+    if (dev < 0) return GENP_EDEVICE;
+    unsigned char* base = (unsigned char*)scratch_on(dev);
+    if (!base) return GENP_EDEVICE;
+    NrBufs b{};
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        void* p = base + off;
+        off += align256(bytes);
+        return p;
+    };
+    b.G64 = (double*)carve(Mp * LR_MAXK * sizeof(double));
+    b.T64 = (double*)carve(Np * LR_MAXK * sizeof(double));
+    b.Sg = (double*)carve((size_t)LR_MAXK * LR_MAXK * sizeof(double));
+    b.od = (NrOut*)carve(sizeof(NrOut));
+    b.part = (double*)(base + off);
+    // as many partial slices as genp_numerical_rank would use, if they fit
+    b.part_cap = std::min<long long>(16LL * std::max(M, N) * LR_MAXK,
+                                     (long long)((NR_SCRATCH_BYTES - off) / sizeof(double)));
+    return nrank_core(A, m, n, lda, G, ldg, rho_minus, rho_plus, cond_max, B, ldb, info, (hipStream_t)stream, b,
+                      nullptr);
 }

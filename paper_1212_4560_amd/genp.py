@@ -27,7 +27,7 @@ F64, F32, BF16, BF16X3 = 0, 1, 2, 3
 G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT, G_HOUSEHOLDER = 0, 1, 2, 3, 4
 SOLVER_LUIR, SOLVER_GMRES = 0, 1
 OK, BREAKDOWN, ENOCONV = 0, 1, 2
-EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP, ESINGULAR = -1, -2, -3, -4, -5, -6
+EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP, ESINGULAR, ESCRATCH = -1, -2, -3, -4, -5, -6, -7
 ETA_HIST = 64
 
 PRECS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
@@ -36,7 +36,7 @@ SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
 # the entry points declared in include/genp.h
 EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",
            "genp_factor_block", "genp_block_pivots", "genp_row_perm",
-           "genp_lowrank", "genp_numerical_rank",
+           "genp_lowrank", "genp_numerical_rank", "genp_numerical_rank_noalloc",
            "genp_refine", "genp_refine_ex", "genp_solve_backward", "genp_solve_backward_ex", "genp_condest",
            "genp_get_info", "genp_copy_work", "genp_strerror")
 GMRES_MAX_RESTART = 1024
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
     L.genp_precondition2.argtypes = [vp, vp, i64, i32, vp, i64, i32, vp, i64]
     L.genp_numerical_rank.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, dbl, vp, i64,
                                       ctypes.POINTER(GenpNrankInfo), vp]
+    L.genp_numerical_rank_noalloc.argtypes = L.genp_numerical_rank.argtypes
     L.genp_lowrank.argtypes = [vp, i64, i64, i64, i32, vp, i64, i64, dbl, dbl, vp, i64, vp, i64, vp, i64,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(GenpLrInfo), vp]
     L.genp_factor.argtypes = [vp, dbl, ctypes.POINTER(i64)]
@@ -418,21 +419,26 @@ def lowrank(A, rho_plus: int, G=None, p=None, tau: float = 1e-8, tau2: float = 1
             "info": info.as_dict(), "_keep": (A, G, p)}
 
 
-def numerical_rank(A, G, rho_minus: int, rho_plus: int, cond_max: float = 1e6, stream=None):
+def numerical_rank(A, G, rho_minus: int, rho_plus: int, cond_max: float = 1e6, stream=None, B=None,
+                   noalloc: bool = False):
     """Numerical rank of A in [rho_-, rho_+] without pivoting or orthogonalization
-    (Proto-Algorithm B.1) through genp_numerical_rank.  G: the m x rho_+ Gaussian multiplier.
-    Returns dict(rank, B (n x rank: the first columns of A^T G), info)."""
+    (Proto-Algorithm B.1) through genp_numerical_rank, or genp_numerical_rank_noalloc (scratch
+    from the library's fixed device array) with noalloc=True.  G: the m x rho_+ Gaussian
+    multiplier; B: optional n x rho_+ output tensor.  Returns dict(rank, B (n x rank: the first
+    columns of A^T G), info)."""
     import torch
     m, n = A.shape
     k = int(rho_plus)
     a, lda = _mat(A, "A", m, n)
     g, ldg = _mat(G, "G", m, k)
-    B = torch.empty((n, k), dtype=torch.float64, device=A.device)
+    if B is None:
+        B = torch.empty((n, k), dtype=torch.float64, device=A.device)
     b, ldb = _mat(B, "B", n, k)
     info = GenpNrankInfo()
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(load().genp_numerical_rank(a, m, n, lda, g, ldg, int(rho_minus), k, float(cond_max), b, ldb,
-                                      ctypes.byref(info), ctypes.c_void_p(st.cuda_stream)), "genp_numerical_rank")
+    name = "genp_numerical_rank_noalloc" if noalloc else "genp_numerical_rank"
+    _check(getattr(load(), name)(a, m, n, lda, g, ldg, int(rho_minus), k, float(cond_max), b, ldb,
+                                 ctypes.byref(info), ctypes.c_void_p(st.cuda_stream)), name)
     r = int(info.rank)
     return {"rank": r, "B": B[:, :r], "info": info.as_dict()}
 

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_covers_codes():
     _lib()
-    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
         s = genp.strerror(code)
         assert s and "unknown" not in s
     assert "unknown" in genp.strerror(99)
@@ -91,3 +91,16 @@ def test_create_without_gpu_reports_device_error():
     h = ctypes.c_void_p()
     assert L.genp_create(ctypes.byref(h), 16, 0, 64, None) == genp.EDEVICE
     assert not h.value
+
+
+def test_noalloc_rejects_oversize_before_device_work():
+    """The allocation-free numerical rank checks its scratch need on the host first: a problem
+    larger than the fixed array is refused with GENP_ESCRATCH (the pointers are never used)."""
+    L = _lib()
+    info = genp.GenpNrankInfo()
+    p = ctypes.c_void_p(256)
+    m = n = 200000
+    st = L.genp_numerical_rank_noalloc(p, m, n, n, p, 64, 0, 64, 1e6, p, 64, ctypes.byref(info), None)
+    assert st == genp.ESCRATCH
+    assert L.genp_numerical_rank_noalloc(None, 10, 10, 10, p, 4, 0, 4, 1e6, p, 4, ctypes.byref(info),
+                                         None) == genp.EINVAL
