@@ -72,12 +72,14 @@ def mixed_sweep(args, n: int) -> list:
     from paper_1212_4560_amd import genp, workloads as wl
     stream = torch.cuda.current_stream()
     out = []
-    for w in wl.haar_family(n, SWEEP_SMAX, wl.MULT_TOEPLITZ, nrhs=1, seed=3):
+    smaxes = tuple(float(v) for v in args.sweep_smax.split(",")) if args.sweep_smax else SWEEP_SMAX
+    precs = tuple(args.sweep_precs.split(",")) if args.sweep_precs else ("f32", "bf16", "bf16x3")
+    for w in wl.haar_family(n, smaxes, wl.MULT_TOEPLITZ, nrhs=1, seed=3):
         Ah = w.A.cpu().numpy()
         Bh = w.B.cpu().numpy()
         X = torch.empty((n, 1), dtype=torch.float64, device="cuda")
         f64_ms = None
-        for prec in ("f64", "f32", "bf16", "bf16x3"):
+        for prec in ("f64",) + precs:
             s = genp.Solver(n, prec, args.nb, stream=stream)
             s.precondition(w.A, p=w.p)
             s.factor(0.0)                     # warm-up of the product and factorization kernels
@@ -469,6 +471,9 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form sweep")
     ap.add_argument("--sweep-restart", type=int, default=100, help="GMRES cycle length in the precision-form sweep")
     ap.add_argument("--sweep-cap", type=int, default=1000, help="inner GMRES steps at most per sweep cell")
+    ap.add_argument("--sweep-smax", default="", help="comma-separated smax values of the sweep (default 1e1,1e2,1e4,1e6)")
+    ap.add_argument("--sweep-precs", default="", help="comma-separated precision forms of the sweep "
+                                                      "(default f32,bf16,bf16x3)")
     ap.add_argument("--gaussian-inputs", action="store_true",
                     help="counter runs: A ~ N(0,1) of the same shape instead of the Haar construction "
                          "(no QR; the kernels' memory traffic does not depend on the values)")

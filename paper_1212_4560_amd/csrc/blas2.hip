@@ -448,6 +448,33 @@ __global__ void __launch_bounds__(1024) dot3_kernel(int n, const double* __restr
     if (t < 3) out[t] = red[t][0];
 }
 
+// FP64 -> FP32 (round to nearest even), then optionally FP32 -> BF16 (round to nearest even on
+// the upper 16 bits, NaN kept quiet), the result held in an FP32 word.
+__device__ inline float round_lp(double x, int bf16) {
+    float f = (float)x;
+    if (!bf16) return f;
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return __uint_as_float(u | 0x00400000u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+__global__ void convert_pad_kernel(const double* __restrict__ A, long long lda, int n, int n_pad,
+                                   float* __restrict__ out, long long ldo, int bf16) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n_pad * n_pad) return;
+    const int i = (int)(e / n_pad), j = (int)(e % n_pad);
+    out[(long long)i * ldo + j] = (i < n && j < n) ? round_lp(A[(long long)i * lda + j], bf16) : 0.f;
+}
+
+__global__ void convert_toep_kernel(const double* __restrict__ p, int n, int n_pad, float* __restrict__ out,
+                                    int bf16) {
+    const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= 2LL * n_pad - 1) return;
+    const long long t = u - (n_pad - n);
+    out[u] = (t >= 0 && t < 2LL * n - 1) ? round_lp(p[t], bf16) : 0.f;
+}
+
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -613,5 +640,20 @@ hipError_t launch_rank1(int M, int N, double alpha, const double* X, long long l
 
 hipError_t launch_dot3(int n, const double* u, const double* v, double* out, hipStream_t s) {
     hipLaunchKernelGGL(dot3_kernel, dim3(1), dim3(1024), 0, s, n, u, v, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_pad(const double* A, long long lda, int n, int n_pad, float* out, long long ldo, int bf16,
+                              hipStream_t s) {
+    const long long tot = (long long)n_pad * n_pad;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(convert_pad_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, A, lda, n, n_pad, out, ldo,
+                       bf16);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_toep(const double* p, int n, int n_pad, float* out, int bf16, hipStream_t s) {
+    const long long tot = 2LL * n_pad - 1;
+    hipLaunchKernelGGL(convert_toep_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, p, n, n_pad, out, bf16);
     return hipGetLastError();
 }

@@ -79,6 +79,22 @@ struct GemmLpArgs {
 };
 hipError_t launch_gemm_lp(const GemmLpArgs& a, int tile, hipStream_t s);
 
+// FP32 product D = A G with register operands (gemm_f32.hip), A row-major M x K (FP32), G
+// generated from FP32 Toeplitz parameters: G(k, j) = p[k - j + ldb - 1], K = ldb, N <= ldb.
+// M, N multiples of 64, K of 16, A 16-byte aligned, lda a multiple of 4.
+struct GemmF32Args {
+    int M, N, K;
+    const float* A; long long lda;
+    const float* p; long long ldb;
+    float* D; long long ldd;
+};
+hipError_t launch_gemm_f32_toep(const GemmF32Args& a, hipStream_t s);
+// out (rows_pad x rows_pad, ldo) = A (n x n FP64) rounded to FP32 (bf16: then to BF16), zero padding
+hipError_t launch_convert_pad(const double* A, long long lda, int n, int n_pad, float* out, long long ldo, int bf16,
+                              hipStream_t s);
+// out[u] = p[u - (n_pad - n)] rounded likewise for u < 2 n_pad - 1 (0 outside p's 2n - 1 entries)
+hipError_t launch_convert_toep(const double* p, int n, int n_pad, float* out, int bf16, hipStream_t s);
+
 // Diagonal block LU (no pivoting) in place, one workgroup; records PanelStats.
 // FP64 256 x 256 diagonal block as two LDS-resident 128 blocks, the panel solves and one update
 hipError_t launch_diag_lu_split(void* Dblk, long long ldd, int nvalid, long long col0, const double* maxc,

@@ -257,13 +257,15 @@ hipError_t launch_t(const GemmLpArgs& a, hipStream_t s) {
 
 template <bool BF16, bool X3 = false>
 hipError_t dispatch(const GemmLpArgs& a, hipStream_t s) {
-    // the combinations the path uses: A G (FP64 A, dense or Toeplitz FP64 G) and the
-    // Schur update (FP32 L21, FP32 U12)
+    // the combinations the path uses: A G (FP64 or FP32 A, dense or Toeplitz G of the same
+    // type) and the Schur update (FP32 L21, FP32 U12)
     if (a.amode == OP_N && a.a_f64 && a.bmode == OP_N && a.b_f64) return launch_t<OP_N, OP_N, true, true, BF16, X3>(a, s);
     if (a.amode == OP_N && a.a_f64 && a.bmode == OP_TOEP && a.b_f64)
         return launch_t<OP_N, OP_TOEP, true, true, BF16, X3>(a, s);
     if (a.amode == OP_N && !a.a_f64 && a.bmode == OP_N && !a.b_f64)
         return launch_t<OP_N, OP_N, false, false, BF16, X3>(a, s);
+    if (a.amode == OP_N && !a.a_f64 && a.bmode == OP_TOEP && !a.b_f64)
+        return launch_t<OP_N, OP_TOEP, false, false, BF16, X3>(a, s);
     return hipErrorInvalidValue;
 }
 

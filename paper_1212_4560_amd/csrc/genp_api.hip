@@ -64,12 +64,18 @@ struct genp_ctx {
     double2* circ_tw = nullptr;
     double2* circ_wp = nullptr;
     double* hw = nullptr;      // Householder: a length-n_pad work vector
+    // precision form: FP32 (or BF16-valued) copies of A and of the multiplier, zero-padded to
+    // n_pad (the operands of the register-operand FP32 product)
+    float* A32 = nullptr;      // n_pad x n_pad
+    float* G32 = nullptr;      // dense G: n_pad x n_pad; Toeplitz: 2 n_pad - 1 parameters
+    size_t g32_bytes = 0;
     double* w2 = nullptr;      // two-sided products with a dense or Toeplitz H: n x n copy of A G
     // right-hand-side scratch, capacity kcap columns
     int64_t kcap = 0;
     double* Z = nullptr;       // n_pad x kcap
     double* R = nullptr;       // n_pad x kcap
     double* Dx = nullptr;      // n_pad x kcap
+    double* Xb = nullptr;      // n_pad x kcap: the best iterate of a GMRES refinement
     double* part = nullptr;    // split-K partials: KSPLIT_MAX x n_pad x kcap
     // GMRES-IR: Krylov basis (gm_cap + 1 vectors of n_pad), the Gram-Schmidt coefficients of
     // one Arnoldi step (2 (gm_cap + 2) doubles), three n_pad work vectors
@@ -98,6 +104,7 @@ struct genp_ctx {
     unsigned long long* tpub = nullptr;
     bool trsv_chain = true;
     bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
+    bool lp_regs = true;               // precision forms: product from FP32 copies of A and G
     // steps per group of the factorization: g_big while the trailing matrix has at least
     // g_switch rows, then g_small
     int g_big = 3, g_small = 2;
@@ -121,12 +128,14 @@ int ensure_rhs(genp_ctx* c, int64_t k) {
     hipFree(c->Z);
     hipFree(c->R);
     hipFree(c->Dx);
+    hipFree(c->Xb);
     hipFree(c->part);
-    c->Z = c->R = c->Dx = c->part = nullptr;
+    c->Z = c->R = c->Dx = c->Xb = c->part = nullptr;
     c->kcap = 0;
     const size_t sz = (size_t)c->n_pad * cap * sizeof(double);
     if (hipMalloc(&c->Z, sz) != hipSuccess || hipMalloc(&c->R, sz) != hipSuccess ||
-        hipMalloc(&c->Dx, sz) != hipSuccess || hipMalloc(&c->part, sz * KSPLIT_MAX) != hipSuccess)
+        hipMalloc(&c->Dx, sz) != hipSuccess || hipMalloc(&c->Xb, sz) != hipSuccess ||
+        hipMalloc(&c->part, sz * KSPLIT_MAX) != hipSuccess)
         return GENP_ENOMEM;
     c->kcap = cap;
     return GENP_OK;
@@ -632,7 +641,59 @@ int right_product(genp_ctx* c, const double* A, int64_t lda) {
         HIPCK(launch_gemm_f64(g, 0, c->stream));
         return GENP_OK;
     }
-    // precision form: operands rounded FP64 -> FP32 (-> BF16) in the loader, FP32 accumulation
+    if (c->lp_regs) {
+        // precision form: A and G rounded once to FP32 (BF16 form: then to BF16) into copies
+        // zero-padded to n_pad, then the product over n_pad (padding rows and columns of C are
+        // reset to the identity afterwards): FP32 with a Toeplitz G on the register-operand
+        // kernel, otherwise the LDS-staged kernel (BF16 MFMA for the BF16 forms)
+        const int np = (int)c->n_pad;
+        const int bf = c->prec == GENP_BF16;
+        const size_t sq = (size_t)np * np * sizeof(float);
+        if (!c->A32 && hipMalloc(&c->A32, sq) != hipSuccess) return GENP_ENOMEM;
+        const bool dense = m.kind == GENP_G_DENSE;
+        const size_t gb = dense ? sq : (size_t)(2 * np) * sizeof(float);
+        if (gb > c->g32_bytes) {
+            hipFree(c->G32);
+            c->G32 = nullptr;
+            c->g32_bytes = 0;
+            if (hipMalloc(&c->G32, gb) != hipSuccess) return GENP_ENOMEM;
+            c->g32_bytes = gb;
+        }
+        HIPCK(launch_convert_pad(A, lda, (int)n, np, c->A32, np, bf, c->stream));
+        if (dense) HIPCK(launch_convert_pad(m.G, m.ldg, (int)n, np, c->G32, np, bf, c->stream));
+        else HIPCK(launch_convert_toep(m.p, (int)n, np, c->G32, bf, c->stream));
+        if (!dense && c->prec == GENP_F32) {
+            GemmF32Args g{};
+            g.N = g.K = np;
+            g.M = np;
+            g.A = c->A32;
+            g.lda = np;
+            g.p = c->G32;
+            g.ldb = np;
+            g.D = (float*)c->C;
+            g.ldd = c->ldc;
+            HIPCK(launch_gemm_f32_toep(g, c->stream));
+            return GENP_OK;
+        }
+        GemmLpArgs g{};
+        g.M = g.N = g.K = np;
+        g.A = c->A32;
+        g.lda = np;
+        g.amode = OP_N;
+        g.a_f64 = 0;
+        g.B = c->G32;
+        g.ldb = np;
+        g.bmode = dense ? OP_N : OP_TOEP;
+        g.b_f64 = 0;
+        g.alpha = 1.f;
+        g.beta = 0.f;
+        g.D = (float*)c->C;
+        g.ldd = c->ldc;
+        g.bf16 = c->prec == GENP_BF16 ? 1 : c->prec == GENP_BF16X3 ? 2 : 0;
+        HIPCK(launch_gemm_lp(g, 0, c->stream));
+        return GENP_OK;
+    }
+    // (GENP_LP_GEMM=lds) operands rounded FP64 -> FP32 (-> BF16, or 2-word BF16) in the loader
     GemmLpArgs g{};
     g.M = g.N = g.K = (int)n;
     g.A = A;
@@ -783,6 +844,8 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
         c->trsv_chain = !(tv && strcmp(tv, "step") == 0);
         const char* dg = getenv("GENP_DIAG");   // "single": one workgroup per 256 diagonal block
         c->diag_split = !(dg && strcmp(dg, "single") == 0);
+        const char* lg = getenv("GENP_LP_GEMM");   // "lds": the precision form's product from FP64 operands
+        c->lp_regs = !(lg && strcmp(lg, "lds") == 0);
     }
     if (ok) ok = ensure_rhs(c, 4) == GENP_OK;
     if (!ok) {
@@ -814,12 +877,15 @@ int genp_destroy(genp_ctx* c) {
         hipFree(m->uv);
     }
     hipFree(c->hw);
+    hipFree(c->A32);
+    hipFree(c->G32);
     hipFree(c->w2);
     hipFree(c->circ_tw);
     hipFree(c->circ_wp);
     hipFree(c->Z);
     hipFree(c->R);
     hipFree(c->Dx);
+    hipFree(c->Xb);
     hipFree(c->part);
     hipFree(c->gm_V);
     hipFree(c->gm_w);
@@ -1251,9 +1317,12 @@ namespace {
 // Refinement of X (n x k) against Op = A (or A^T when trans) and the right-hand sides B, in FP64:
 // R = B - Op X, then the correction D = M^{-1} R (LU-IR, section 7.1) or, per column, one GMRES
 // cycle for Op d = r right-preconditioned by M^{-1}; X += D.  Stops when max_j eta_j <= tol, after
-// o.max_outer corrections, once the GMRES budget o.max_inner is spent, or when a correction made
-// eta worse (it is undone: X is the best iterate).  Status: GENP_OK when eta <= tol, or when
-// tol = 0 (the steps were asked for, not a target); else GENP_ENOCONV.
+// o.max_outer corrections, or once the GMRES budget o.max_inner is spent.  LU-IR also stops when a
+// correction made eta worse (it is undone): the contraction factor is then above 1 and later
+// steps only diverge.  GMRES-IR keeps going through such a step (a cycle shrinks the residual's
+// 2-norm, which the infinity-norm eta need not follow at once) and stops after three steps in a
+// row without a new best; the best iterate is kept aside and returned.  Status: GENP_OK when
+// eta <= tol, or when tol = 0 (the steps were asked for, not a target); else GENP_ENOCONV.
 int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
                 const genp_refine_opts& o, std::vector<double>& eta, int* iters_out, int* inner_out,
                 double* hist, int* n_hist) {
@@ -1262,9 +1331,11 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
     const int restart = o.restart > 0 ? o.restart : 50;
     const double rtol = o.inner_rtol > 0 ? o.inner_rtol : 1e-10;
     const int aop = trans ? OP_T : OP_N;
+    const bool gm = o.solver == GENP_SOLVER_GMRES;
     int inner_total = 0;
     double best = INFINITY;
-    int it = 0;
+    int it = 0, stall = 0;
+    bool cur_best = true;              // X is the best iterate so far (GMRES-IR)
     int status = GENP_OK;
     *n_hist = 0;
     for (;;) {
@@ -1272,7 +1343,7 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
         CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
         const double e = max_of(eta);
         if (*n_hist < GENP_ETA_HIST) hist[(*n_hist)++] = e;
-        if (!(e <= best) && it > 0) {
+        if (!(e <= best) && it > 0 && !gm) {
             // the last correction made things worse (or produced NaN): undo it
             HIPCK(launch_axpy2d(-1.0, c->Dx, k, X, ldx, n, k, c->stream));
             CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
@@ -1280,10 +1351,18 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
             status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
             break;
         }
-        best = std::min(best, e);
+        if (e < best || it == 0) {
+            best = std::min(best, e);
+            stall = 0;
+            cur_best = true;
+            if (gm) HIPCK(launch_copy2d(X, ldx, c->Xb, k, n, k, c->stream));
+        } else {
+            ++stall;
+            cur_best = false;
+        }
         if (e <= o.tol) break;
-        const bool budget = o.solver == GENP_SOLVER_GMRES && o.max_inner > 0 && inner_total >= o.max_inner;
-        if (it >= o.max_outer || budget) {
+        const bool budget = gm && o.max_inner > 0 && inner_total >= o.max_inner;
+        if (it >= o.max_outer || budget || (gm && stall >= 3)) {
             status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
             break;
         }
@@ -1309,6 +1388,13 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
         }
         HIPCK(launch_axpy2d(1.0, c->Dx, k, X, ldx, n, k, c->stream));
         ++it;
+    }
+    if (gm && !cur_best) {
+        // return the best iterate, with its eta
+        HIPCK(launch_copy2d(c->Xb, k, X, ldx, n, k, c->stream));
+        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
+        CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
+        if (max_of(eta) <= o.tol) status = GENP_OK;
     }
     *iters_out = it;
     *inner_out = inner_total;
