@@ -62,8 +62,9 @@ def mixed_sweep(args, n: int) -> list:
     """The precision form against FP64 over kappa(A): the benchmark recipe (Haar U, V, Toeplitz G
     and b of seed 3) with smax in SWEEP_SMAX.  Per smax: the FP64 path on that matrix (one warm-up,
     one timed step, LU-IR), then each precision form (FP32, BF16 operands, 2-word BF16): C = A G and
-    the LU in that precision, the substitutions and FP64 GMRES-IR (cycles of --sweep-restart steps,
-    at most --sweep-cap inner steps) until eta <= tol, timed as one step after a warm-up of the
+    the LU in that precision, the substitutions and FP64 refinement (LU-IR while each step divides
+    eta by 4, then GMRES-IR in cycles of --sweep-restart steps, at most --sweep-cap inner steps)
+    until eta <= tol, timed as one step after a warm-up of the
     product and factorization.  Outside the timed region: the kappa_1 estimate of the factored
     matrix (genp_condest) and the oracle's eta of every returned x."""
     import numpy as np
@@ -94,7 +95,7 @@ def mixed_sweep(args, n: int) -> list:
                 if prec == "f64":
                     st, eta = s.refine(w.B, X, args.max_refine, args.tol, "luir")
                 else:
-                    st, eta = s.refine(w.B, X, 10 ** 6, args.tol, "gmres", restart=args.sweep_restart,
+                    st, eta = s.refine(w.B, X, 10 ** 6, args.tol, "auto", restart=args.sweep_restart,
                                        max_inner=args.sweep_cap)
             e1.record(stream)
             torch.cuda.synchronize()
@@ -114,7 +115,7 @@ def mixed_sweep(args, n: int) -> list:
                     "ms_refine": round(inf["ms_refine"], 2),
                     "speedup_vs_f64": round(f64_ms / ms, 3) if f64_ms else None}
             if prec != "f64":
-                cell["solver"] = f"gmres(restart {args.sweep_restart}, cap {args.sweep_cap})"
+                cell["solver"] = f"auto: LU-IR, then GMRES(restart {args.sweep_restart}, cap {args.sweep_cap})"
             out.append(cell)
             log(f"[sweep] smax {w.smax:.0e} {prec}: {ms:.1f} ms (precond {inf['ms_precond']:.1f}, factor "
                 f"{inf['ms_factor']:.1f}, refine {inf['ms_refine']:.1f}), status {st}, eta {eta_o:.2e}, outer "

@@ -72,7 +72,9 @@ enum {
 /* Refinement solvers for genp_refine. */
 enum {
     GENP_SOLVER_LUIR = 0,   /* classical refinement: X += G (LU)^{-1} (B - A X)          */
-    GENP_SOLVER_GMRES = 1   /* FP64 GMRES on A x = r right-preconditioned by G (LU)^{-1} */
+    GENP_SOLVER_GMRES = 1,  /* FP64 GMRES on A x = r right-preconditioned by G (LU)^{-1} */
+    GENP_SOLVER_AUTO = 2    /* LU-IR while each correction divides eta by 4 or more, then
+                               GMRES-IR from the best iterate                                */
 };
 
 enum {
@@ -276,7 +278,7 @@ int genp_refine(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs,
 /* Options of genp_refine_ex and genp_solve_backward_ex. */
 #define GENP_GMRES_MAX_RESTART 1024
 typedef struct {
-    int32_t solver;       /* GENP_SOLVER_LUIR or GENP_SOLVER_GMRES                               */
+    int32_t solver;       /* GENP_SOLVER_LUIR, GENP_SOLVER_GMRES or GENP_SOLVER_AUTO             */
     int32_t max_outer;    /* corrections (outer steps) at most, >= 0                               */
     int32_t restart;      /* GMRES: steps of one cycle (one cycle per column and outer step),
                              1 .. GENP_GMRES_MAX_RESTART; 0 = 50                                   */

@@ -165,6 +165,14 @@ __global__ void convert_kernel(const double* __restrict__ s, long long lds, floa
     d[(long long)i * ldd + j] = (float)s[(long long)i * lds + j];
 }
 
+__global__ void widen_kernel(const float* __restrict__ s, long long lds, double* __restrict__ d,
+                             long long ldd, int rows, int cols) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    d[(long long)i * ldd + j] = (double)s[(long long)i * lds + j];
+}
+
 __global__ void axpy2d_kernel(double alpha, const double* __restrict__ x, long long ldx,
                               double* __restrict__ y, long long ldy, int rows, int cols) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -399,6 +407,69 @@ __global__ void gemv_t_reduce_kernel(int M, int NR, int P, const double* __restr
     double v = alpha * s;
     if (beta != 0.0) v = fma(beta, Yin[(long long)j * ldyi + c], v);
     Y[(long long)j * ldy + c] = v;
+}
+
+// Toeplitz matrix-vector products y = T x, T(i, k) = p[i - k + t - 1] (M x K, 1..4 columns of x),
+// with partial sums over K slices: workgroup (row block b, slice q) stages the p window of its
+// 1024 rows and 256 columns (1279 values) and the 256 x-values in LDS, and thread r keeps rows
+// 4 r .. 4 r + 3 with their four p values in registers: moving to the next column shifts the
+// window by one entry, so each column costs one LDS read of p, one of x and four FMAs.
+constexpr int TG_ROWS = 1024, TG_KC = 256;
+template <int NR>
+__global__ void __launch_bounds__(256)
+toep_gemv_part_kernel(int M, int K, const double* __restrict__ p, long long t, const double* __restrict__ X,
+                      long long ldx, int slice, double* __restrict__ part) {
+    __shared__ double pw[TG_ROWS + TG_KC];
+    __shared__ double xs[TG_KC][NR];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * TG_ROWS;          // first row of the block
+    const int kbeg = blockIdx.y * slice, kend = min(K, kbeg + slice);
+    const int ib = 4 * tid;                        // this thread's first row within the block
+    double acc[4][NR];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[r][c] = 0.0;
+    for (int k0 = kbeg; k0 < kend; k0 += TG_KC) {
+        const int kc = min(TG_KC, kend - k0);
+        __syncthreads();
+        // pw[u] = T(i0 + u - (TG_KC - 1), k0) = p[i0 + u - (TG_KC - 1) - k0 + t - 1], 0 outside p
+        for (int u = tid; u < TG_ROWS + TG_KC - 1; u += 256) {
+            const long long idx = (long long)i0 + u - (TG_KC - 1) - k0 + t - 1;
+            pw[u] = (idx >= 0 && idx < 2 * t - 1) ? p[idx] : 0.0;
+        }
+        for (int e = tid; e < TG_KC * NR; e += 256) {
+            const int kk = e / NR, c = e % NR;
+            xs[kk][c] = (kk < kc) ? X[(long long)(k0 + kk) * ldx + c] : 0.0;
+        }
+        __syncthreads();
+        // T(i0 + ib + r, k0 + kk) = pw[ib + r - kk + TG_KC - 1]
+        double w0 = pw[ib + TG_KC - 1], w1 = pw[ib + TG_KC], w2 = pw[ib + TG_KC + 1], w3 = pw[ib + TG_KC + 2];
+        for (int kk = 0; kk < kc; ++kk) {
+            double xv[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) xv[c] = xs[kk][c];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                acc[0][c] = fma(w0, xv[c], acc[0][c]);
+                acc[1][c] = fma(w1, xv[c], acc[1][c]);
+                acc[2][c] = fma(w2, xv[c], acc[2][c]);
+                acc[3][c] = fma(w3, xv[c], acc[3][c]);
+            }
+            // next column: the window moves down one entry of p
+            w3 = w2;
+            w2 = w1;
+            w1 = w0;
+            if (kk + 1 < kc) w0 = pw[ib + TG_KC - 2 - kk];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + ib + r;
+        if (i < M)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) part[((long long)blockIdx.y * M + i) * NR + c] = acc[r][c];
+    }
 }
 
 // Y = alpha (X - s a b^T) + beta Yin with s = factor / dot[0] read from device memory (the
@@ -655,5 +726,39 @@ hipError_t launch_convert_pad(const double* A, long long lda, int n, int n_pad, 
 hipError_t launch_convert_toep(const double* p, int n, int n_pad, float* out, int bf16, hipStream_t s) {
     const long long tot = 2LL * n_pad - 1;
     hipLaunchKernelGGL(convert_toep_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, p, n, n_pad, out, bf16);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f32_f64(const float* src, long long lds, double* dst, long long ldd, int rows, int cols,
+                                  hipStream_t s) {
+    const long long tot = (long long)rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(widen_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_toep_gemv(int M, int K, int nrhs, double alpha, const double* p, long long t, const double* X,
+                            long long ldx, double beta, const double* Yin, long long ldyi, double* Y, long long ldy,
+                            double* part, long long part_cap, hipStream_t s) {
+    if (M <= 0 || nrhs <= 0) return hipSuccess;
+    if (nrhs > 4 || K <= 0) return hipErrorInvalidValue;
+    const long long rb = (M + TG_ROWS - 1) / TG_ROWS;
+    // K slices of whole 256-column chunks: about 512 workgroups, partials within part_cap
+    long long P = std::max<long long>(1, 512 / rb);
+    P = std::min<long long>(P, (K + TG_KC - 1) / TG_KC);
+    P = std::min<long long>(P, part_cap / ((long long)M * nrhs));
+    if (P < 1) return hipErrorInvalidValue;
+    const int slice = (int)(((K + P - 1) / P + TG_KC - 1) / TG_KC * TG_KC);
+    P = (K + slice - 1) / slice;
+    const dim3 grid((unsigned)rb, (unsigned)P);
+    switch (nrhs) {
+        case 1: hipLaunchKernelGGL(toep_gemv_part_kernel<1>, grid, dim3(256), 0, s, M, K, p, t, X, ldx, slice, part); break;
+        case 2: hipLaunchKernelGGL(toep_gemv_part_kernel<2>, grid, dim3(256), 0, s, M, K, p, t, X, ldx, slice, part); break;
+        case 3: hipLaunchKernelGGL(toep_gemv_part_kernel<3>, grid, dim3(256), 0, s, M, K, p, t, X, ldx, slice, part); break;
+        default: hipLaunchKernelGGL(toep_gemv_part_kernel<4>, grid, dim3(256), 0, s, M, K, p, t, X, ldx, slice, part); break;
+    }
+    const int tot = M * nrhs;
+    hipLaunchKernelGGL(gemv_t_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, M, nrhs, (int)P, part, alpha,
+                       beta, Yin, ldyi, Y, ldy);
     return hipGetLastError();
 }

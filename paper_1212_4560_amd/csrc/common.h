@@ -195,6 +195,13 @@ hipError_t launch_trsv_full(int kind, int t_f32, const void* T, long long ldt, i
 hipError_t launch_convert_f64_f32(const double* src, long long lds, float* dst, long long ldd, int rows, int cols,
                                   hipStream_t s);
 hipError_t launch_scale2d(double alpha, double* X, long long ldx, int rows, int cols, hipStream_t s);
+// y (M x nrhs) = alpha T X + beta yin for the Toeplitz T(i, k) = p[i - k + t - 1] (K columns, nrhs <= 4),
+// partial sums over K slices through part (part_cap doubles, at least M * nrhs), then their sum
+hipError_t launch_toep_gemv(int M, int K, int nrhs, double alpha, const double* p, long long t, const double* X,
+                            long long ldx, double beta, const double* Yin, long long ldyi, double* Y, long long ldy,
+                            double* part, long long part_cap, hipStream_t s);
+hipError_t launch_convert_f32_f64(const float* src, long long lds, double* dst, long long ldd, int rows, int cols,
+                                  hipStream_t s);
 
 // Vector kernels of GMRES and of the 1-norm estimator (krylov.hip).
 // out[i] = V_i . w for i < j1, V_i = V + i * ldv (n entries each); fixed reduction order.

@@ -69,6 +69,7 @@ struct genp_ctx {
     float* A32 = nullptr;      // n_pad x n_pad
     float* G32 = nullptr;      // dense G: n_pad x n_pad; Toeplitz: 2 n_pad - 1 parameters
     size_t g32_bytes = 0;
+    double* dwork = nullptr;   // FP32 forms, nb = 256: an FP64 copy of the current diagonal block
     double* w2 = nullptr;      // two-sided products with a dense or Toeplitz H: n x n copy of A G
     // right-hand-side scratch, capacity kcap columns
     int64_t kcap = 0;
@@ -167,6 +168,12 @@ int skinny(genp_ctx* c, int M, int K, int k, double alpha, const void* A, int64_
         return GENP_OK;
     }
     if (k <= 4) {
+        if (amode == OP_TOEP && c->kcap > 0) {
+            // Toeplitz operand (the multiplier): LDS-staged windows of its parameters, split over K
+            HIPCK(launch_toep_gemv(M, K, k, alpha, (const double*)A, lda, X, ldx, beta, Yin, ldyi, Y, ldy, c->part,
+                                   (long long)KSPLIT_MAX * c->n_pad * c->kcap, c->stream));
+            return GENP_OK;
+        }
         if (amode == OP_T && M >= 64 && c->kcap > 0) {
             // transposed operand: partial sums over row slices (coalesced), then their sum
             HIPCK(launch_gemv_t_f64(M, K, k, alpha, A, lda, a_f32, X, ldx, beta, Yin, ldyi, Y, ldy, c->part,
@@ -842,7 +849,7 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
         }
         const char* tv = getenv("GENP_TRSV");   // "step": one launch per block instead of the chained solve
         c->trsv_chain = !(tv && strcmp(tv, "step") == 0);
-        const char* dg = getenv("GENP_DIAG");   // "single": one workgroup per 256 diagonal block
+        const char* dg = getenv("GENP_DIAG");   // "single": one workgroup per 256 diagonal block (any precision)
         c->diag_split = !(dg && strcmp(dg, "single") == 0);
         const char* lg = getenv("GENP_LP_GEMM");   // "lds": the precision form's product from FP64 operands
         c->lp_regs = !(lg && strcmp(lg, "lds") == 0);
@@ -878,6 +885,7 @@ int genp_destroy(genp_ctx* c) {
     }
     hipFree(c->hw);
     hipFree(c->A32);
+    hipFree(c->dwork);
     hipFree(c->G32);
     hipFree(c->w2);
     hipFree(c->circ_tw);
@@ -1013,6 +1021,9 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
     const size_t es = esize(c->prec);
     char* Cb = (char*)c->C;
     auto at = [&](int64_t r, int64_t col) -> void* { return Cb + (r * ldc + col) * es; };
+    if (lp && c->diag_split && nb == 256 && !c->dwork &&
+        hipMalloc(&c->dwork, (size_t)256 * 256 * sizeof(double)) != hipSuccess)
+        return GENP_ENOMEM;
     const double* maxc = (const double*)(c->red + R_MAXC);
     const int64_t K = np / nb;
     hipStream_t S = c->stream, P = c->side;
@@ -1030,7 +1041,14 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
             HIPCK(launch_block_row_perm((double*)c->C, ldc, k, (int)nb, (int)np, c->perm + k, st));
         } else if (c->diag_split && c->prec == GENP_F64 && nb == 256)
             HIPCK(launch_diag_lu_split(at(k, k), ldc, nvalid, k, maxc, pivot_tol, c->stats + j, st));
-        else
+        else if (c->diag_split && nb == 256) {
+            // FP32 storage: the block widened into an FP64 scratch block, factored there by the
+            // same two-half kernels (FP64 arithmetic), and rounded back to FP32; one scratch
+            // block serves every step since the diagonal blocks run one after another on st
+            HIPCK(launch_convert_f32_f64((const float*)at(k, k), ldc, c->dwork, 256, 256, 256, st));
+            HIPCK(launch_diag_lu_split(c->dwork, 256, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+            HIPCK(launch_convert_f64_f32(c->dwork, 256, (float*)at(k, k), ldc, 256, 256, st));
+        } else
             HIPCK(launch_diag_lu(c->prec, at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
         return GENP_OK;
     };
@@ -1321,8 +1339,10 @@ namespace {
 // correction made eta worse (it is undone): the contraction factor is then above 1 and later
 // steps only diverge.  GMRES-IR keeps going through such a step (a cycle shrinks the residual's
 // 2-norm, which the infinity-norm eta need not follow at once) and stops after three steps in a
-// row without a new best; the best iterate is kept aside and returned.  Status: GENP_OK when
-// eta <= tol, or when tol = 0 (the steps were asked for, not a target); else GENP_ENOCONV.
+// row without a new best; the best iterate is kept aside and returned.  GENP_SOLVER_AUTO starts
+// with LU-IR and turns to GMRES-IR (from the best iterate) at the first correction that does
+// not divide eta by 4.  Status: GENP_OK when eta <= tol, or when tol = 0 (the steps were asked
+// for, not a target); else GENP_ENOCONV.
 int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
                 const genp_refine_opts& o, std::vector<double>& eta, int* iters_out, int* inner_out,
                 double* hist, int* n_hist) {
@@ -1331,42 +1351,51 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
     const int restart = o.restart > 0 ? o.restart : 50;
     const double rtol = o.inner_rtol > 0 ? o.inner_rtol : 1e-10;
     const int aop = trans ? OP_T : OP_N;
-    const bool gm = o.solver == GENP_SOLVER_GMRES;
+    auto residual = [&]() -> int {
+        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
+        return backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm);
+    };
+    // GENP_SOLVER_AUTO: LU-IR while each correction divides eta by 4 or more, GMRES-IR after
+    bool gm = o.solver == GENP_SOLVER_GMRES;
+    const bool adaptive = o.solver == GENP_SOLVER_AUTO;
     int inner_total = 0;
-    double best = INFINITY;
+    double best = INFINITY, prev = INFINITY;
     int it = 0, stall = 0;
-    bool cur_best = true;              // X is the best iterate so far (GMRES-IR)
+    bool cur_best = true;              // X is the best iterate so far
     int status = GENP_OK;
     *n_hist = 0;
     for (;;) {
-        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
-        CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
-        const double e = max_of(eta);
+        CK(residual());
+        double e = max_of(eta);
         if (*n_hist < GENP_ETA_HIST) hist[(*n_hist)++] = e;
-        if (!(e <= best) && it > 0 && !gm) {
-            // the last correction made things worse (or produced NaN): undo it
+        if (!gm && it > 0 && !(e <= best)) {
+            // an LU-IR correction made things worse (or produced NaN): undo it
             HIPCK(launch_axpy2d(-1.0, c->Dx, k, X, ldx, n, k, c->stream));
-            CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
-            CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
-            status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
-            break;
-        }
-        if (e < best || it == 0) {
+            CK(residual());
+            e = max_of(eta);
+            if (!adaptive) {
+                status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
+                break;
+            }
+            gm = true;   // X is the best iterate again: go on with GMRES-IR from it
+        } else if (e < best || it == 0) {
             best = std::min(best, e);
             stall = 0;
             cur_best = true;
-            if (gm) HIPCK(launch_copy2d(X, ldx, c->Xb, k, n, k, c->stream));
         } else {
             ++stall;
             cur_best = false;
         }
+        if (adaptive && !gm && it > 0 && !(e <= 0.25 * prev)) gm = true;   // LU-IR contracts too slowly
+        prev = e;
+        if (gm && cur_best) HIPCK(launch_copy2d(X, ldx, c->Xb, k, n, k, c->stream));
         if (e <= o.tol) break;
         const bool budget = gm && o.max_inner > 0 && inner_total >= o.max_inner;
         if (it >= o.max_outer || budget || (gm && stall >= 3)) {
             status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
             break;
         }
-        if (o.solver == GENP_SOLVER_LUIR) {
+        if (!gm) {
             // Dx = M^{-1} R
             if (trans) CK(solve_t_into(c, c->R, k, k, c->Dx, k));
             else CK(solve_into(c, c->R, k, k, c->Dx, k));
@@ -1392,8 +1421,7 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
     if (gm && !cur_best) {
         // return the best iterate, with its eta
         HIPCK(launch_copy2d(c->Xb, k, X, ldx, n, k, c->stream));
-        CK(skinny(c, n, n, k, -1.0, c->A, c->lda, aop, 0, X, ldx, 1.0, B, ldb, c->R, k));
-        CK(backward_error(c, c->R, k, X, ldx, B, ldb, k, eta, anorm));
+        CK(residual());
         if (max_of(eta) <= o.tol) status = GENP_OK;
     }
     *iters_out = it;
@@ -1403,7 +1431,8 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
 
 int check_opts(const genp_refine_opts* o) {
     if (!o) return GENP_EINVAL;
-    if (o->solver != GENP_SOLVER_LUIR && o->solver != GENP_SOLVER_GMRES) return GENP_EINVAL;
+    if (o->solver != GENP_SOLVER_LUIR && o->solver != GENP_SOLVER_GMRES && o->solver != GENP_SOLVER_AUTO)
+        return GENP_EINVAL;
     if (o->max_outer < 0 || o->max_inner < 0 || o->restart < 0 || o->restart > GENP_GMRES_MAX_RESTART ||
         !(o->tol >= 0) || !(o->inner_rtol >= 0))
         return GENP_EINVAL;
@@ -1430,7 +1459,7 @@ int backward_impl(genp_ctx* c, const double* W, int64_t ldw, const double* X, in
                   int64_t lddb, double* dA, int64_t ldda, const genp_refine_opts& o, double* eta_out) {
     const int k = (int)nrhs, n = (int)c->n;
     CK(ensure_rhs(c, nrhs));
-    if (o.solver == GENP_SOLVER_GMRES) CK(ensure_gmres(c, o.restart > 0 ? o.restart : 50));
+    if (o.solver != GENP_SOLVER_LUIR) CK(ensure_gmres(c, o.restart > 0 ? o.restart : 50));
     CK(ensure_anorm1(c));
     ev_begin(c, EV_BWD);
     CK(solve_t_into(c, W, ldw, k, dB, lddb));
@@ -1472,7 +1501,7 @@ int backward_impl(genp_ctx* c, const double* W, int64_t ldw, const double* X, in
 int refine_impl(genp_ctx* c, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
                 const genp_refine_opts& o, double* eta_out) {
     CK(ensure_rhs(c, nrhs));
-    if (o.solver == GENP_SOLVER_GMRES) CK(ensure_gmres(c, o.restart > 0 ? o.restart : 50));
+    if (o.solver != GENP_SOLVER_LUIR) CK(ensure_gmres(c, o.restart > 0 ? o.restart : 50));
     const int k = (int)nrhs;
     ev_begin(c, EV_REF);
     std::vector<double> eta;

@@ -25,13 +25,13 @@ LIB_PATH = os.path.join(HERE, "libgenp.so")
 
 F64, F32, BF16, BF16X3 = 0, 1, 2, 3
 G_DENSE, G_TOEPLITZ, G_NONE, G_CIRCULANT, G_HOUSEHOLDER = 0, 1, 2, 3, 4
-SOLVER_LUIR, SOLVER_GMRES = 0, 1
+SOLVER_LUIR, SOLVER_GMRES, SOLVER_AUTO = 0, 1, 2
 OK, BREAKDOWN, ENOCONV = 0, 1, 2
 EINVAL, EDEVICE, ENOMEM, ESTATE, ENOTSUP, ESINGULAR, ESCRATCH = -1, -2, -3, -4, -5, -6, -7
 ETA_HIST = 64
 
 PRECS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
-SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES}
+SOLVERS = {"luir": SOLVER_LUIR, "gmres": SOLVER_GMRES, "auto": SOLVER_AUTO}
 
 # the entry points declared in include/genp.h
 EXPORTS = ("genp_create", "genp_destroy", "genp_precondition", "genp_precondition2", "genp_factor", "genp_solve",

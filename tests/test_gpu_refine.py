@@ -171,3 +171,23 @@ def test_backward_ex_gmres_fp32_factors(n, smax):
     assert info["anorm_1"] == pytest.approx(np.max(np.sum(np.abs(w.A), axis=0)), rel=1e-13)
     tol = 10 * kappa * max(eo.max(), U64)
     assert err_b <= tol and err_a <= tol
+
+
+@pytest.mark.parametrize("smax,expect_switch", [(10.0, False), (1e6, True)])
+def test_refine_auto_luir_then_gmres(smax, expect_switch):
+    """GENP_SOLVER_AUTO: with FP32 factors and kappa(C) u32 < 1 it stays on LU-IR (no inner GMRES
+    steps); with kappa(C) u32 >> 1 it turns to GMRES-IR and still reaches the FP64 bar."""
+    n = 400
+    w = wl.haar_logspaced(n, smax, wl.MULT_TOEPLITZ, nrhs=2, seed=21)
+    s = genp.Solver(n, "f32", 128)
+    s.precondition(dev(w.A), p=dev(w.p))
+    assert s.factor() == 0
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, max_iter=60, tol=1e-14, solver="auto", restart=60)
+    info = s.info()
+    eta_o = og.backward_error_inf(w.A, host(X), w.B)
+    print(f"  smax {smax:g}: status {st} outer {info['iters']} inner {info['inner_iters']} eta {max(eta):.2e} "
+          f"oracle {eta_o.max():.2e} hist {['%.1e' % e for e in info['eta_hist']]}", flush=True)
+    assert st == genp.OK and np.all(eta_o <= 1e-14)
+    assert (info["inner_iters"] > 0) == expect_switch
