@@ -89,6 +89,25 @@ struct GemmF32Args {
     float* D; long long ldd;
 };
 hipError_t launch_gemm_f32_toep(const GemmF32Args& a, hipStream_t s);
+// BF16 product D (FP32, M x N) = A Bt^T with A (M x K) and Bt (N x K) BF16 row-major (gemm_bf16.hip);
+// with Alo and Btlo (the second words of 2-word BF16 operands) D = A Bt^T + A Btlo^T + Alo Bt^T.
+// M, N multiples of 256, K of 32, operands 16-byte aligned, lda and ldb multiples of 8.
+struct GemmBf16Args {
+    int M, N, K;
+    const unsigned short* A; long long lda;
+    const unsigned short* Bt; long long ldb;
+    const unsigned short* Alo;
+    const unsigned short* Btlo;
+    float* D; long long ldd;
+};
+hipError_t launch_gemm_bf16_nt(const GemmBf16Args& a, hipStream_t s);
+// hi (n_pad x n_pad) = bf16(fp32(A)), lo (nullable) = bf16(fp32(A) - hi); zero padding
+hipError_t launch_to_bf16(const double* A, long long lda, int n, int n_pad, unsigned short* hi, unsigned short* lo,
+                          hipStream_t s);
+// hi / lo (n_pad x n_pad): the transpose of G (dense, ldg; or Toeplitz parameters when toep) in the
+// same 2-word BF16 split, zero padding
+hipError_t launch_gt_bf16(const double* G, long long ldg, int toep, int n, int n_pad, unsigned short* hi,
+                          unsigned short* lo, hipStream_t s);
 // out (rows_pad x rows_pad, ldo) = A (n x n FP64) rounded to FP32 (bf16: then to BF16), zero padding
 hipError_t launch_convert_pad(const double* A, long long lda, int n, int n_pad, float* out, long long ldo, int bf16,
                               hipStream_t s);

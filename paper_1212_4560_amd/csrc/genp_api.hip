@@ -70,6 +70,9 @@ struct genp_ctx {
     float* G32 = nullptr;      // dense G: n_pad x n_pad; Toeplitz: 2 n_pad - 1 parameters
     size_t g32_bytes = 0;
     double* dwork = nullptr;   // FP32 forms, nb = 256: an FP64 copy of the current diagonal block
+    // BF16 forms: BF16 copies of A and of G^T (hi words; lo words for the 2-word form), n_pad x n_pad
+    unsigned short* Abf[2] = {nullptr, nullptr};
+    unsigned short* Gtbf[2] = {nullptr, nullptr};
     double* w2 = nullptr;      // two-sided products with a dense or Toeplitz H: n x n copy of A G
     // right-hand-side scratch, capacity kcap columns
     int64_t kcap = 0;
@@ -648,6 +651,33 @@ int right_product(genp_ctx* c, const double* A, int64_t lda) {
         HIPCK(launch_gemm_f64(g, 0, c->stream));
         return GENP_OK;
     }
+    if (c->lp_regs && c->prec != GENP_F32 && c->n_pad % 256 == 0) {
+        // BF16 forms: A and G^T rounded once (FP64 -> FP32 -> BF16; the 2-word form also keeps
+        // lo = bf16(x - hi)) into zero-padded copies, then the LDS-staged BF16 MFMA product
+        const int np = (int)c->n_pad;
+        const bool x3 = c->prec == GENP_BF16X3;
+        const size_t sq = (size_t)np * np * sizeof(unsigned short);
+        for (int w = 0; w < (x3 ? 2 : 1); ++w) {
+            if (!c->Abf[w] && hipMalloc(&c->Abf[w], sq) != hipSuccess) return GENP_ENOMEM;
+            if (!c->Gtbf[w] && hipMalloc(&c->Gtbf[w], sq) != hipSuccess) return GENP_ENOMEM;
+        }
+        const bool dense = m.kind == GENP_G_DENSE;
+        HIPCK(launch_to_bf16(A, lda, (int)n, np, c->Abf[0], x3 ? c->Abf[1] : nullptr, c->stream));
+        HIPCK(launch_gt_bf16(dense ? m.G : m.p, dense ? m.ldg : 0, dense ? 0 : 1, (int)n, np, c->Gtbf[0],
+                             x3 ? c->Gtbf[1] : nullptr, c->stream));
+        GemmBf16Args g{};
+        g.M = g.N = g.K = np;
+        g.A = c->Abf[0];
+        g.lda = np;
+        g.Bt = c->Gtbf[0];
+        g.ldb = np;
+        g.Alo = x3 ? c->Abf[1] : nullptr;
+        g.Btlo = x3 ? c->Gtbf[1] : nullptr;
+        g.D = (float*)c->C;
+        g.ldd = c->ldc;
+        HIPCK(launch_gemm_bf16_nt(g, c->stream));
+        return GENP_OK;
+    }
     if (c->lp_regs) {
         // precision form: A and G rounded once to FP32 (BF16 form: then to BF16) into copies
         // zero-padded to n_pad, then the product over n_pad (padding rows and columns of C are
@@ -886,6 +916,10 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->hw);
     hipFree(c->A32);
     hipFree(c->dwork);
+    for (int w = 0; w < 2; ++w) {
+        hipFree(c->Abf[w]);
+        hipFree(c->Gtbf[w]);
+    }
     hipFree(c->G32);
     hipFree(c->w2);
     hipFree(c->circ_tw);

@@ -42,8 +42,12 @@ def host(t):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("n,mult", [(1, "dense"), (64, "dense"), (200, "dense"), (517, "toeplitz"),
-                                    (300, "toeplitz")])
+                                    (300, "toeplitz"), (512, "toeplitz"), (768, "dense")])
 def test_lowprec_precondition_entrywise(prec, n, mult):
+    """C = A G in each precision form against the product of the rounded operands.  Sizes whose
+    padded order is a multiple of 256 (200, 512, 768) take the BF16 forms' LDS-staged BF16 kernel
+    from BF16 copies of A and G^T; FP32 with a Toeplitz G takes the register-operand kernel; the
+    others the LDS-staged kernel from FP32 copies."""
     print(f"precondition {prec} n={n} {mult}", flush=True)
     g = np.random.default_rng(n + 1)
     A = g.standard_normal((n, n))
