@@ -431,7 +431,9 @@ def log(*a):
 
 
 def cpu_baseline(name: str, n_sample: int, prec_note: str) -> dict:
-    """The FP64 oracle (block elimination, nb = 256) on the host cores, same recipe at n_sample."""
+    """The FP64 oracle (block elimination, nb = 256) on the host cores, same recipe at n_sample
+    (the benchmark's n by default), with numpy.linalg.solve (LAPACK, partial pivoting) timed
+    beside it on the same A and b as the conventional host solve."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -446,13 +448,21 @@ def cpu_baseline(name: str, n_sample: int, prec_note: str) -> dict:
     t0 = time.perf_counter()
     res, LU, info = og.genp_solve(A, B, G, nb=256, refine_steps=2, tol=1e-14)
     dt = time.perf_counter() - t0
+    del LU, G
     threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
     steps = res.steps if res is not None else 0
     gf = method_flops(n_sample, 1, steps) / dt / 1e9
+    t1 = time.perf_counter()
+    xg = np.linalg.solve(A, B)
+    dg = time.perf_counter() - t1
+    eta_g = float(np.max(og.backward_error_inf(A, xg, B)))
+    gepp = {"seconds": round(dg, 2), "gflops_lu": round((2.0 / 3.0) * n_sample ** 3 / dg / 1e9, 1), "eta": eta_g,
+            "note": "numpy.linalg.solve (LAPACK getrf/getrs, partial pivoting) on the same A and b"}
+    log(f"[bench] cpu baseline: oracle {dt:.1f} s ({gf:.0f} GFLOP/s), LAPACK solve {dg:.1f} s, {threads} threads")
     return {"value": round(gf, 2), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{name} recipe at n={n_sample}, 1 RHS, FP64 block GENP (nb=256) + {steps} refinement "
                       f"step(s), {dt:.1f} s wall; {prec_note}",
-            "eta": float(res.eta_hist[-1]) if res is not None else None}
+            "eta": float(res.eta_hist[-1]) if res is not None else None, "gepp_reference": gepp}
 
 
 def main() -> int:
@@ -468,7 +478,7 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-14)
     ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--solver", default="luir", choices=["luir", "gmres"])
-    ap.add_argument("--cpu-sample-n", type=int, default=12288)
+    ap.add_argument("--cpu-sample-n", type=int, default=16384)
     ap.add_argument("--no-mixed", action="store_true", help="skip the precision-form sweep")
     ap.add_argument("--sweep-restart", type=int, default=100, help="GMRES cycle length in the precision-form sweep")
     ap.add_argument("--sweep-cap", type=int, default=1000, help="inner GMRES steps at most per sweep cell")

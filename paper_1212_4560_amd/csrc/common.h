@@ -99,8 +99,14 @@ struct GemmBf16Args {
     const unsigned short* Alo;
     const unsigned short* Btlo;
     float* D; long long ldd;
+    float alpha, beta;                  // D = alpha product + beta Cin (Cin may alias D)
+    const float* Cin; long long ldci;
 };
 hipError_t launch_gemm_bf16_nt(const GemmBf16Args& a, hipStream_t s);
+// hi / lo (rows x cols, ldo) = 2-word BF16 split of an FP32 block X (rows x cols, ldx); with trans,
+// hi / lo (cols x rows) = the split of X^T; lo nullable
+hipError_t launch_split_bf16(const float* X, long long ldx, int rows, int cols, int trans, unsigned short* hi,
+                             unsigned short* lo, long long ldo, hipStream_t s);
 // hi (n_pad x n_pad) = bf16(fp32(A)), lo (nullable) = bf16(fp32(A) - hi); zero padding
 hipError_t launch_to_bf16(const double* A, long long lda, int n, int n_pad, unsigned short* hi, unsigned short* lo,
                           hipStream_t s);

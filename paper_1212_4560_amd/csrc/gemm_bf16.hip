@@ -23,6 +23,14 @@ constexpr int BKB = 32;      // k-chunk
 constexpr int LDB = BKB + 8; // LDS row stride in bf16 (80 bytes: 16-byte aligned rows)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet)
+__device__ inline unsigned short bf16_bits(float f) {
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
 typedef const u32x4 __attribute__((address_space(1)))* gu4_ptr;
 
 template <bool X3>
@@ -117,25 +125,49 @@ gemm_bf16_nt_kernel(GemmBf16Args g) {
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
-    // D = acc (row 4 lq + r, column lr of each 16 x 16 tile)
+    // D = alpha acc + beta Cin (row 4 lq + r, column lr of each 16 x 16 tile); each element is
+    // read before it is written, by the same lane, so Cin may alias D
     float __attribute__((address_space(1)))* D = (float __attribute__((address_space(1)))*)g.D;
+    const bool rd = g.beta != 0.f;
 #pragma unroll
     for (int mi = 0; mi < 8; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 8; ++ni)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                D[(long long)(m0 + wm * 128 + mi * 16 + lq * 4 + r) * g.ldd + n0 + wn * 128 + ni * 16 + lr] = acc[mi][ni][r];
+            for (int r = 0; r < 4; ++r) {
+                const long long row = m0 + wm * 128 + mi * 16 + lq * 4 + r, col = n0 + wn * 128 + ni * 16 + lr;
+                float v = g.alpha * acc[mi][ni][r];
+                if (rd) v = fmaf(g.beta, g.Cin[row * g.ldci + col], v);
+                D[row * g.ldd + col] = v;
+            }
 }
 
-// FP64 -> FP32 -> BF16, round to nearest even at each step (NaN kept quiet); with lo, also
-// lo = bf16(x32 - hi) (exact in FP32: hi carries x32's leading bits)
-__device__ inline unsigned short bf16_bits(float f) {
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x0040u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+// hi / lo = 2-word BF16 split of an FP32 block (trans: of its transpose), 32 x 32 tiles via LDS
+__global__ void __launch_bounds__(256)
+split_bf16_kernel(const float* __restrict__ X, long long ldx, int rows, int cols, int trans,
+                  unsigned short* __restrict__ hi, unsigned short* __restrict__ lo, long long ldo) {
+    __shared__ float t[32][33];
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = r0 + r, j = c0 + tx;
+        t[r][tx] = (i < rows && j < cols) ? X[(long long)i * ldx + j] : 0.f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        // output row: trans ? column c0 + r of X : row r0 + r; output column likewise
+        const int oi = trans ? c0 + r : r0 + r, oj = trans ? r0 + tx : c0 + tx;
+        const float v = trans ? t[tx][r] : t[r][tx];
+        if (oi < (trans ? cols : rows) && oj < (trans ? rows : cols)) {
+            const unsigned short h = bf16_bits(v);
+            hi[(long long)oi * ldo + oj] = h;
+            if (lo) lo[(long long)oi * ldo + oj] = bf16_bits(v - __uint_as_float((unsigned int)h << 16));
+        }
+    }
 }
+
+// FP64 -> FP32 -> BF16, round to nearest even at each step; with lo, also lo = bf16(x32 - hi)
+// (exact in FP32: hi carries x32's leading bits)
 
 __device__ inline void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
     const float f = (float)x;
@@ -207,5 +239,13 @@ hipError_t launch_gt_bf16(const double* G, long long ldg, int toep, int n, int n
                           unsigned short* lo, hipStream_t s) {
     const dim3 grid((unsigned)((n_pad + 31) / 32), (unsigned)((n_pad + 31) / 32));
     hipLaunchKernelGGL(gt_bf16_kernel, grid, dim3(256), 0, s, G, ldg, toep, n, n_pad, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_bf16(const float* X, long long ldx, int rows, int cols, int trans, unsigned short* hi,
+                             unsigned short* lo, long long ldo, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    hipLaunchKernelGGL(split_bf16_kernel, grid, dim3(256), 0, s, X, ldx, rows, cols, trans, hi, lo, ldo);
     return hipGetLastError();
 }

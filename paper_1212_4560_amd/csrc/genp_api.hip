@@ -73,6 +73,9 @@ struct genp_ctx {
     // BF16 forms: BF16 copies of A and of G^T (hi words; lo words for the 2-word form), n_pad x n_pad
     unsigned short* Abf[2] = {nullptr, nullptr};
     unsigned short* Gtbf[2] = {nullptr, nullptr};
+    // ... and of the update operands L21 (n_pad x K) and U12^T (n_pad x K), K <= 8 nb
+    unsigned short* Lbf[2] = {nullptr, nullptr};
+    unsigned short* Ubf[2] = {nullptr, nullptr};
     double* w2 = nullptr;      // two-sided products with a dense or Toeplitz H: n x n copy of A G
     // right-hand-side scratch, capacity kcap columns
     int64_t kcap = 0;
@@ -675,6 +678,8 @@ int right_product(genp_ctx* c, const double* A, int64_t lda) {
         g.Btlo = x3 ? c->Gtbf[1] : nullptr;
         g.D = (float*)c->C;
         g.ldd = c->ldc;
+        g.alpha = 1.f;
+        g.beta = 0.f;
         HIPCK(launch_gemm_bf16_nt(g, c->stream));
         return GENP_OK;
     }
@@ -919,6 +924,8 @@ int genp_destroy(genp_ctx* c) {
     for (int w = 0; w < 2; ++w) {
         hipFree(c->Abf[w]);
         hipFree(c->Gtbf[w]);
+        hipFree(c->Lbf[w]);
+        hipFree(c->Ubf[w]);
     }
     hipFree(c->G32);
     hipFree(c->w2);
@@ -1058,6 +1065,13 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
     if (lp && c->diag_split && nb == 256 && !c->dwork &&
         hipMalloc(&c->dwork, (size_t)256 * 256 * sizeof(double)) != hipSuccess)
         return GENP_ENOMEM;
+    if (lp && c->prec != GENP_F32 && c->lp_regs && nb == 256) {
+        const size_t sz = (size_t)np * 8 * nb * sizeof(unsigned short);
+        for (int w = 0; w < (c->prec == GENP_BF16X3 ? 2 : 1); ++w) {
+            if (!c->Lbf[w] && hipMalloc(&c->Lbf[w], sz) != hipSuccess) return GENP_ENOMEM;
+            if (!c->Ubf[w] && hipMalloc(&c->Ubf[w], sz) != hipSuccess) return GENP_ENOMEM;
+        }
+    }
     const double* maxc = (const double*)(c->red + R_MAXC);
     const int64_t K = np / nb;
     hipStream_t S = c->stream, P = c->side;
@@ -1098,6 +1112,7 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         CK(diag(j, st));
         return solves(j, st);
     };
+    int64_t l21_key[4] = {-1, -1, -1, -1};   // BF16 forms: the L21 block last split into BF16 words
     // Schur update of steps j .. j+kb-1 (kb = 1 or 2: their L21 columns and U12 rows are
     // adjacent, so both updates are one product with K = kb nb), restricted to rows
     // [r0, r0 + M) x cols [c0, c0 + N) of the trailing block
@@ -1105,6 +1120,40 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         if (M <= 0 || N <= 0) return GENP_OK;
         const int64_t k = j * nb;
         const int KK = (int)(kb * nb);
+        if (lp && c->prec != GENP_F32 && c->lp_regs && nb == 256) {
+            // BF16 forms: L21 and U12^T split into BF16 words (scratch), then the BF16 MFMA product
+            // A22 -= L21 U12 (the 2-word form: hi hi + hi lo + lo hi)
+            const bool x3 = c->prec == GENP_BF16X3;
+            // the parts of one bulk update share their L21: split it once
+            if (!(l21_key[0] == r0 && l21_key[1] == k && l21_key[2] == KK && l21_key[3] == M)) {
+                HIPCK(launch_split_bf16((const float*)at(r0, k), ldc, (int)M, KK, 0, c->Lbf[0],
+                                        x3 ? c->Lbf[1] : nullptr, KK, st));
+                l21_key[0] = r0;
+                l21_key[1] = k;
+                l21_key[2] = KK;
+                l21_key[3] = M;
+            }
+            HIPCK(launch_split_bf16((const float*)at(k, c0), ldc, KK, (int)N, 1, c->Ubf[0], x3 ? c->Ubf[1] : nullptr,
+                                    KK, st));
+            GemmBf16Args g{};
+            g.M = (int)M;
+            g.N = (int)N;
+            g.K = KK;
+            g.A = c->Lbf[0];
+            g.lda = KK;
+            g.Bt = c->Ubf[0];
+            g.ldb = KK;
+            g.Alo = x3 ? c->Lbf[1] : nullptr;
+            g.Btlo = x3 ? c->Ubf[1] : nullptr;
+            g.D = (float*)at(r0, c0);
+            g.ldd = ldc;
+            g.alpha = -1.f;
+            g.beta = 1.f;
+            g.Cin = (const float*)at(r0, c0);
+            g.ldci = ldc;
+            HIPCK(launch_gemm_bf16_nt(g, st));
+            return GENP_OK;
+        }
         if (lp) {
             GemmLpArgs g{};
             g.M = (int)M;
