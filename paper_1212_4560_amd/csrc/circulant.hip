@@ -7,9 +7,9 @@
 // with X, Y, C the DFTs of length n.
 //
 // One workgroup per vector.  The real vector of length n = 2N is packed as N complex
-// numbers z[k] = x[2k] + i x[2k+1] and transformed in place in LDS (radix 2, length N:
-// decimation in time from bit-reversed order, so the spectrum comes out in natural
-// order).  The spectrum of the real vector follows from Z[f] and Z[N-f]:
+// numbers z[k] = x[2k] + i x[2k+1] and transformed in place in LDS (radix-2 butterflies,
+// three stages per pass over LDS, length N: decimation in time from bit-reversed order, so
+// the spectrum comes out in natural order).  The spectrum of the real vector follows from Z[f] and Z[N-f]:
 //   E[f] = (Z[f] + conj Z[N-f]) / 2,  O[f] = (Z[f] - conj Z[N-f]) / (2i),
 //   X[f] = E[f] + W^f O[f]  (W = e^{-2 pi i / n}),  f = 0..N.
 // After the product R = X S (S = C or conj C), the inverse runs the same relations
@@ -26,6 +26,7 @@ namespace {
 
 constexpr int CIRC_MAXN2 = 8192;   // largest N = n / 2: N complex doubles = 128 KB of LDS
 constexpr int CIRC_THREADS = 512;
+constexpr int FFT_R = 4;           // radix-2 stages per pass over LDS
 
 struct cplx {
     double re, im;
@@ -35,6 +36,57 @@ __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im};
 __device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
 __device__ inline cplx cconj(cplx a) { return {a.re, -a.im}; }
 __device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
+
+// r consecutive radix-2 stages (r <= 4) of a length-N FFT in place in L.  Forward (decimation
+// in time): stages of halves q, 2q, .., q 2^(r-1), q = 2^qlog; inverse (decimation in
+// frequency, conjugate twiddles): stages of halves q 2^(r-1), .., 2q, q.  Each thread owns the
+// 2^r elements base + m q of aligned blocks of 2^r q (registers: r is a template parameter, so
+// every index into v is a constant).
+template <bool INV, int RL>
+__device__ inline void fft_pass_r(cplx* L, int N, int qlog, int tid, const double2* __restrict__ tw) {
+    constexpr int R = 1 << RL;
+    const int q = 1 << qlog;
+    for (int g = tid; g < (N >> RL); g += CIRC_THREADS) {
+        const int pos = g & (q - 1);
+        const int base = (g - pos) * R + pos;
+        cplx v[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = L[base + m * q];
+#pragma unroll
+        for (int t = 0; t < RL; ++t) {
+            const int sb = INV ? RL - 1 - t : t;   // pairs m, m + 2^sb (compile-time after unrolling)
+            const int h = q << sb;                 // the stage's half
+            const int step = N / (2 * h);
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                if (m & (1 << sb)) continue;
+                const int mm = m + (1 << sb);
+                const int p = pos + (m & ((1 << sb) - 1)) * q;
+                const double2 w2 = tw[p * step];
+                if (!INV) {
+                    const cplx tt = cmul({w2.x, w2.y}, v[mm]);
+                    const cplx a = v[m];
+                    v[m] = cadd(a, tt);
+                    v[mm] = csub(a, tt);
+                } else {
+                    const cplx a = v[m], c = v[mm];
+                    v[m] = cadd(a, c);
+                    v[mm] = cmul(csub(a, c), {w2.x, -w2.y});
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) L[base + m * q] = v[m];
+    }
+}
+
+template <bool INV>
+__device__ inline void fft_pass(cplx* L, int N, int qlog, int r, int tid, const double2* __restrict__ tw) {
+    if (r == 4) fft_pass_r<INV, 4>(L, N, qlog, tid, tw);
+    else if (r == 3) fft_pass_r<INV, 3>(L, N, qlog, tid, tw);
+    else if (r == 2) fft_pass_r<INV, 2>(L, N, qlog, tid, tw);
+    else fft_pass_r<INV, 1>(L, N, qlog, tid, tw);
+}
 
 // MODE 0: y = alpha * (x correlated / convolved with c) + beta * yin.
 // MODE 1: the spectrum X[0..N] of x itself (the multiplier's spectrum, once per multiplier),
@@ -57,19 +109,18 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
         L[r] = {xv[(2LL * k) * sx], xv[(2LL * k + 1) * sx]};
     }
     __syncthreads();
-    // forward FFT of length N, decimation in time
-    for (int len = 2; len <= N; len <<= 1) {
-        const int half = len >> 1, step = N / len;
-        for (int j = tid; j < (N >> 1); j += CIRC_THREADS) {
-            const int pos = j & (half - 1);
-            const int i0 = (j - pos) * 2 + pos, i1 = i0 + half;
-            const double2 w2 = tw[pos * step];
-            const cplx t = cmul({w2.x, w2.y}, L[i1]);
-            const cplx a = L[i0];
-            L[i0] = cadd(a, t);
-            L[i1] = csub(a, t);
-        }
+    // forward FFT of length N, decimation in time: the radix-2 stages of halves 1, 2, .., N/2
+    // taken FFT_R at a time.  In a pass whose first stage has half q, a thread owns the 2^r
+    // elements base + m q of one aligned block of 2^r q and runs the pass's stages on them in
+    // registers: stage s pairs m and m + 2^s (bit s of m clear) at distance h = q 2^s, with the
+    // twiddle of the lower element's offset pos + (m mod 2^s) q in its block of 2h -- the same
+    // butterflies, in the same order per element, as one stage at a time, with a fraction of the
+    // LDS passes and barriers.
+    for (int s0 = 0; s0 < logN;) {
+        const int r = min(FFT_R, logN - s0);
+        fft_pass<false>(L, N, s0, r, tid, tw);
         __syncthreads();
+        s0 += r;
     }
     // spectrum of the real vector, product with the multiplier's spectrum, repack
     double smax = 0.0, smin = __builtin_inf();   // MODE 1: extreme moduli (NaN sticks)
@@ -148,18 +199,14 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
         return;
     }
     __syncthreads();
-    // inverse FFT of length N, decimation in frequency (bit-reversed output)
-    for (int len = N; len >= 2; len >>= 1) {
-        const int half = len >> 1, step = N / len;
-        for (int j = tid; j < (N >> 1); j += CIRC_THREADS) {
-            const int pos = j & (half - 1);
-            const int i0 = (j - pos) * 2 + pos, i1 = i0 + half;
-            const double2 w2 = tw[pos * step];
-            const cplx a = L[i0], c = L[i1];
-            L[i0] = cadd(a, c);
-            L[i1] = cmul(csub(a, c), {w2.x, -w2.y});
-        }
+    // inverse FFT of length N, decimation in frequency (bit-reversed output): the stages of
+    // halves N/2, N/4, .., 1, FFT_R at a time in the same way (a pass whose last stage has half
+    // q: elements base + m q, stage t pairs m and m + 2^(r-1-t))
+    for (int sh = logN - 1; sh >= 0;) {
+        const int r = min(FFT_R, sh + 1);
+        fft_pass<true>(L, N, sh - r + 1, r, tid, tw);
         __syncthreads();
+        sh -= r;
     }
     const double s = alpha / (double)N;
     TO* yv = y + b * by;
