@@ -282,8 +282,8 @@ typedef struct {
     int32_t max_outer;    /* corrections (outer steps) at most, >= 0                               */
     int32_t restart;      /* GMRES: steps of one cycle (one cycle per column and outer step),
                              1 .. GENP_GMRES_MAX_RESTART; 0 = 50                                   */
-    int32_t max_inner;    /* GMRES: inner steps summed over all cycles at most (0 = no cap); the
-                             last cycle is shortened to fit                                         */
+    int32_t max_inner;    /* GMRES: inner steps summed over all cycles and columns at most (0 = no
+                             cap); the last cycle is shortened to fit                               */
     double tol;           /* stop once max_j eta_j <= tol (0: run the steps, no target)             */
     double inner_rtol;    /* GMRES: a cycle stops once its residual 2-norm has dropped by this
                              factor (0 = 1e-10)                                                      */
@@ -295,12 +295,17 @@ typedef struct {
  * that A M^{-1} = I for exact factors).  Each outer step computes R = B - A X in FP64 from the
  * original A, then the correction (LU-IR: D = M^{-1} R; GMRES: one cycle of at most
  * o->restart steps per column, classical Gram-Schmidt applied twice, within the o->max_inner
- * budget), X += D.  Stops at max_j eta_j <= o->tol, after o->max_outer steps, when the budget
+ * budget), X += D.  With 2 to 64 right-hand sides the columns' cycles run side by side (one
+ * preconditioner solve and one product with A per step for all columns; a column stops
+ * growing once it meets inner_rtol), each cycle then gets at most
+ * (max_inner - steps so far) / nrhs steps, and the budget counts as spent once fewer than
+ * nrhs steps remain.  Stops at max_j eta_j <= o->tol, after o->max_outer steps, when the budget
  * is spent, or when a step raised eta (it is undone; X holds the best iterate).  Returns GENP_OK
  * (eta <= tol, or tol = 0) or GENP_ENOCONV; eta_out (nullable, host, nrhs doubles) receives the
  * final eta_j; genp_info records the steps, the inner steps and the eta history.
  * Errors: GENP_EINVAL (bad options or arguments), GENP_ESTATE, GENP_ENOMEM (the Krylov basis,
- * (restart + 1) n_pad doubles, is allocated on first use of a larger restart), GENP_EDEVICE.
+ * (restart + 1) n_pad doubles per column, is allocated on first use of a larger one),
+ * GENP_EDEVICE.
  * Synchronizes the stream.
  */
 int genp_refine_ex(genp_ctx* ctx, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,

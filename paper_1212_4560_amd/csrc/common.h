@@ -232,6 +232,15 @@ hipError_t launch_convert_f32_f64(const float* src, long long lds, double* dst, 
 // out[i] = V_i . w for i < j1, V_i = V + i * ldv (n entries each); fixed reduction order.
 hipError_t launch_multidot(int n, int j1, const double* V, long long ldv, const double* w, double* out,
                            hipStream_t s);
+// k columns at once (k <= 64), V_i = V + i * vs and W n x k row-major blocks:
+// out[i * k + c] = V_i(:, c) . W(:, c) for i < j1
+hipError_t launch_bdot(int n, int k, int j1, const double* V, long long vs, const double* W, double* out,
+                       hipStream_t s);
+// W = beta W + sign sum_{i < j1} V_i diag(h[i * k .. i * k + k - 1])
+hipError_t launch_bcomb(int n, int k, int j1, const double* V, long long vs, const double* h, double sign, double beta,
+                        double* W, hipStream_t s);
+// X(:, c) *= f[c] for an n x k block (f: device, k doubles); f[c] = 0 sets the column to zero
+hipError_t launch_colscale(int n, int k, const double* f, double* X, hipStream_t s);
 // out[0] = ||y||_1, out[1] = 1 if sign(y) == xi elementwise (sign(0) = +1) else 0; then xi = sign(y).
 hipError_t launch_cest_sign(int n, const double* y, double* xi, double* out, hipStream_t s);
 // out[0] = ||z||_inf, out[1] = first index attaining it, out[2] = z[jlast] (or -1 when jlast < 0).

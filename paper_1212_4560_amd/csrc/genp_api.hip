@@ -92,6 +92,13 @@ struct genp_ctx {
     double* gm_z = nullptr;
     double* gm_r = nullptr;
     double* gm_h = nullptr;
+    // GMRES-IR over several columns at once: Krylov blocks ((restart + 1) x n_pad x k), two
+    // n_pad x 64 work blocks, the coefficients of a step (2 (restart + 2) 64 + 64 doubles)
+    size_t gmb_cap = 0;
+    double* gmb_V = nullptr;
+    double* gmb_w = nullptr;
+    double* gmb_z = nullptr;
+    double* gmb_h = nullptr;
     // 1-norm estimator: four n_pad vectors, then 8 scalars
     double* cest = nullptr;
     double anorm1 = -1.0;              // ||A||_1 (= ||A^T||_inf), < 0 until the adjoint needs it
@@ -112,6 +119,7 @@ struct genp_ctx {
     bool trsv_chain = true;
     bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
     bool lp_regs = true;               // precision forms: product from FP32 copies of A and G
+    bool gm_batched = true;            // GMRES-IR over 2..64 columns: one cycle for all columns
     // steps per group of the factorization: g_big while the trailing matrix has at least
     // g_switch rows, then g_small
     int g_big = 3, g_small = 2;
@@ -452,6 +460,25 @@ int ensure_gmres(genp_ctx* c, int m) {
     return GENP_OK;
 }
 
+int ensure_gmres_batched(genp_ctx* c, int m, int k) {
+    const size_t np = (size_t)c->n_pad;
+    if (!c->gmb_w) {
+        if (hipMalloc(&c->gmb_w, np * 64 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->gmb_z, np * 64 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->gmb_h, ((size_t)2 * (GENP_GMRES_MAX_RESTART + 2) * 64 + 64) * sizeof(double)) != hipSuccess)
+            return GENP_ENOMEM;
+    }
+    const size_t need = (size_t)(m + 1) * np * k;
+    if (need > c->gmb_cap) {
+        hipFree(c->gmb_V);
+        c->gmb_V = nullptr;
+        c->gmb_cap = 0;
+        if (hipMalloc(&c->gmb_V, need * sizeof(double)) != hipSuccess) return GENP_ENOMEM;
+        c->gmb_cap = need;
+    }
+    return GENP_OK;
+}
+
 // X (n x k) = H^T U^{-T} L^{-T} G^T Bin (the transposed solve: C^T = G^T A^T H^T), Z as workspace.
 int solve_t_into(genp_ctx* c, const double* Bin, int64_t ldb, int k, double* X, int64_t ldx) {
     double* Z = c->Z;
@@ -554,6 +581,118 @@ int gmres_cycle(genp_ctx* c, bool trans, int m, const double* r, double* d, doub
     // the host vector y must outlive the copy above
     HIPCK(hipStreamSynchronize(c->stream));
     return precond(c, trans, c->gm_w, d);
+}
+
+// The same cycle for the k <= 64 columns of R (n x k, row-major, ld k) at once: one Arnoldi step
+// preconditions and multiplies all k basis columns together (the many-column substitutions and a
+// GEMM with A instead of k vector sweeps), the Gram-Schmidt dots and updates run per column on
+// the device, and each column keeps its own Hessenberg matrix, rotations and stopping test on the
+// host.  A column that has met its tolerance (or broken down) stops growing: its later basis
+// vectors are scaled to zero.  D (n x k, ld k) receives the corrections; its[c] the steps of
+// column c.
+int gmres_cycle_batched(genp_ctx* c, bool trans, int m, int k, const double* R, double* D, double tol_rel,
+                        std::vector<int>& its) {
+    const int n = (int)c->n;
+    const long long vs = (long long)c->n_pad * k;     // block stride of the basis
+    double* V = c->gmb_V;
+    double* hd1 = c->gmb_h;                            // first Gram-Schmidt pass: (m + 2) x k
+    double* hd2 = hd1 + (size_t)(m + 2) * k;           // second pass and the new norms
+    double* fs = hd2 + (size_t)(m + 2) * k;            // k column scales
+    its.assign(k, 0);
+    HIPCK(hipMemcpyAsync(V, R, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCK(launch_bdot(n, k, 1, V, vs, V, hd1, c->stream));
+    std::vector<double> beta(k), f(k), h1((size_t)(m + 2) * k), h2((size_t)(m + 2) * k);
+    HIPCK(hipMemcpyAsync(beta.data(), hd1, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    std::vector<char> active(k);
+    int nact = 0;
+    for (int col = 0; col < k; ++col) {
+        beta[col] = sqrt(beta[col]);
+        active[col] = beta[col] > 0 && std::isfinite(beta[col]);
+        f[col] = active[col] ? 1.0 / beta[col] : 0.0;
+        nact += active[col];
+    }
+    if (nact == 0) {
+        HIPCK(launch_fill2d(0.0, D, k, n, k, c->stream));
+        return GENP_OK;
+    }
+    HIPCK(hipMemcpyAsync(fs, f.data(), k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCK(launch_colscale(n, k, fs, V, c->stream));
+    std::vector<std::vector<double>> H(k, std::vector<double>((size_t)(m + 1) * m, 0.0));
+    std::vector<std::vector<double>> cs(k, std::vector<double>(m)), sn(k, std::vector<double>(m));
+    std::vector<std::vector<double>> g(k, std::vector<double>(m + 1, 0.0));
+    for (int col = 0; col < k; ++col) g[col][0] = beta[col];
+    int jmax = 0;
+    for (int j = 0; j < m && nact > 0; ++j) {
+        double* Vj = V + (size_t)j * vs;
+        double* Vj1 = V + (size_t)(j + 1) * vs;
+        if (trans) CK(solve_t_into(c, Vj, k, k, c->gmb_z, k));
+        else CK(solve_into(c, Vj, k, k, c->gmb_z, k));
+        CK(skinny(c, n, n, k, 1.0, c->A, c->lda, trans ? OP_T : OP_N, 0, c->gmb_z, k, 0.0, nullptr, k, Vj1, k));
+        HIPCK(launch_bdot(n, k, j + 1, V, vs, Vj1, hd1, c->stream));
+        HIPCK(launch_bcomb(n, k, j + 1, V, vs, hd1, -1.0, 1.0, Vj1, c->stream));
+        HIPCK(launch_bdot(n, k, j + 1, V, vs, Vj1, hd2, c->stream));
+        HIPCK(launch_bcomb(n, k, j + 1, V, vs, hd2, -1.0, 1.0, Vj1, c->stream));
+        HIPCK(launch_bdot(n, k, 1, Vj1, vs, Vj1, hd2 + (size_t)(j + 1) * k, c->stream));
+        HIPCK(hipMemcpyAsync(h1.data(), hd1, (size_t)(j + 1) * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(hipMemcpyAsync(h2.data(), hd2, (size_t)(j + 2) * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(hipStreamSynchronize(c->stream));
+        jmax = j + 1;
+        for (int col = 0; col < k; ++col) {
+            f[col] = 0.0;
+            if (!active[col]) continue;
+            std::vector<double> h(j + 2);
+            for (int i = 0; i <= j; ++i) h[i] = h1[(size_t)i * k + col] + h2[(size_t)i * k + col];
+            const double hk1 = sqrt(h2[(size_t)(j + 1) * k + col]);
+            auto& C = cs[col];
+            auto& S = sn[col];
+            auto& gg = g[col];
+            for (int i = 0; i < j; ++i) {
+                const double a = C[i] * h[i] + S[i] * h[i + 1];
+                h[i + 1] = -S[i] * h[i] + C[i] * h[i + 1];
+                h[i] = a;
+            }
+            const double den = hypot(h[j], hk1);
+            C[j] = den > 0 ? h[j] / den : 1.0;
+            S[j] = den > 0 ? hk1 / den : 0.0;
+            h[j] = den;
+            gg[j + 1] = -S[j] * gg[j];
+            gg[j] = C[j] * gg[j];
+            for (int i = 0; i <= j; ++i) H[col][(size_t)i * m + j] = h[i];
+            its[col] = j + 1;
+            const bool done = fabs(gg[j + 1]) <= tol_rel * beta[col] || !(hk1 > 0) || !std::isfinite(hk1);
+            if (done) {
+                active[col] = 0;
+                --nact;
+            } else {
+                f[col] = 1.0 / hk1;
+            }
+        }
+        if (j + 1 < m && nact > 0) {
+            HIPCK(hipMemcpyAsync(fs, f.data(), k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCK(launch_colscale(n, k, fs, Vj1, c->stream));
+        }
+    }
+    // per column: y = R^{-1} g over its own steps; u = V y for all columns at once; D = M^{-1} u
+    std::vector<double> y((size_t)std::max(jmax, 1) * k, 0.0);
+    for (int col = 0; col < k; ++col) {
+        const int kc = its[col];
+        for (int i = kc - 1; i >= 0; --i) {
+            double v = g[col][i];
+            for (int t = i + 1; t < kc; ++t) v -= H[col][(size_t)i * m + t] * y[(size_t)t * k + col];
+            const double d = H[col][(size_t)i * m + i];
+            y[(size_t)i * k + col] = d != 0.0 ? v / d : 0.0;
+        }
+    }
+    if (jmax > 0) {
+        HIPCK(hipMemcpyAsync(hd1, y.data(), (size_t)jmax * k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCK(launch_bcomb(n, k, jmax, V, vs, hd1, 1.0, 0.0, c->gmb_w, c->stream));
+    } else {
+        HIPCK(launch_fill2d(0.0, c->gmb_w, k, n, k, c->stream));
+    }
+    HIPCK(hipStreamSynchronize(c->stream));   // the host vectors must outlive their copies
+    if (trans) return solve_t_into(c, c->gmb_w, k, k, D, k);
+    return solve_into(c, c->gmb_w, k, k, D, k);
 }
 
 int check_ctx(const genp_ctx* c) {
@@ -886,6 +1025,8 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
         c->trsv_chain = !(tv && strcmp(tv, "step") == 0);
         const char* dg = getenv("GENP_DIAG");   // "single": one workgroup per 256 diagonal block (any precision)
         c->diag_split = !(dg && strcmp(dg, "single") == 0);
+        const char* gb = getenv("GENP_GMRES");   // "columns": one GMRES cycle per column
+        c->gm_batched = !(gb && strcmp(gb, "columns") == 0);
         const char* lg = getenv("GENP_LP_GEMM");   // "lds": the precision form's product from FP64 operands
         c->lp_regs = !(lg && strcmp(lg, "lds") == 0);
     }
@@ -941,6 +1082,10 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->gm_z);
     hipFree(c->gm_r);
     hipFree(c->gm_h);
+    hipFree(c->gmb_V);
+    hipFree(c->gmb_w);
+    hipFree(c->gmb_z);
+    hipFree(c->gmb_h);
     hipFree(c->cest);
     for (int e = 0; e < EV_N; ++e) {
         if (c->ev0[e]) hipEventDestroy(c->ev0[e]);
@@ -1473,7 +1618,9 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
         prev = e;
         if (gm && cur_best) HIPCK(launch_copy2d(X, ldx, c->Xb, k, n, k, c->stream));
         if (e <= o.tol) break;
-        const bool budget = gm && o.max_inner > 0 && inner_total >= o.max_inner;
+        // (the many-column cycle needs one step per column; with fewer left the budget is spent)
+        const bool batched = k > 1 && k <= 64 && c->gm_batched;
+        const bool budget = gm && o.max_inner > 0 && o.max_inner - inner_total < (batched ? k : 1);
         if (it >= o.max_outer || budget || (gm && stall >= 3)) {
             status = (o.tol > 0) ? GENP_ENOCONV : GENP_OK;
             break;
@@ -1482,6 +1629,18 @@ int refine_core(genp_ctx* c, bool trans, const double* B, int64_t ldb, int k, do
             // Dx = M^{-1} R
             if (trans) CK(solve_t_into(c, c->R, k, k, c->Dx, k));
             else CK(solve_into(c, c->R, k, k, c->Dx, k));
+        } else if (batched) {
+            // all columns in one cycle; the budget counts every column's steps
+            int m = restart;
+            if (o.max_inner > 0) m = std::min(m, (o.max_inner - inner_total) / k);
+            if (m <= 0) {
+                HIPCK(launch_fill2d(0.0, c->Dx, k, n, k, c->stream));
+            } else {
+                CK(ensure_gmres_batched(c, m, k));
+                std::vector<int> its;
+                CK(gmres_cycle_batched(c, trans, m, k, c->R, c->Dx, rtol, its));
+                for (int v : its) inner_total += v;
+            }
         } else {
             for (int j = 0; j < k; ++j) {
                 int m = restart;

@@ -190,7 +190,74 @@ col_abs_sum_max_kernel(int n, int P, const double* __restrict__ part, unsigned l
     if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, s);
 }
 
+// Many columns at once (the k right-hand sides of one refinement step, k <= 64): V_i and W
+// are n x k row-major blocks, V_i = V + i * vs.  out[i * k + c] = sum_t V_i[t][c] W[t][c]:
+// one block per i, lane group c of 64, four row groups; fixed order.
+__global__ void __launch_bounds__(256)
+bdot_kernel(int n, int k, const double* __restrict__ V, long long vs, const double* __restrict__ W,
+            double* __restrict__ out) {
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const double* v = V + (long long)blockIdx.x * vs;
+    double s0 = 0.0, s1 = 0.0;
+    if (c < k) {
+        int t = rg;
+        for (; t + 4 < n; t += 8) {
+            s0 = fma(v[(long long)t * k + c], W[(long long)t * k + c], s0);
+            s1 = fma(v[(long long)(t + 4) * k + c], W[(long long)(t + 4) * k + c], s1);
+        }
+        for (; t < n; t += 4) s0 = fma(v[(long long)t * k + c], W[(long long)t * k + c], s0);
+    }
+    red[rg][c] = s0 + s1;
+    __syncthreads();
+    if (rg == 0 && c < k) out[(long long)blockIdx.x * k + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// W[t][c] = beta W[t][c] + sign sum_{i < j1} V_i[t][c] h[i * k + c] (beta = 0: W not read)
+__global__ void __launch_bounds__(256)
+bcomb_kernel(int n, int k, int j1, const double* __restrict__ V, long long vs, const double* __restrict__ h,
+             double sign, double beta, double* __restrict__ W) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * k) return;
+    const int c = (int)(e % k);
+    double s = 0.0;
+    for (int i = 0; i < j1; ++i) s = fma(V[(long long)i * vs + e], h[(long long)i * k + c], s);
+    W[e] = (beta != 0.0 ? beta * W[e] : 0.0) + sign * s;
+}
+
+// X[t][c] *= f[c] (column scaling of an n x k block); f[c] = 0 clears the column, NaN included
+__global__ void colscale_kernel(int n, int k, const double* __restrict__ f, double* __restrict__ X) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n * k) return;
+    const double fc = f[e % k];
+    X[e] = fc != 0.0 ? X[e] * fc : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_bdot(int n, int k, int j1, const double* V, long long vs, const double* W, double* out,
+                       hipStream_t s) {
+    if (j1 <= 0) return hipSuccess;
+    if (k < 1 || k > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bdot_kernel, dim3(j1), dim3(256), 0, s, n, k, V, vs, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bcomb(int n, int k, int j1, const double* V, long long vs, const double* h, double sign, double beta,
+                        double* W, hipStream_t s) {
+    const long long tot = (long long)n * k;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bcomb_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, k, j1, V, vs, h, sign,
+                       beta, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_colscale(int n, int k, const double* f, double* X, hipStream_t s) {
+    const long long tot = (long long)n * k;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(colscale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, k, f, X);
+    return hipGetLastError();
+}
 
 hipError_t launch_multidot(int n, int j1, const double* V, long long ldv, const double* w, double* out,
                            hipStream_t s) {

@@ -191,3 +191,60 @@ def test_refine_auto_luir_then_gmres(smax, expect_switch):
           f"oracle {eta_o.max():.2e} hist {['%.1e' % e for e in info['eta_hist']]}", flush=True)
     assert st == genp.OK and np.all(eta_o <= 1e-14)
     assert (info["inner_iters"] > 0) == expect_switch
+
+
+def _fp32_system(n, smax, k, seed):
+    w = wl.haar_logspaced(n, smax, wl.MULT_TOEPLITZ, nrhs=k, seed=seed)
+    s = genp.Solver(n, "f32", 128)
+    s.precondition(dev(w.A), p=dev(w.p))
+    assert s.factor() == 0
+    return w, s
+
+
+@pytest.mark.parametrize("k", [2, 7, 64])
+def test_refine_gmres_many_columns_matches_column_by_column(k, monkeypatch):
+    """GMRES-IR over k right-hand sides at once (one preconditioner solve and one product with A
+    per Arnoldi step for all columns) reaches the FP64 bar on every column, and its X agrees with
+    the one-cycle-per-column path's (GENP_GMRES=columns) to the accuracy both reach,
+    kappa_inf(A) eta."""
+    n = 400
+    w, s = _fp32_system(n, 1e6, k, 31)
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, max_iter=60, tol=1e-14, solver="gmres", restart=60)
+    info = s.info()
+    monkeypatch.setenv("GENP_GMRES", "columns")
+    w2, s2 = _fp32_system(n, 1e6, k, 31)
+    X2 = s2.solve(Bd)
+    st2, eta2 = s2.refine(Bd, X2, max_iter=60, tol=1e-14, solver="gmres", restart=60)
+    info2 = s2.info()
+    Xh, X2h = host(X), host(X2)
+    eta_o = og.backward_error_inf(w.A, Xh, w.B)
+    kappa = np.linalg.cond(w.A, np.inf)
+    diff = np.max(np.abs(Xh - X2h), axis=0) / np.max(np.abs(X2h), axis=0)
+    print(f"  k {k}: batched status {st} outer {info['iters']} inner {info['inner_iters']} eta {max(eta):.2e} "
+          f"(oracle {eta_o.max():.2e}); per column status {st2} outer {info2['iters']} inner "
+          f"{info2['inner_iters']}; max rel diff {diff.max():.2e} (kappa {kappa:.2e})", flush=True)
+    assert st == genp.OK and st2 == genp.OK
+    assert np.all(eta_o <= 1e-14)
+    assert same_eta(eta, eta_o)
+    assert np.all(diff <= 10 * kappa * 1e-14)
+
+
+def test_refine_gmres_many_columns_budget():
+    """The many-column cycle honours the inner-step budget summed over columns: 8 columns,
+    restart 8, budget 50 -> cycles of at most 50 // 8 = 6 steps per column, and the refinement
+    stops once fewer than 8 steps remain (ENOCONV, eta lowered)."""
+    n, k = 400, 8
+    w, s = _fp32_system(n, 1e6, k, 21)
+    Bd = dev(w.B)
+    X = s.solve(Bd)
+    st, eta = s.refine(Bd, X, max_iter=50, tol=1e-30, solver="gmres", restart=8, max_inner=50)
+    info = s.info()
+    eta_o = og.backward_error_inf(w.A, host(X), w.B)
+    print(f"  status {st} outer {info['iters']} inner {info['inner_iters']} eta {max(eta):.2e} "
+          f"hist {['%.1e' % e for e in info['eta_hist']]}", flush=True)
+    assert st == genp.ENOCONV
+    assert 0 < info["inner_iters"] <= 50 and info["inner_iters"] > 50 - k
+    assert same_eta(eta, eta_o)
+    assert max(eta) < info["eta_hist"][0]
