@@ -25,25 +25,47 @@
 namespace {
 
 constexpr int CIRC_MAXN2 = 8192;   // largest N = n / 2: N complex doubles = 128 KB of LDS
-constexpr int CIRC_THREADS = 512;
-constexpr int FFT_R = 4;           // radix-2 stages per pass over LDS
+constexpr int CIRC_THREADS = 1024;
+constexpr int FFT_R = 3;           // radix-2 stages per pass over LDS
 
 struct cplx {
     double re, im;
 };
+
+// LDS slot of element i.  A row of the 64 four-byte banks holds 16 complex doubles, so the
+// power-of-two strides of the radix-2 passes and of the bit-reversed load and store would put
+// every lane of a wave on the same banks; XOR-ing the low four index bits with bits 4..7 and
+// 9..12 spreads each of those access patterns over all 16 bank groups (a bijection: only bits
+// 0..3 change, as a function of the bits above them).
+__device__ inline int sw(int i) { return i ^ (((i >> 4) ^ (i >> 9)) & 15); }
 __device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 __device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
 __device__ inline cplx cconj(cplx a) { return {a.re, -a.im}; }
 __device__ inline cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
 
+// Twiddle factors W_N^e, 0 <= e < N/2, from two 64-entry tables in LDS: Tf[j] = W_N^j and
+// Tc[j] = W_N^(64 j), so W_N^e = Tc[e / 64] Tf[e mod 64] (one complex product; exact for e < 64,
+// where Tc[0] = 1).  Both tables hold the correctly rounded values of the twiddle table in
+// global memory.
+struct Twid {
+    const double2* Tf;
+    const double2* Tc;
+    __device__ inline cplx operator()(int e) const {
+        const double2 a = Tc[e >> 6], b = Tf[e & 63];
+        return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    }
+};
+
 // r consecutive radix-2 stages (r <= 4) of a length-N FFT in place in L.  Forward (decimation
 // in time): stages of halves q, 2q, .., q 2^(r-1), q = 2^qlog; inverse (decimation in
 // frequency, conjugate twiddles): stages of halves q 2^(r-1), .., 2q, q.  Each thread owns the
 // 2^r elements base + m q of aligned blocks of 2^r q (registers: r is a template parameter, so
-// every index into v is a constant).
+// every index into v is a constant).  In the stage of half h the pair (m, m + 2^sb) takes the
+// twiddle of its lower element's offset p = pos + j q in its block of 2h, j = m mod 2^sb, i.e.
+// W_N^(p N / 2h): 2^sb distinct factors per stage, computed once each.
 template <bool INV, int RL>
-__device__ inline void fft_pass_r(cplx* L, int N, int qlog, int tid, const double2* __restrict__ tw) {
+__device__ inline void fft_pass_r(cplx* L, int N, int qlog, int tid, const Twid& W) {
     constexpr int R = 1 << RL;
     const int q = 1 << qlog;
     for (int g = tid; g < (N >> RL); g += CIRC_THREADS) {
@@ -51,41 +73,53 @@ __device__ inline void fft_pass_r(cplx* L, int N, int qlog, int tid, const doubl
         const int base = (g - pos) * R + pos;
         cplx v[R];
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[m] = L[base + m * q];
+        for (int m = 0; m < R; ++m) v[m] = L[sw(base + m * q)];
 #pragma unroll
         for (int t = 0; t < RL; ++t) {
             const int sb = INV ? RL - 1 - t : t;   // pairs m, m + 2^sb (compile-time after unrolling)
             const int h = q << sb;                 // the stage's half
             const int step = N / (2 * h);
+            cplx w[1 << sb];
+#pragma unroll
+            for (int j = 0; j < (1 << sb); ++j) {
+                const cplx x = W((pos + j * q) * step);
+                w[j] = INV ? cconj(x) : x;
+            }
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 if (m & (1 << sb)) continue;
                 const int mm = m + (1 << sb);
-                const int p = pos + (m & ((1 << sb) - 1)) * q;
-                const double2 w2 = tw[p * step];
+                const cplx wm = w[m & ((1 << sb) - 1)];
                 if (!INV) {
-                    const cplx tt = cmul({w2.x, w2.y}, v[mm]);
+                    const cplx tt = cmul(wm, v[mm]);
                     const cplx a = v[m];
                     v[m] = cadd(a, tt);
                     v[mm] = csub(a, tt);
                 } else {
                     const cplx a = v[m], c = v[mm];
                     v[m] = cadd(a, c);
-                    v[mm] = cmul(csub(a, c), {w2.x, -w2.y});
+                    v[mm] = cmul(csub(a, c), wm);
                 }
             }
         }
 #pragma unroll
-        for (int m = 0; m < R; ++m) L[base + m * q] = v[m];
+        for (int m = 0; m < R; ++m) L[sw(base + m * q)] = v[m];
     }
 }
 
+// (only the stage counts up to FFT_R are instantiated: the largest sets the register budget)
 template <bool INV>
-__device__ inline void fft_pass(cplx* L, int N, int qlog, int r, int tid, const double2* __restrict__ tw) {
-    if (r == 4) fft_pass_r<INV, 4>(L, N, qlog, tid, tw);
-    else if (r == 3) fft_pass_r<INV, 3>(L, N, qlog, tid, tw);
-    else if (r == 2) fft_pass_r<INV, 2>(L, N, qlog, tid, tw);
-    else fft_pass_r<INV, 1>(L, N, qlog, tid, tw);
+__device__ inline void fft_pass(cplx* L, int N, int qlog, int r, int tid, const Twid& W) {
+    if constexpr (FFT_R >= 4) {
+        if (r == 4) return fft_pass_r<INV, 4>(L, N, qlog, tid, W);
+    }
+    if constexpr (FFT_R >= 3) {
+        if (r == 3) return fft_pass_r<INV, 3>(L, N, qlog, tid, W);
+    }
+    if constexpr (FFT_R >= 2) {
+        if (r == 2) return fft_pass_r<INV, 2>(L, N, qlog, tid, W);
+    }
+    fft_pass_r<INV, 1>(L, N, qlog, tid, W);
 }
 
 // MODE 0: y = alpha * (x correlated / convolved with c) + beta * yin.
@@ -99,14 +133,31 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
             double alpha, double beta, const double* yin, long long syi, long long byi, TO* y, long long sy,
             long long by, double2* __restrict__ spec_out) {
     __shared__ cplx L[CIRC_MAXN2];
+    __shared__ double2 Tf[64], Tc[64];
     const int N = n >> 1;
     const int tid = threadIdx.x;
     const long long b = blockIdx.x;
     const double* xv = x + b * bx;
-    // packed, bit-reversed load
-    for (int k = tid; k < N; k += CIRC_THREADS) {
-        const int r = (int)(__brev((unsigned)k) >> (32 - logN));
-        L[r] = {xv[(2LL * k) * sx], xv[(2LL * k + 1) * sx]};
+    // the twiddle tables (entries past N/2 are never used)
+    if (tid < 64) {
+        Tf[tid] = tid < (N >> 1) ? tw[tid] : make_double2(1.0, 0.0);
+        Tc[tid] = 64 * tid < (N >> 1) ? tw[64 * tid] : make_double2(1.0, 0.0);
+    }
+    const Twid W{Tf, Tc};
+    // packed, bit-reversed load: every global load issued before the first LDS store
+    {
+        constexpr int KL = CIRC_MAXN2 / CIRC_THREADS;
+        cplx ld[KL];
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int k = tid + i * CIRC_THREADS;
+            if (k < N) ld[i] = {xv[(2LL * k) * sx], xv[(2LL * k + 1) * sx]};
+        }
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int k = tid + i * CIRC_THREADS;
+            if (k < N) L[sw((int)(__brev((unsigned)k) >> (32 - logN)))] = ld[i];
+        }
     }
     __syncthreads();
     // forward FFT of length N, decimation in time: the radix-2 stages of halves 1, 2, .., N/2
@@ -118,7 +169,7 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
     // LDS passes and barriers.
     for (int s0 = 0; s0 < logN;) {
         const int r = min(FFT_R, logN - s0);
-        fft_pass<false>(L, N, s0, r, tid, tw);
+        fft_pass<false>(L, N, s0, r, tid, W);
         __syncthreads();
         s0 += r;
     }
@@ -130,9 +181,13 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
         upd_max(v);
         upd_min(v);
     };
-    for (int f = tid; f <= (N >> 1); f += CIRC_THREADS) {
+    constexpr int KS = CIRC_MAXN2 / 2 / CIRC_THREADS + 1;   // pairs per thread at most
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+        const int f = tid + i * CIRC_THREADS;
+        if (f > (N >> 1)) continue;
         if (f == 0) {
-            const cplx z0 = L[0];
+            const cplx z0 = L[sw(0)];
             const double x0 = z0.re + z0.im, xN = z0.re - z0.im;   // X[0], X[N] (real)
             if (MODE == 1) {
                 spec_out[0] = make_double2(x0, 0.0);
@@ -145,11 +200,11 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
             const cplx rN = cmul({xN, 0.0}, CONJ ? cconj({spec[N].x, spec[N].y}) : cplx{spec[N].x, spec[N].y});
             // E'[0] = (R[0] + conj R[N]) / 2, O'[0] = (R[0] - conj R[N]) / 2
             const cplx e = cscale(cadd(r0, cconj(rN)), 0.5), o = cscale(csub(r0, cconj(rN)), 0.5);
-            L[0] = {e.re - o.im, e.im + o.re};
+            L[sw(0)] = {e.re - o.im, e.im + o.re};
             continue;
         }
         const int g = N - f;
-        const cplx zf = L[f], zg = L[g];
+        const cplx zf = L[sw(f)], zg = L[sw(g)];
         const double2 wf2 = wp[f], wg2 = wp[g];
         const cplx wf = {wf2.x, wf2.y}, wg = {wg2.x, wg2.y};
         // E = (Z[f] + conj Z[N-f]) / 2; O = (Z[f] - conj Z[N-f]) / (2i) = -i (Z[f] - conj Z[N-f]) / 2
@@ -172,8 +227,8 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
         const cplx of2 = cmul(cscale(csub(rf, cconj(rg)), 0.5), cconj(wf));
         const cplx eg2 = cscale(cadd(rg, cconj(rf)), 0.5);
         const cplx og2 = cmul(cscale(csub(rg, cconj(rf)), 0.5), cconj(wg));
-        L[f] = {ef2.re - of2.im, ef2.im + of2.re};
-        if (g != f) L[g] = {eg2.re - og2.im, eg2.im + og2.re};
+        L[sw(f)] = {ef2.re - of2.im, ef2.im + of2.re};
+        if (g != f) L[sw(g)] = {eg2.re - og2.im, eg2.im + og2.re};
     }
     if constexpr (MODE == 1) {
         // block reduction of the extreme moduli: within each wave, then across the 8 waves
@@ -204,7 +259,7 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
     // q: elements base + m q, stage t pairs m and m + 2^(r-1-t))
     for (int sh = logN - 1; sh >= 0;) {
         const int r = min(FFT_R, sh + 1);
-        fft_pass<true>(L, N, sh - r + 1, r, tid, tw);
+        fft_pass<true>(L, N, sh - r + 1, r, tid, W);
         __syncthreads();
         sh -= r;
     }
@@ -213,7 +268,7 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
     const double* yiv = (beta != 0.0) ? yin + b * byi : nullptr;
     for (int k = tid; k < N; k += CIRC_THREADS) {
         const int r = (int)(__brev((unsigned)k) >> (32 - logN));
-        const cplx z = L[r];
+        const cplx z = L[sw(r)];
         double v0 = s * z.re, v1 = s * z.im;
         if (yiv) {
             v0 = fma(beta, yiv[(2LL * k) * syi], v0);
