@@ -472,13 +472,14 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     }
     __syncthreads();
     // wave 0's row of the diagonal block and its pivot's reciprocal, read before the waits
-    // so that only the substitution itself follows the last one
+    // so that only the substitution itself follows the last one; the row's entries that do
+    // not update this lane (the diagonal, and the solved side) are zeroed
     double trow[BS];
     double rd = 1.0;
     if (wave == 0) {
         if (!UNIT) rd = 1.0 / Td[lane][lane];
 #pragma unroll
-        for (int i = 0; i < BS; ++i) trow[i] = Td[lane][i];
+        for (int i = 0; i < BS; ++i) trow[i] = (LOWER ? lane > i : lane < i) ? Td[lane][i] : 0.0;
     }
     const int ri = tid >> 2, part = tid & 3;   // row and column quarter of the block products
     double acc[NR];
@@ -530,19 +531,22 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         double z[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) z[c] = zs[lane][c];
+        // step i: x_i = z_i / T_ii formed on every lane (lane i's is the one broadcast), then
+        // z_j -= T_ji x_i on the lanes still to solve (the others' T_ji are zero); one product,
+        // one broadcast and one FMA on the chain per step.  Lane j's z_j is final after its
+        // own step, so its x_j is the same product once more.
 #pragma unroll
         for (int u = 0; u < BS; ++u) {
             const int i = LOWER ? u : BS - 1 - u;
-            const double ri_ = UNIT ? 1.0 : readlane_d(rd, i);
-            const double m = trow[i];
-            const bool upd = LOWER ? lane > i : lane < i;
-            const bool own = lane == i;
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
-                const double xi = readlane_d(z[c], i) * ri_;
-                const double nv = fma(-m, xi, z[c]);
-                z[c] = own ? xi : (upd ? nv : z[c]);
+                const double xi = readlane_d(UNIT ? z[c] : z[c] * rd, i);
+                z[c] = fma(-trow[i], xi, z[c]);
             }
+        }
+        if (!UNIT) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) z[c] *= rd;
         }
 #pragma unroll
         for (int c = 0; c < NR; ++c)
