@@ -233,9 +233,10 @@ hipError_t launch_convert_f32_f64(const float* src, long long lds, double* dst, 
 hipError_t launch_multidot(int n, int j1, const double* V, long long ldv, const double* w, double* out,
                            hipStream_t s);
 // k columns at once (k <= 64), V_i = V + i * vs and W n x k row-major blocks:
-// out[i * k + c] = V_i(:, c) . W(:, c) for i < j1
+// out[i * k + c] = V_i(:, c) . W(:, c) for i < j1; part: device scratch of part_cap doubles,
+// at least (j1 + 1024) * k (fixed-order reduction over row chunks)
 hipError_t launch_bdot(int n, int k, int j1, const double* V, long long vs, const double* W, double* out,
-                       hipStream_t s);
+                       double* part, long long part_cap, hipStream_t s);
 // W = beta W + sign sum_{i < j1} V_i diag(h[i * k .. i * k + k - 1])
 hipError_t launch_bcomb(int n, int k, int j1, const double* V, long long vs, const double* h, double sign, double beta,
                         double* W, hipStream_t s);

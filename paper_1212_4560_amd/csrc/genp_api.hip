@@ -99,6 +99,7 @@ struct genp_ctx {
     double* gmb_w = nullptr;
     double* gmb_z = nullptr;
     double* gmb_h = nullptr;
+    double* gmb_part = nullptr;        // row-chunk partial dots: (GENP_GMRES_MAX_RESTART + 2 + 1024) x 64
     // 1-norm estimator: four n_pad vectors, then 8 scalars
     double* cest = nullptr;
     double anorm1 = -1.0;              // ||A||_1 (= ||A^T||_inf), < 0 until the adjoint needs it
@@ -460,12 +461,15 @@ int ensure_gmres(genp_ctx* c, int m) {
     return GENP_OK;
 }
 
+constexpr long long GMB_PART = (long long)(GENP_GMRES_MAX_RESTART + 2 + 1024) * 64;
+
 int ensure_gmres_batched(genp_ctx* c, int m, int k) {
     const size_t np = (size_t)c->n_pad;
     if (!c->gmb_w) {
         if (hipMalloc(&c->gmb_w, np * 64 * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->gmb_z, np * 64 * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->gmb_h, ((size_t)2 * (GENP_GMRES_MAX_RESTART + 2) * 64 + 64) * sizeof(double)) != hipSuccess)
+            hipMalloc(&c->gmb_h, ((size_t)2 * (GENP_GMRES_MAX_RESTART + 2) * 64 + 64) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->gmb_part, (size_t)GMB_PART * sizeof(double)) != hipSuccess)
             return GENP_ENOMEM;
     }
     const size_t need = (size_t)(m + 1) * np * k;
@@ -600,7 +604,7 @@ int gmres_cycle_batched(genp_ctx* c, bool trans, int m, int k, const double* R, 
     double* fs = hd2 + (size_t)(m + 2) * k;            // k column scales
     its.assign(k, 0);
     HIPCK(hipMemcpyAsync(V, R, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    HIPCK(launch_bdot(n, k, 1, V, vs, V, hd1, c->stream));
+    HIPCK(launch_bdot(n, k, 1, V, vs, V, hd1, c->gmb_part, GMB_PART, c->stream));
     std::vector<double> beta(k), f(k), h1((size_t)(m + 2) * k), h2((size_t)(m + 2) * k);
     HIPCK(hipMemcpyAsync(beta.data(), hd1, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
@@ -629,11 +633,11 @@ int gmres_cycle_batched(genp_ctx* c, bool trans, int m, int k, const double* R, 
         if (trans) CK(solve_t_into(c, Vj, k, k, c->gmb_z, k));
         else CK(solve_into(c, Vj, k, k, c->gmb_z, k));
         CK(skinny(c, n, n, k, 1.0, c->A, c->lda, trans ? OP_T : OP_N, 0, c->gmb_z, k, 0.0, nullptr, k, Vj1, k));
-        HIPCK(launch_bdot(n, k, j + 1, V, vs, Vj1, hd1, c->stream));
+        HIPCK(launch_bdot(n, k, j + 1, V, vs, Vj1, hd1, c->gmb_part, GMB_PART, c->stream));
         HIPCK(launch_bcomb(n, k, j + 1, V, vs, hd1, -1.0, 1.0, Vj1, c->stream));
-        HIPCK(launch_bdot(n, k, j + 1, V, vs, Vj1, hd2, c->stream));
+        HIPCK(launch_bdot(n, k, j + 1, V, vs, Vj1, hd2, c->gmb_part, GMB_PART, c->stream));
         HIPCK(launch_bcomb(n, k, j + 1, V, vs, hd2, -1.0, 1.0, Vj1, c->stream));
-        HIPCK(launch_bdot(n, k, 1, Vj1, vs, Vj1, hd2 + (size_t)(j + 1) * k, c->stream));
+        HIPCK(launch_bdot(n, k, 1, Vj1, vs, Vj1, hd2 + (size_t)(j + 1) * k, c->gmb_part, GMB_PART, c->stream));
         HIPCK(hipMemcpyAsync(h1.data(), hd1, (size_t)(j + 1) * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCK(hipMemcpyAsync(h2.data(), hd2, (size_t)(j + 2) * k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCK(hipStreamSynchronize(c->stream));
@@ -1086,6 +1090,7 @@ int genp_destroy(genp_ctx* c) {
     hipFree(c->gmb_w);
     hipFree(c->gmb_z);
     hipFree(c->gmb_h);
+    hipFree(c->gmb_part);
     hipFree(c->cest);
     for (int e = 0; e < EV_N; ++e) {
         if (c->ev0[e]) hipEventDestroy(c->ev0[e]);

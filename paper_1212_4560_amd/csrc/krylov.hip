@@ -191,26 +191,40 @@ col_abs_sum_max_kernel(int n, int P, const double* __restrict__ part, unsigned l
 }
 
 // Many columns at once (the k right-hand sides of one refinement step, k <= 64): V_i and W
-// are n x k row-major blocks, V_i = V + i * vs.  out[i * k + c] = sum_t V_i[t][c] W[t][c]:
-// one block per i, lane group c of 64, four row groups; fixed order.
+// are n x k row-major blocks, V_i = V + i * vs.  out[i * k + c] = sum_t V_i[t][c] W[t][c] in
+// two passes with a fixed order: workgroup (p, i) sums the rows of chunk p (lane group c of
+// 64, four row groups, two partial sums each) into part[(i P + p) k + c], then the P chunk
+// sums are added in order p = 0 .. P-1.  Chunks spread a step's few basis blocks over the
+// whole GPU.
 __global__ void __launch_bounds__(256)
-bdot_kernel(int n, int k, const double* __restrict__ V, long long vs, const double* __restrict__ W,
-            double* __restrict__ out) {
+bdot_part_kernel(int n, int k, int rc, const double* __restrict__ V, long long vs, const double* __restrict__ W,
+                 double* __restrict__ part) {
     __shared__ double red[4][64];
     const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-    const double* v = V + (long long)blockIdx.x * vs;
+    const int p = blockIdx.x, P = gridDim.x, i = blockIdx.y;
+    const double* v = V + (long long)i * vs;
+    const int r0 = p * rc, r1 = min(n, r0 + rc);
     double s0 = 0.0, s1 = 0.0;
     if (c < k) {
-        int t = rg;
-        for (; t + 4 < n; t += 8) {
+        int t = r0 + rg;
+        for (; t + 4 < r1; t += 8) {
             s0 = fma(v[(long long)t * k + c], W[(long long)t * k + c], s0);
             s1 = fma(v[(long long)(t + 4) * k + c], W[(long long)(t + 4) * k + c], s1);
         }
-        for (; t < n; t += 4) s0 = fma(v[(long long)t * k + c], W[(long long)t * k + c], s0);
+        for (; t < r1; t += 4) s0 = fma(v[(long long)t * k + c], W[(long long)t * k + c], s0);
     }
     red[rg][c] = s0 + s1;
     __syncthreads();
-    if (rg == 0 && c < k) out[(long long)blockIdx.x * k + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    if (rg == 0 && c < k) part[((long long)i * P + p) * k + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+__global__ void bdot_sum_kernel(int k, int P, int j1, const double* __restrict__ part, double* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= j1 * k) return;
+    const int i = e / k, c = e % k;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += part[((long long)i * P + p) * k + c];
+    out[e] = s;
 }
 
 // W[t][c] = beta W[t][c] + sign sum_{i < j1} V_i[t][c] h[i * k + c] (beta = 0: W not read)
@@ -235,11 +249,21 @@ __global__ void colscale_kernel(int n, int k, const double* __restrict__ f, doub
 
 }  // namespace
 
+int bdot_chunks(int n, int j1) {
+    // about 1024 workgroups in all, chunks of 256 rows at least
+    const int by_rows = std::max(1, (n + 255) / 256);
+    return std::max(1, std::min(by_rows, (1024 + j1 - 1) / j1));
+}
+
 hipError_t launch_bdot(int n, int k, int j1, const double* V, long long vs, const double* W, double* out,
-                       hipStream_t s) {
+                       double* part, long long part_cap, hipStream_t s) {
     if (j1 <= 0) return hipSuccess;
-    if (k < 1 || k > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(bdot_kernel, dim3(j1), dim3(256), 0, s, n, k, V, vs, W, out);
+    if (k < 1 || k > 64 || n <= 0) return hipErrorInvalidValue;
+    const int P = bdot_chunks(n, j1);
+    if ((long long)j1 * P * k > part_cap) return hipErrorInvalidValue;
+    const int rc = (n + P - 1) / P;
+    hipLaunchKernelGGL(bdot_part_kernel, dim3(P, j1), dim3(256), 0, s, n, k, rc, V, vs, W, part);
+    hipLaunchKernelGGL(bdot_sum_kernel, dim3((j1 * k + 255) / 256), dim3(256), 0, s, k, P, j1, part, out);
     return hipGetLastError();
 }
 

@@ -566,10 +566,11 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
 // block p in solve order, T(t, p) is staged through LDS (prefetched one block ahead through
 // registers) and the values of X_p are polled straight into B operands, one 16-row tile of p
 // at a time in the order p solves its tiles: the product with a block overlaps the end of
-// that block's own solve.  Then the diagonal block is solved in place in the accumulators,
-// tile by tile (substitution with a cross-lane broadcast of each solved row, forward or
-// backward, then the MFMA update of the tiles still to be solved), and each tile is
-// published as soon as it is final.
+// that block's own solve.  Then the diagonal block is solved tile by tile: the tile goes
+// through a per-wave LDS slab to lanes 0..15, each of which substitutes one column of it in
+// registers (forward or backward, pivots applied as reciprocals; no cross-lane traffic inside
+// the substitution), and back into the accumulators; then the MFMA update of the tiles still
+// to be solved.  Each tile is published as soon as it is final.
 template <bool LOWER, bool UNIT, bool TT, typename TF>
 __global__ void __launch_bounds__(256)
 trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, long long ldx, int ncols,
@@ -577,6 +578,8 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     constexpr int BS = 64;
     __shared__ double Td[BS][BS + 1];
     __shared__ double To[2][BS][BS + 1];
+    __shared__ double Ys[4][16][17];   // per wave: the 16 x 16 tile being substituted
+    __shared__ double rdg[BS];         // reciprocals of the diagonal block's pivots
     __shared__ int s_q;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
@@ -625,27 +628,36 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         const int p = order(s_);
         const int buf = s_ & 1;
         if (s_ + 1 < q) load_blk(t, order(s_ + 1), vn);
+        // all sixteen values of this lane for block p requested at once (one round trip when p
+        // is long solved); a tile's values still unset are polled again before its products
+        const unsigned long long* srcp = pub + (long long)p * BS * 64 + (long long)lq * 64 + cc;
+        unsigned long long pv[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                pv[j][u] = cok ? __hip_atomic_load(srcp + (16 * tord(j) + 4 * u) * 64, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : 0ull;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int pb = tord(j);
+            unsigned it = 0;
+            while (pv[j][0] == kUnset || pv[j][1] == kUnset || pv[j][2] == kUnset || pv[j][3] == kUnset) {
+                if (++it > spin_limit) {
+                    __hip_atomic_fetch_or(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (pv[j][u] == kUnset)
+                        pv[j][u] = __hip_atomic_load(srcp + (16 * pb + 4 * u) * 64, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            }
             double bq[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                bq[u] = 0.0;
-                if (cok) {
-                    unsigned long long* src = pub + ((long long)p * BS + 16 * pb + 4 * u + lq) * 64 + cc;
-                    unsigned long long v;
-                    unsigned it = 0;
-                    while ((v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kUnset) {
-                        if (++it > spin_limit) {
-                            __hip_atomic_fetch_or(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    bq[u] = __longlong_as_double((long long)v);
-                }
-            }
+            for (int u = 0; u < 4; ++u) bq[u] = cok ? __longlong_as_double((long long)pv[j][u]) : 0.0;
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -656,23 +668,34 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         if (s_ + 1 < q) store_blk(To[buf ^ 1], vn);
         __syncthreads();
     }
+    if (!UNIT) {
+        if (tid < BS) rdg[tid] = 1.0 / Td[tid][tid];
+        __syncthreads();
+    }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int b = tord(jb);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int sr = LOWER ? j : 15 - j;
-            double v = acc[b][sr >> 2];
-            if (!UNIT) v = v / Td[16 * b + sr][16 * b + sr];
-            const double ys = __shfl(v, (sr & 3) * 16 + lr, 64);
+        for (int r = 0; r < 4; ++r) Ys[w][lq + 4 * r][lr] = acc[b][r];
+        __syncthreads();
+        if (lq == 0) {
+            double y[16];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = lq + 4 * r;
-                const double nv = fma(-Td[16 * b + i][16 * b + sr], ys, acc[b][r]);
-                const bool upd = LOWER ? i > sr : i < sr;
-                acc[b][r] = upd ? nv : ((i == sr) ? ys : acc[b][r]);
+            for (int i = 0; i < 16; ++i) y[i] = Ys[w][i][lr];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int j = LOWER ? jj : 15 - jj;
+                if (!UNIT) y[j] *= rdg[16 * b + j];
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (LOWER ? i > j : i < j) y[i] = fma(-Td[16 * b + i][16 * b + j], y[j], y[i]);
             }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Ys[w][i][lr] = y[i];
         }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[b][r] = Ys[w][lq + 4 * r][lr];
         if (cok) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
