@@ -38,6 +38,18 @@ struct cplx {
 // 9..12 spreads each of those access patterns over all 16 bank groups (a bijection: only bits
 // 0..3 change, as a function of the bits above them).
 __device__ inline int sw(int i) { return i ^ (((i >> 4) ^ (i >> 9)) & 15); }
+
+__device__ inline double nanmax_d(double m, double a) { return (a > m || a != a) ? a : m; }
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max_nan(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = nanmax_d(v, __shfl_xor(v, o, 64));
+    return v;
+}
 __device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 __device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
@@ -131,9 +143,10 @@ __global__ void __launch_bounds__(CIRC_THREADS)
 circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
             const double2* __restrict__ spec, const double2* __restrict__ tw, const double2* __restrict__ wp,
             double alpha, double beta, const double* yin, long long syi, long long byi, TO* y, long long sy,
-            long long by, double2* __restrict__ spec_out) {
+            long long by, double2* __restrict__ spec_out, unsigned long long* xsum_max, unsigned long long* ymax) {
     __shared__ cplx L[CIRC_MAXN2];
     __shared__ double2 Tf[64], Tc[64];
+    __shared__ double red[CIRC_THREADS / 64];
     const int N = n >> 1;
     const int tid = threadIdx.x;
     const long long b = blockIdx.x;
@@ -148,18 +161,45 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
     {
         constexpr int KL = CIRC_MAXN2 / CIRC_THREADS;
         cplx ld[KL];
+        if (sx == 1 && ((uintptr_t)xv & 15) == 0) {
+            // contiguous vector: one 16-byte load per complex element
+            const double2* x2 = reinterpret_cast<const double2*>(xv);
 #pragma unroll
-        for (int i = 0; i < KL; ++i) {
-            const int k = tid + i * CIRC_THREADS;
-            if (k < N) ld[i] = {xv[(2LL * k) * sx], xv[(2LL * k + 1) * sx]};
+            for (int i = 0; i < KL; ++i) {
+                const int k = tid + i * CIRC_THREADS;
+                if (k < N) {
+                    const double2 v = x2[k];
+                    ld[i] = {v.x, v.y};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < KL; ++i) {
+                const int k = tid + i * CIRC_THREADS;
+                if (k < N) ld[i] = {xv[(2LL * k) * sx], xv[(2LL * k + 1) * sx]};
+            }
         }
 #pragma unroll
         for (int i = 0; i < KL; ++i) {
             const int k = tid + i * CIRC_THREADS;
             if (k < N) L[sw((int)(__brev((unsigned)k) >> (32 - logN)))] = ld[i];
         }
+        if (MODE == 0 && xsum_max) {
+            // sum of |x| over the vector: per thread, per wave, then the waves in order
+            double a = 0.0;
+#pragma unroll
+            for (int i = 0; i < KL; ++i)
+                if (tid + i * CIRC_THREADS < N) a += fabs(ld[i].re) + fabs(ld[i].im);
+            a = wave_sum_d(a);
+            if ((tid & 63) == 0) red[tid >> 6] = a;
+        }
     }
     __syncthreads();
+    if (MODE == 0 && xsum_max && tid == 0) {
+        double a = 0.0;
+        for (int w = 0; w < CIRC_THREADS / 64; ++w) a += red[w];
+        atomic_max_nonneg(xsum_max, a);
+    }
     // forward FFT of length N, decimation in time: the radix-2 stages of halves 1, 2, .., N/2
     // taken FFT_R at a time.  In a pass whose first stage has half q, a thread owns the 2^r
     // elements base + m q of one aligned block of 2^r q and runs the pass's stages on them in
@@ -237,17 +277,17 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
             upd_max(a);
             upd_min(b);
         }
-        __shared__ double red[2][CIRC_THREADS / 64];
+        __shared__ double red2[2][CIRC_THREADS / 64];
         const int wv = tid >> 6;
         if ((tid & 63) == 0) {
-            red[0][wv] = smax;
-            red[1][wv] = smin;
+            red2[0][wv] = smax;
+            red2[1][wv] = smin;
         }
         __syncthreads();
         if (tid == 0) {
             for (int w = 0; w < CIRC_THREADS / 64; ++w) {
-                upd_max(red[0][w]);
-                upd_min(red[1][w]);
+                upd_max(red2[0][w]);
+                upd_min(red2[1][w]);
             }
             spec_out[N + 1] = make_double2(smax, smin);
         }
@@ -266,6 +306,9 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
     const double s = alpha / (double)N;
     TO* yv = y + b * by;
     const double* yiv = (beta != 0.0) ? yin + b * byi : nullptr;
+    // contiguous output: the pair of results as one store (16 bytes, or 8 for FP32)
+    const bool pair = sy == 1 && ((uintptr_t)yv % (2 * sizeof(TO))) == 0;
+    double ym = 0.0;   // max |y| as stored (a NaN sticks)
     for (int k = tid; k < N; k += CIRC_THREADS) {
         const int r = (int)(__brev((unsigned)k) >> (32 - logN));
         const cplx z = L[sw(r)];
@@ -274,8 +317,25 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
             v0 = fma(beta, yiv[(2LL * k) * syi], v0);
             v1 = fma(beta, yiv[(2LL * k + 1) * syi], v1);
         }
-        yv[(2LL * k) * sy] = (TO)v0;
-        yv[(2LL * k + 1) * sy] = (TO)v1;
+        if (pair) {
+            if constexpr (sizeof(TO) == 8) reinterpret_cast<double2*>(yv)[k] = make_double2(v0, v1);
+            else reinterpret_cast<float2*>(yv)[k] = make_float2((float)v0, (float)v1);
+        } else {
+            yv[(2LL * k) * sy] = (TO)v0;
+            yv[(2LL * k + 1) * sy] = (TO)v1;
+        }
+        if (ymax) ym = nanmax_d(nanmax_d(ym, fabs((double)(TO)v0)), fabs((double)(TO)v1));
+    }
+    if (ymax) {
+        // red was last read before the first FFT pass's barrier: free to reuse
+        ym = wave_max_nan(ym);
+        if ((tid & 63) == 0) red[tid >> 6] = ym;
+        __syncthreads();
+        if (tid == 0) {
+            double m = 0.0;
+            for (int w = 0; w < CIRC_THREADS / 64; ++w) m = nanmax_d(m, red[w]);
+            atomic_max_nonneg(ymax, m);
+        }
     }
 }
 
@@ -296,20 +356,20 @@ hipError_t launch_circ_spectrum(int n, const double* c, const double2* tw, const
     if (!circ_size_ok(n)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((circ_kernel<1, false, double>), dim3(1), dim3(CIRC_THREADS), 0, s, n, ilog2(n / 2), c, 1LL,
                        0LL, (const double2*)nullptr, tw, wp, 1.0, 0.0, (const double*)nullptr, 0LL, 0LL,
-                       (double*)nullptr, 0LL, 0LL, spec);
+                       (double*)nullptr, 0LL, 0LL, spec, (unsigned long long*)nullptr, (unsigned long long*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_circ_apply(int n, int nvec, int conj, const double* x, long long sx, long long bx, const double2* spec,
                              const double2* tw, const double2* wp, double alpha, double beta, const double* yin,
                              long long syi, long long byi, void* y, int y_f32, long long sy, long long by,
-                             hipStream_t s) {
+                             hipStream_t s, unsigned long long* xsum_max, unsigned long long* ymax) {
     if (!circ_size_ok(n)) return hipErrorInvalidValue;
     if (nvec <= 0) return hipSuccess;
     const int lg = ilog2(n / 2);
 #define GENP_CIRC_GO(CJ, TO)                                                                                   \
     hipLaunchKernelGGL((circ_kernel<0, CJ, TO>), dim3(nvec), dim3(CIRC_THREADS), 0, s, n, lg, x, sx, bx, spec, \
-                       tw, wp, alpha, beta, yin, syi, byi, (TO*)y, sy, by, (double2*)nullptr)
+                       tw, wp, alpha, beta, yin, syi, byi, (TO*)y, sy, by, (double2*)nullptr, xsum_max, ymax)
     if (conj) {
         if (y_f32) GENP_CIRC_GO(true, float);
         else GENP_CIRC_GO(true, double);

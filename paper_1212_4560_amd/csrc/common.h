@@ -193,11 +193,14 @@ hipError_t launch_circ_spectrum(int n, const double* c, const double2* tw, const
                                 hipStream_t s);
 // y_b = alpha * op(x_b) + beta * yin_b for nvec vectors b: element t of vector b is at
 // x[b * bx + t * sx] (likewise y, yin); op = correlation with c (conj = 1: x^T G, G^T x)
-// or convolution (conj = 0: G x).  y is FP32 when y_f32.
+// or convolution (conj = 0: G x).  y is FP32 when y_f32.  Optional fused reductions (device
+// slots for atomic_max_nonneg, already initialized): xsum_max <- max_b sum_t |x_b[t]| (the
+// infinity norm of A when the vectors are its rows), ymax <- max |y| as stored.
 hipError_t launch_circ_apply(int n, int nvec, int conj, const double* x, long long sx, long long bx, const double2* spec,
                              const double2* tw, const double2* wp, double alpha, double beta, const double* yin,
                              long long syi, long long byi, void* y, int y_f32, long long sy, long long by,
-                             hipStream_t s);
+                             hipStream_t s, unsigned long long* xsum_max = nullptr,
+                             unsigned long long* ymax = nullptr);
 // The two block solves of an elimination step in one launch: A12 <- L11^{-1} A12
 // (nb x m) and A21 <- A21 U11^{-1} (m x nb), with L11 \ U11 the factored diagonal
 // block D.  nb in {64, 128, 256}; f32: D, A12 and A21 are FP32 (arithmetic in FP64).

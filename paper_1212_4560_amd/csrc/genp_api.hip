@@ -749,7 +749,9 @@ int set_mult(genp_ctx* c, Mult& m, int kind, const double* G, int64_t ldg) {
 }
 
 // C = A G (or C = A without a right multiplier), in the working precision.
-int right_product(genp_ctx* c, const double* A, int64_t lda) {
+// fuse_norms (circulant only): the product also forms ||A||_inf and max |C| (the slots
+// R_ANORM and R_MAXC), which the caller then does not compute separately.
+int right_product(genp_ctx* c, const double* A, int64_t lda, bool fuse_norms = false) {
     const int64_t n = c->n;
     const Mult& m = c->mr;
     const int lp = c->prec != GENP_F64;
@@ -761,7 +763,8 @@ int right_product(genp_ctx* c, const double* A, int64_t lda) {
     if (m.kind == GENP_G_CIRCULANT) {
         // each row of A correlated with c, by FFT
         HIPCK(launch_circ_apply((int)n, (int)n, 1, A, 1, lda, m.spec, c->circ_tw, c->circ_wp, 1.0, 0.0, nullptr, 0, 0,
-                                c->C, lp, 1, c->ldc, c->stream));
+                                c->C, lp, 1, c->ldc, c->stream, fuse_norms ? c->red + R_ANORM : nullptr,
+                                fuse_norms ? c->red + R_MAXC : nullptr));
         return GENP_OK;
     }
     if (m.kind == GENP_G_HOUSEHOLDER) {
@@ -1132,12 +1135,16 @@ int genp_precondition2(genp_ctx* c, const double* A, int64_t lda, int left, cons
     CK(set_mult(c, c->ml, left, H, ldh));
     HIPCK(hipMemsetAsync(c->red, 0, sizeof(unsigned long long) * R_COLS, c->stream));
     HIPCK(hipEventRecord(c->ev_ag[0], c->stream));
-    CK(right_product(c, A, lda));
+    // a lone circulant product forms the two norms on the fly (one pass over A and C fewer)
+    const bool fused = right == GENP_G_CIRCULANT && left == GENP_G_NONE;
+    CK(right_product(c, A, lda, fused));
     if (left != GENP_G_NONE) CK(left_product(c, A, lda, right == GENP_G_NONE));
     HIPCK(hipEventRecord(c->ev_ag[1], c->stream));
     HIPCK(launch_pad_identity(c->prec, c->C, c->ldc, (int)n, (int)c->n_pad, c->stream));
-    HIPCK(launch_max_abs(c->prec, c->C, c->ldc, (int)n, (int)n, 0, c->red + R_MAXC, c->stream));
-    HIPCK(launch_row_abs_sum_max(A, lda, (int)n, c->red + R_ANORM, c->stream));
+    if (!fused) {
+        HIPCK(launch_max_abs(c->prec, c->C, c->ldc, (int)n, (int)n, 0, c->red + R_MAXC, c->stream));
+        HIPCK(launch_row_abs_sum_max(A, lda, (int)n, c->red + R_ANORM, c->stream));
+    }
     ev_end(c, EV_PRE);
     unsigned long long h[3];
     double2 sv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};   // circulant: (max, min) |spectrum|

@@ -53,6 +53,11 @@ def test_circulant_product_entrywise(n):
     bound = _fft_bound(A, c) + og.gamma(n) * (np.abs(A) @ np.abs(G))
     print(f"  max err {err.max():.2e}, min slack {np.min(bound - err):.2e}", flush=True)
     assert np.all(err <= bound)
+    # the two norms the product forms on the fly: max |C| of the stored C exactly, and
+    # ||A||_inf up to the summation order
+    info = s.info()
+    assert info["max_abs_c"] == np.max(np.abs(C))
+    assert abs(info["anorm_inf"] - np.max(np.sum(np.abs(A), axis=1))) <= 1e-13 * info["anorm_inf"]
 
 
 def test_circulant_product_fp32():
@@ -67,6 +72,9 @@ def test_circulant_product_fp32():
     Co = og.precondition(A, og.circulant_from_params(c, n))
     bound = U32 * np.abs(Co) + 2 * _fft_bound(A, c)
     assert np.all(np.abs(C - Co) <= bound)
+    info = s.info()
+    assert info["max_abs_c"] == np.max(np.abs(C))   # max over the FP32-stored values
+    assert abs(info["anorm_inf"] - np.max(np.sum(np.abs(A), axis=1))) <= 1e-13 * info["anorm_inf"]
 
 
 @pytest.mark.parametrize("n", [2, 3, 100, 300, 32768])
