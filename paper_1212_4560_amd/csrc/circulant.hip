@@ -91,7 +91,7 @@ __device__ inline void fft_pass_r(cplx* L, int N, int qlog, int tid, const Twid&
             const int sb = INV ? RL - 1 - t : t;   // pairs m, m + 2^sb (compile-time after unrolling)
             const int h = q << sb;                 // the stage's half
             const int step = N / (2 * h);
-            cplx w[1 << sb];
+            cplx w[R / 2];   // 2^sb <= R / 2 of them used
 #pragma unroll
             for (int j = 0; j < (1 << sb); ++j) {
                 const cplx x = W((pos + j * q) * step);
@@ -156,7 +156,9 @@ circ_kernel(int n, int logN, const double* x, long long sx, long long bx,
         Tf[tid] = tid < (N >> 1) ? tw[tid] : make_double2(1.0, 0.0);
         Tc[tid] = 64 * tid < (N >> 1) ? tw[64 * tid] : make_double2(1.0, 0.0);
     }
-    const Twid W{Tf, Tc};
+    Twid W;   // (assigned, not brace-initialized: no constant initializer from LDS addresses)
+    W.Tf = Tf;
+    W.Tc = Tc;
     // packed, bit-reversed load: every global load issued before the first LDS store
     {
         constexpr int KL = CIRC_MAXN2 / CIRC_THREADS;
