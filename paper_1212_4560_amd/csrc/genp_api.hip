@@ -125,6 +125,11 @@ struct genp_ctx {
     // g_switch rows, then g_small
     int g_big = 3, g_small = 2;
     int64_t g_switch = 8192;
+    // FP64 update products: 128 x 128 tiles, two workgroups per CU, so a launch runs in
+    // rounds of round_tiles tiles; the bulk of a step group is cut into parts of whole
+    // rounds (the last part takes the rest) so that only one part pays a partly filled round
+    int64_t round_tiles = 512;
+    bool round_cut = true;
     // block Gaussian elimination: rows interchanged inside the diagonal blocks, P C = L U;
     // factor row r came from row perm[r] of C (n_pad entries)
     bool block_ge = false;
@@ -991,6 +996,18 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
     genp_ctx* c = new (std::nothrow) genp_ctx();
     if (!c) return GENP_ENOMEM;
     c->device = dev;
+    {
+        hipDeviceProp_t prop{};
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            c->round_tiles = 2LL * prop.multiProcessorCount;
+        // GENP_ROUND_CUT: "0" cuts the bulk into equal column parts; a positive number sets
+        // the tiles per round (tests use small rounds to take this path at small n)
+        if (const char* rc = getenv("GENP_ROUND_CUT")) {
+            const long long v = atoll(rc);
+            c->round_cut = v > 0;
+            if (v > 1) c->round_tiles = v;
+        }
+    }
     c->stream = (hipStream_t)stream;
     c->n = n;
     c->nb = nb;
@@ -1438,9 +1455,28 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         HIPCK(hipEventRecord(ev(a, 0), S));
         gstart.push_back(a);
         CK(schur_two(a, r2, r2, m, w, r2, r2 + w, w, m - w, S, (int)g));
+        // the bulk's column cuts: equal parts of whole blocks, or (FP64) parts of whole rounds
+        // of update tiles, in 128-column steps, the last part taking what remains
+        std::vector<int64_t> cut(gn + 1);
+        for (int64_t i = 0; i <= gn; ++i) cut[i] = rb + (bb * i / gn) * nb;
+        if (!lp && c->round_cut && mb > 0) {
+            const int64_t tm = (mb + 127) / 128, tn = mb / 128;
+            const int64_t rounds = (tm * tn + c->round_tiles - 1) / c->round_tiles;
+            // (with fewer than two rounds a part the equal cut stays: it keeps every diagonal
+            // block under some update work)
+            if (rounds >= 2 * gn) {
+                int64_t col = 0;
+                for (int64_t i = 0; i < gn; ++i) {
+                    cut[i] = rb + col * 128;
+                    const int64_t ri = rounds * (i + 1) / gn - rounds * i / gn;
+                    col = std::min(tn, col + ri * c->round_tiles / tm);
+                }
+                cut[gn] = rb + mb;   // the last part takes the rest (nb = 64: also a half tile)
+            }
+        }
         for (int64_t i = 0; i < gn; ++i) {
             const int64_t j = a2 + i;
-            const int64_t c0 = rb + (bb * i / gn) * nb, c1 = rb + (bb * (i + 1) / gn) * nb;
+            const int64_t c0 = cut[i], c1 = cut[i + 1];
             CK(diag_async(j, 4));
             CK(schur(a, rb, c0, mb, c1 - c0, S, (int)g));
             CK(wait_diag(j));

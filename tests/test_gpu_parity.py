@@ -328,6 +328,20 @@ def test_lookahead_does_not_change_the_factors(monkeypatch, n, nb, prec):
     assert np.array_equal(on, off)
 
 
+@pytest.mark.parametrize("n,nb", [(2560, 256), (1031, 64), (1500, 128)])
+def test_round_cuts_do_not_change_the_factors(monkeypatch, n, nb):
+    """FP64: the bulk of a step group is cut into column parts of whole rounds of update
+    tiles instead of equal parts of whole blocks.  Every entry takes the same products in the
+    same order either way (the cuts fall on 128-column tile edges; with nb = 64 the last part
+    takes the half tile), so the factors are bit-identical."""
+    g = np.random.default_rng(n + 7)
+    A, G = g.standard_normal((n, n)), g.standard_normal((n, n))
+    # rounds of 8 tiles, so that these small trailing matrices take the cut by rounds
+    _, on = _factor_with_env(monkeypatch, "GENP_ROUND_CUT", "8", A, G, n, nb)
+    _, off = _factor_with_env(monkeypatch, "GENP_ROUND_CUT", "0", A, G, n, nb)
+    assert np.array_equal(on, off)
+
+
 @pytest.mark.parametrize("n", [512, 1280, 1100])
 def test_split_diagonal_blocks_match_single_workgroup_blocks(monkeypatch, n):
     """FP64 nb = 256: the diagonal block as two LDS-resident 128 halves with the panel solves
