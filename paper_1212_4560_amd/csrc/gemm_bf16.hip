@@ -126,20 +126,32 @@ gemm_bf16_nt_kernel(GemmBf16Args g) {
         __syncthreads();
     }
     // D = alpha acc + beta Cin (row 4 lq + r, column lr of each 16 x 16 tile); each element is
-    // read before it is written, by the same lane, so Cin may alias D
+    // read before it is written, by the same lane, so Cin may alias D.  The reads of a 16-row
+    // strip are issued together before its stores: with Cin possibly aliasing D the compiler
+    // keeps every read after the stores that precede it, and one read-then-store per element
+    // made the update's epilogue some 250 memory round trips long.
     float __attribute__((address_space(1)))* D = (float __attribute__((address_space(1)))*)g.D;
+    const float __attribute__((address_space(1)))* Ci = (const float __attribute__((address_space(1)))*)g.Cin;
     const bool rd = g.beta != 0.f;
 #pragma unroll
-    for (int mi = 0; mi < 8; ++mi)
+    for (int mi = 0; mi < 8; ++mi) {
+        const long long row0 = m0 + wm * 128 + mi * 16 + lq * 4;
+        float cv[8][4];
+        if (rd) {
+#pragma unroll
+            for (int ni = 0; ni < 8; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cv[ni][r] = Ci[(row0 + r) * g.ldci + n0 + wn * 128 + ni * 16 + lr];
+        }
 #pragma unroll
         for (int ni = 0; ni < 8; ++ni)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const long long row = m0 + wm * 128 + mi * 16 + lq * 4 + r, col = n0 + wn * 128 + ni * 16 + lr;
                 float v = g.alpha * acc[mi][ni][r];
-                if (rd) v = fmaf(g.beta, g.Cin[row * g.ldci + col], v);
-                D[row * g.ldd + col] = v;
+                if (rd) v = fmaf(g.beta, cv[ni][r], v);
+                D[(row0 + r) * g.ldd + n0 + wn * 128 + ni * 16 + lr] = v;
             }
+    }
 }
 
 // hi / lo = 2-word BF16 split of an FP32 block (trans: of its transpose), 32 x 32 tiles via LDS
