@@ -75,7 +75,15 @@ def mixed_sweep(args, n: int) -> list:
     out = []
     smaxes = tuple(float(v) for v in args.sweep_smax.split(",")) if args.sweep_smax else SWEEP_SMAX
     precs = tuple(args.sweep_precs.split(",")) if args.sweep_precs else ("f32", "bf16", "bf16x3")
-    for w in wl.haar_family(n, smaxes, wl.MULT_TOEPLITZ, nrhs=1, seed=3):
+    if args.gaussian_inputs:
+        # counter runs: one Gaussian A of the same shape (no QR), the same multiplier recipe
+        g = np.random.default_rng(3)
+        ws = [wl.Workload("gaussianA", n, 3, torch.from_numpy(g.standard_normal((n, n))).to("cuda"),
+                          torch.from_numpy(g.standard_normal((n, 1))).to("cuda"), wl.MULT_TOEPLITZ,
+                          p=torch.from_numpy(g.standard_normal(2 * n - 1)).to("cuda"), smax=float("nan"))]
+    else:
+        ws = wl.haar_family(n, smaxes, wl.MULT_TOEPLITZ, nrhs=1, seed=3)
+    for w in ws:
         Ah = w.A.cpu().numpy()
         Bh = w.B.cpu().numpy()
         X = torch.empty((n, 1), dtype=torch.float64, device="cuda")
