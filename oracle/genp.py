@@ -453,10 +453,3 @@ def factor_residual(C: np.ndarray, LU: np.ndarray):
 def gamma(n: int, u: float = U64) -> float:
     """gamma_n = n u / (1 - n u), the constant of standard rounding-error bounds."""
     return n * u / (1 - n * u)
-
-
-def flops_method(n: int, nrhs: int, refine_steps: int) -> float:
-    """Algorithmic flop count of one solve: 2n^3 (A G) + GENP + substitutions and
-    recovery (4 n^2 k) + refinement (6 n^2 k per step)."""
-    lu = (2.0 / 3.0) * n ** 3 - 0.5 * n ** 2 - n / 6.0
-    return 2.0 * n ** 3 + lu + 4.0 * n * n * nrhs + refine_steps * 6.0 * n * n * nrhs
