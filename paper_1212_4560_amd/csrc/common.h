@@ -89,6 +89,18 @@ struct GemmF32Args {
     float* D; long long ldd;
 };
 hipError_t launch_gemm_f32_toep(const GemmF32Args& a, hipStream_t s);
+// FP32 update D = alpha A B + beta Cin (row-major FP32 operands, Cin may alias D), LDS-staged,
+// each MFMA over four consecutive k (gemm_f32.hip).  M, N multiples of 64, K of 16; A and B
+// 16-byte aligned with leading dimensions that are multiples of 4.
+struct GemmF32UpdArgs {
+    int M, N, K;
+    const float* A; long long lda;
+    const float* B; long long ldb;
+    float alpha, beta;
+    const float* Cin; long long ldci;
+    float* D; long long ldd;
+};
+hipError_t launch_gemm_f32_upd(const GemmF32UpdArgs& a, hipStream_t s);
 // BF16 product D (FP32, M x N) = A Bt^T with A (M x K) and Bt (N x K) BF16 row-major (gemm_bf16.hip);
 // with Alo and Btlo (the second words of 2-word BF16 operands) D = A Bt^T + A Btlo^T + Alo Bt^T.
 // M, N multiples of 256, K of 32, operands 16-byte aligned, lda and ldb multiples of 8.

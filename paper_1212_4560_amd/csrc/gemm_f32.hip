@@ -117,7 +117,132 @@ __global__ void __launch_bounds__(512, 1) gemm_f32_toep_kernel(GemmF32Args g) {
                                                             ni * 16 + lr] = acc[mi][ni][r];
 }
 
+// Schur update of the FP32 precision form, D = alpha A B + beta Cin (A: L21, M x K; B: U12,
+// K x N; FP32 row-major; Cin may alias D), LDS-staged: 256 x 128 workgroups of eight 64 x 64
+// waves, 16-deep K chunks in two LDS buffers, 16-byte global loads (the next chunk in flight
+// while the current one is multiplied).  Each MFMA takes four consecutive k (lane group q of
+// step s: k0 + 4 s + q), in increasing k, the grouping and order of the general LDS-staged
+// kernel, so the products are the same.  The epilogue reads each 16-row strip of Cin before
+// storing it.
+template <int BK>
+__global__ void __launch_bounds__(512, 1) gemm_f32_upd_kernel(GemmF32UpdArgs g) {
+    constexpr int BM = 256, BN = 128;
+    constexpr int NA = BK / 8, NB = BK / 16;   // 16-byte loads per thread per chunk (A, B)
+    __shared__ __attribute__((aligned(16))) float As[2][BK][BM + 4];   // [k][row]
+    __shared__ __attribute__((aligned(16))) float Bs[2][BK][BN + 4];   // [k][col]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
+    const int pid = xcd_remap(blockIdx.x, ntm * ntn);
+    constexpr int GROUP = 8;
+    const int first_m = (pid / (GROUP * ntn)) * GROUP;
+    const int gsz = min(ntm - first_m, GROUP);
+    const int tm = first_m + (pid % (GROUP * ntn)) % gsz;
+    const int tn = (pid % (GROUP * ntn)) / gsz;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int lr = lane & 15, lq = lane >> 4;
+    // global -> registers, 16 bytes a load: A element f = tid + 512 r covers row f / (BK / 4) and
+    // k 4 (f % (BK / 4)) .. + 3; B element f covers row k = f / 32 and columns 4 (f % 32) .. + 3
+    f32x4v ra[NA], rb[NB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            const int f = tid + 512 * r, row = m0 + f / (BK / 4), kq = f % (BK / 4);
+            ra[r] = row < g.M ? *(gcf4_ptr)(g.A + (long long)row * g.lda + k0 + 4 * kq) : f32x4v{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int f = tid + 512 * r, k = f / 32, col = n0 + 4 * (f % 32);
+            rb[r] = col < g.N ? *(gcf4_ptr)(g.B + (long long)(k0 + k) * g.ldb + col) : f32x4v{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            const int f = tid + 512 * r, row = f / (BK / 4), kq = f % (BK / 4);
+            As[buf][4 * kq + 0][row] = ra[r].x;
+            As[buf][4 * kq + 1][row] = ra[r].y;
+            As[buf][4 * kq + 2][row] = ra[r].z;
+            As[buf][4 * kq + 3][row] = ra[r].w;
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int f = tid + 512 * r;
+            *reinterpret_cast<f32x4v*>(&Bs[buf][f / 32][4 * (f % 32)]) = rb[r];
+        }
+    };
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bool live = wm * 64 < g.M - m0 && wn * 64 < g.N - n0;   // this wave has outputs
+    const int nk = g.K / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (live) {
+#pragma unroll
+            for (int st = 0; st < BK / 4; ++st) {
+                float af[4], bf[4];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi) af[mi] = As[cur][4 * st + lq][wm * 64 + mi * 16 + lr];
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[cur][4 * st + lq][wn * 64 + ni * 16 + lr];
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+            }
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    if (!live) return;
+    float __attribute__((address_space(1)))* D = (float __attribute__((address_space(1)))*)g.D;
+    const float __attribute__((address_space(1)))* Ci = (const float __attribute__((address_space(1)))*)g.Cin;
+    const bool rd = g.beta != 0.f;
+    const int mw = m0 + wm * 64, nw = n0 + wn * 64;
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+        float cv[4][4];
+        if (rd) {
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cv[ni][r] = Ci[(long long)(mw + mi * 16 + lq * 4 + r) * g.ldci + nw + ni * 16 + lr];
+        }
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = g.alpha * acc[mi][ni][r];
+                if (rd) v = fmaf(g.beta, cv[ni][r], v);
+                D[(long long)(mw + mi * 16 + lq * 4 + r) * g.ldd + nw + ni * 16 + lr] = v;
+            }
+    }
+}
+
 }  // namespace
+
+constexpr int F32_UPD_BK = 16;   // K chunk of the FP32 update kernel (16 or 32)
+
+hipError_t launch_gemm_f32_upd(const GemmF32UpdArgs& a, hipStream_t s) {
+    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    auto al = [](const float* p, long long ld) { return ((uintptr_t)p & 15) == 0 && (ld & 3) == 0; };
+    if (a.M % 64 || a.N % 64 || a.K <= 0 || a.K % 16 || !a.A || !a.B || !a.D || !al(a.A, a.lda) ||
+        !al(a.B, a.ldb) || (a.beta != 0.f && !a.Cin))
+        return hipErrorInvalidValue;
+    const int tiles = ((a.M + 255) / 256) * ((a.N + 127) / 128);
+    if (a.K % 32 == 0 && F32_UPD_BK == 32) hipLaunchKernelGGL(gemm_f32_upd_kernel<32>, dim3(tiles), dim3(512), 0, s, a);
+    else hipLaunchKernelGGL(gemm_f32_upd_kernel<16>, dim3(tiles), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_f32_toep(const GemmF32Args& a, hipStream_t s) {
     if (a.M <= 0 || a.N <= 0 || a.M % 64 || a.N % 64 || a.K % 16 || a.K != a.ldb || a.N > a.ldb ||

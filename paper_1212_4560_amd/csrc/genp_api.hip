@@ -120,6 +120,7 @@ struct genp_ctx {
     bool trsv_chain = true;
     bool diag_split = true;            // FP64 nb = 256 diagonal blocks as two LDS-resident halves
     bool lp_regs = true;               // precision forms: product from FP32 copies of A and G
+    bool f32_upd = true;               // FP32 form: updates on the 256 x 128 FP32 kernel
     bool gm_batched = true;            // GMRES-IR over 2..64 columns: one cycle for all columns
     // steps per group of the factorization: g_big while the trailing matrix has at least
     // g_switch rows, then g_small
@@ -1051,6 +1052,8 @@ int genp_create(genp_ctx** out, int64_t n, int prec, int nb, void* stream) {
         c->diag_split = !(dg && strcmp(dg, "single") == 0);
         const char* gb = getenv("GENP_GMRES");   // "columns": one GMRES cycle per column
         c->gm_batched = !(gb && strcmp(gb, "columns") == 0);
+        const char* fu = getenv("GENP_F32_UPD");   // "lp": the FP32 form's updates on the general kernel
+        c->f32_upd = !(fu && strcmp(fu, "lp") == 0);
         const char* lg = getenv("GENP_LP_GEMM");   // "lds": the precision form's product from FP64 operands
         c->lp_regs = !(lg && strcmp(lg, "lds") == 0);
     }
@@ -1326,6 +1329,25 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
             g.Cin = (const float*)at(r0, c0);
             g.ldci = ldc;
             HIPCK(launch_gemm_bf16_nt(g, st));
+            return GENP_OK;
+        }
+        if (lp && c->prec == GENP_F32 && c->f32_upd) {
+            // FP32: the 256 x 128 LDS-staged update kernel (same k grouping and order)
+            GemmF32UpdArgs g{};
+            g.M = (int)M;
+            g.N = (int)N;
+            g.K = KK;
+            g.A = (const float*)at(r0, k);
+            g.lda = ldc;
+            g.B = (const float*)at(k, c0);
+            g.ldb = ldc;
+            g.alpha = -1.f;
+            g.beta = 1.f;
+            g.Cin = (const float*)at(r0, c0);
+            g.ldci = ldc;
+            g.D = (float*)at(r0, c0);
+            g.ldd = ldc;
+            HIPCK(launch_gemm_f32_upd(g, st));
             return GENP_OK;
         }
         if (lp) {
