@@ -342,6 +342,18 @@ def test_round_cuts_do_not_change_the_factors(monkeypatch, n, nb):
     assert np.array_equal(on, off)
 
 
+@pytest.mark.parametrize("n,nb", [(1280, 256), (1100, 128), (900, 64)])
+def test_fp32_update_kernel_matches_general_kernel(monkeypatch, n, nb):
+    """FP32 form: the Schur updates on the dedicated 256 x 128 FP32 kernel and on the general
+    LDS-staged kernel feed every MFMA the same four consecutive k in the same order, so the
+    factors are bit-identical."""
+    g = np.random.default_rng(n + 11)
+    A, G = g.standard_normal((n, n)), g.standard_normal((n, n))
+    _, on = _factor_with_env(monkeypatch, "GENP_F32_UPD", "upd", A, G, n, nb, "f32")
+    _, off = _factor_with_env(monkeypatch, "GENP_F32_UPD", "lp", A, G, n, nb, "f32")
+    assert np.array_equal(on, off)
+
+
 @pytest.mark.parametrize("n", [512, 1280, 1100])
 def test_split_diagonal_blocks_match_single_workgroup_blocks(monkeypatch, n):
     """FP64 nb = 256: the diagonal block as two LDS-resident 128 halves with the panel solves
