@@ -566,11 +566,12 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
 // block p in solve order, T(t, p) is staged through LDS (prefetched one block ahead through
 // registers) and the values of X_p are polled straight into B operands, one 16-row tile of p
 // at a time in the order p solves its tiles: the product with a block overlaps the end of
-// that block's own solve.  Then the diagonal block is solved tile by tile: the tile goes
-// through a per-wave LDS slab to lanes 0..15, each of which substitutes one column of it in
-// registers (forward or backward, pivots applied as reciprocals; no cross-lane traffic inside
-// the substitution), and back into the accumulators; then the MFMA update of the tiles still
-// to be solved.  Each tile is published as soon as it is final.
+// that block's own solve; a lane's sixteen values of p are requested in one go and only the
+// ones still unset are polled again.  Then the diagonal block is solved in place in the
+// accumulators, tile by tile: substitution row by row with a cross-lane broadcast of each
+// solved row (pivots applied as reciprocals taken when the block is loaded, so no division
+// sits on the chain), then the MFMA update of the tiles still to be solved.  Each tile is
+// published as soon as it is final.
 template <bool LOWER, bool UNIT, bool TT, typename TF>
 __global__ void __launch_bounds__(256)
 trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, long long ldx, int ncols,
@@ -578,7 +579,6 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     constexpr int BS = 64;
     __shared__ double Td[BS][BS + 1];
     __shared__ double To[2][BS][BS + 1];
-    __shared__ double Ys[4][16][17];   // per wave: the 16 x 16 tile being substituted
     __shared__ double rdg[BS];         // reciprocals of the diagonal block's pivots
     __shared__ int s_q;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -612,6 +612,13 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         double v[16];
         load_blk(t, t, v);
         store_blk(Td, v);
+        if (!UNIT) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int e = tid + 256 * k;
+                if ((e >> 6) == (e & 63)) rdg[e & 63] = 1.0 / v[k];
+            }
+        }
     }
     double vn[16];
     if (q > 0) {
@@ -668,34 +675,23 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
         if (s_ + 1 < q) store_blk(To[buf ^ 1], vn);
         __syncthreads();
     }
-    if (!UNIT) {
-        if (tid < BS) rdg[tid] = 1.0 / Td[tid][tid];
-        __syncthreads();
-    }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int b = tord(jb);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Ys[w][lq + 4 * r][lr] = acc[b][r];
-        __syncthreads();
-        if (lq == 0) {
-            double y[16];
+        for (int j = 0; j < 16; ++j) {
+            const int sr = LOWER ? j : 15 - j;
+            double v = acc[b][sr >> 2];
+            if (!UNIT) v = v * rdg[16 * b + sr];
+            const double ys = __shfl(v, (sr & 3) * 16 + lr, 64);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) y[i] = Ys[w][i][lr];
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const int j = LOWER ? jj : 15 - jj;
-                if (!UNIT) y[j] *= rdg[16 * b + j];
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (LOWER ? i > j : i < j) y[i] = fma(-Td[16 * b + i][16 * b + j], y[j], y[i]);
+            for (int r = 0; r < 4; ++r) {
+                const int i = lq + 4 * r;
+                const double nv = fma(-Td[16 * b + i][16 * b + sr], ys, acc[b][r]);
+                const bool upd = LOWER ? i > sr : i < sr;
+                acc[b][r] = upd ? nv : ((i == sr) ? ys : acc[b][r]);
             }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) Ys[w][i][lr] = y[i];
         }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[b][r] = Ys[w][lq + 4 * r][lr];
         if (cok) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
