@@ -67,6 +67,11 @@ __device__ inline int wave_min_i(int v) {
 //  3. the trailing block takes the rank-16 Schur update (Fact 2.1) on the
 //     matrix cores: 16 x 16 tiles, 8 per wave per batch of loads, operands from
 //     LDS (the panel below the diagonal and the new rows of U).
+// Steps 3 and 1 overlap (look-ahead): wave 0 updates the next panel's column of tiles first,
+// keeps it in LDS and factors it while waves 1-3 update the rest of the trailing block; the
+// panel's L goes to the other of two LDS buffers.  Every tile takes the same operations in the
+// same order as without the overlap (the next panel staged at the storage precision), so the
+// factors are the same.
 //
 // PIV: block Gaussian elimination with the diagonal block as the block pivot (Theorem 2.2):
 // rows are interchanged inside the block, at each column the row with the largest |entry|
@@ -79,12 +84,13 @@ __global__ void __launch_bounds__(256)
 diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long col0,
                const double* __restrict__ maxc, double pivot_tol, PanelStats* __restrict__ st,
                int* __restrict__ perm) {
-    __shared__ double Ls[MAXNB][PW + 1];        // panel rows kb.. (row r - kb), 16 columns
+    __shared__ double Ls[2][MAXNB][PW + 1];     // two panels: rows kb.. (row r - kb), 16 columns
     __shared__ double Rs[PW][MAXNB - PW + 1];   // rows kb..kb+15 of U right of the panel
     __shared__ int sw[MAXNB];                   // PIV: row interchanged with row r at step r
     __shared__ int ptmp[MAXNB];                 // PIV: the current panel's net row movement
     __shared__ int bperm[MAXNB];                // PIV: the block's net permutation so far
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
     const double tol_abs = pivot_tol * maxc[0];
     double s_min = INFINITY, s_max = 0.0;
     long long s_bad = -1;
@@ -92,135 +98,192 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
         bperm[tid] = tid;
         __syncthreads();
     }
-    for (int kb = 0; kb < nb; kb += PW) {
+    // wave 0: factor the panel at columns kb..kb+15, rows kb..nb-1, read from D or (from_lds)
+    // from Lp, written to D and Lp
+    auto factor_panel = [&](int kb, double (*Lp)[PW + 1], bool from_lds) {
         const int rows = nb - kb;
-        if (wave == 0) {
-            double p[4][PW];
+        double p[4][PW];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = s * 64 + lane;
+#pragma unroll
+            for (int c = 0; c < PW; ++c)
+                    p[s][c] = (r < rows) ? (from_lds ? Lp[r][c] : (double)D[(long long)(kb + r) * ldd + kb + c]) : 0.0;
+        }
+        // PIV: the panel's rows stay in their registers; pos[s] is the current position of
+        // the row in slot s (LAPACK's interchange order: at step c the chosen row takes
+        // position c and the row that held position c takes the chosen row's place) and
+        // done[s] marks rows already taken as pivot rows.  Rows are written back at their
+        // final positions.  Without PIV, pos[s] = r and pivot row c sits in lane c, slot 0.
+        int pos[4];
+        bool done[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            pos[s] = s * 64 + lane;
+            done[s] = false;
+        }
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+            double prow[PW];
+            if (PIV) {
+                // pivot: the largest |entry| of column c among the rows not yet taken (valid
+                // rows only; a NaN counts below every number), the smallest position on ties
+                int q = c, qpos = c;   // pad columns: the pad row at position c, never moved
+                if (kb + c < nvalid) {
+                    double best = -1.0;
+                    int bp = 1 << 30, bi = c;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int r = s * 64 + lane;
+                        const double a = fabs(p[s][c]);
+                        const double key = a == a ? a : -0.5;
+                        if (!done[s] && kb + r < nvalid && (key > best || (key == best && pos[s] < bp))) {
+                            best = key;
+                            bp = pos[s];
+                            bi = r;
+                        }
+                    }
+                    const double m = wave_max_d(best);
+                    unsigned long long hold = __ballot(best == m);
+                    if (__popcll(hold) > 1) {
+                        // several lanes hold the maximum: keep those with the smallest position
+                        const int mp = wave_min_i(best == m ? bp : 1 << 30);
+                        hold = __ballot(best == m && bp == mp);
+                    }
+                    const int wl = __builtin_ctzll(hold);
+                    q = __builtin_amdgcn_readlane(bi, wl);
+                    qpos = __builtin_amdgcn_readlane(bp, wl);
+                }
+                if (lane == 0) sw[kb + c] = kb + qpos;
+                const int qs = q >> 6, ql = q & 63;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    if (pos[s] == c) pos[s] = qpos;
+                    if (s == qs && lane == ql) {
+                        pos[s] = c;
+                        done[s] = true;
+                    }
+                }
+                auto get = [&](const double (&row)[PW]) {
+#pragma unroll
+                    for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(row[t], ql) : 0.0;
+                };
+                switch (qs) {
+                    case 0: get(p[0]); break;
+                    case 1: get(p[1]); break;
+                    case 2: get(p[2]); break;
+                    default: get(p[3]); break;
+                }
+            } else {
+                // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
+#pragma unroll
+                for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(p[0][t], c) : 0.0;
+            }
+            const double piv = prow[c];
+            if (lane == 0 && kb + c < nvalid) {
+                const double a = fabs(piv);
+                if (s_bad < 0 && (!isfinite(a) || a <= tol_abs)) s_bad = col0 + kb + c;
+                if (s_bad < 0) {
+                    s_min = fmin(s_min, a);
+                    s_max = fmax(s_max, a);
+                }
+            }
+            const double rp = 1.0 / piv;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int r = s * 64 + lane;
+                if ((PIV ? !done[s] : r > c) && r < rows) {
+                    const double l = p[s][c] * rp;
+                    p[s][c] = l;
 #pragma unroll
-                for (int c = 0; c < PW; ++c) p[s][c] = (r < rows) ? (double)D[(long long)(kb + r) * ldd + kb + c] : 0.0;
-            }
-            // PIV: the panel's rows stay in their registers; pos[s] is the current position of
-            // the row in slot s (LAPACK's interchange order: at step c the chosen row takes
-            // position c and the row that held position c takes the chosen row's place) and
-            // done[s] marks rows already taken as pivot rows.  Rows are written back at their
-            // final positions.  Without PIV, pos[s] = r and pivot row c sits in lane c, slot 0.
-            int pos[4];
-            bool done[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                pos[s] = s * 64 + lane;
-                done[s] = false;
-            }
-#pragma unroll
-            for (int c = 0; c < PW; ++c) {
-                double prow[PW];
-                if (PIV) {
-                    // pivot: the largest |entry| of column c among the rows not yet taken (valid
-                    // rows only; a NaN counts below every number), the smallest position on ties
-                    int q = c, qpos = c;   // pad columns: the pad row at position c, never moved
-                    if (kb + c < nvalid) {
-                        double best = -1.0;
-                        int bp = 1 << 30, bi = c;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const int r = s * 64 + lane;
-                            const double a = fabs(p[s][c]);
-                            const double key = a == a ? a : -0.5;
-                            if (!done[s] && kb + r < nvalid && (key > best || (key == best && pos[s] < bp))) {
-                                best = key;
-                                bp = pos[s];
-                                bi = r;
-                            }
-                        }
-                        const double m = wave_max_d(best);
-                        unsigned long long hold = __ballot(best == m);
-                        if (__popcll(hold) > 1) {
-                            // several lanes hold the maximum: keep those with the smallest position
-                            const int mp = wave_min_i(best == m ? bp : 1 << 30);
-                            hold = __ballot(best == m && bp == mp);
-                        }
-                        const int wl = __builtin_ctzll(hold);
-                        q = __builtin_amdgcn_readlane(bi, wl);
-                        qpos = __builtin_amdgcn_readlane(bp, wl);
-                    }
-                    if (lane == 0) sw[kb + c] = kb + qpos;
-                    const int qs = q >> 6, ql = q & 63;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        if (pos[s] == c) pos[s] = qpos;
-                        if (s == qs && lane == ql) {
-                            pos[s] = c;
-                            done[s] = true;
-                        }
-                    }
-                    auto get = [&](const double (&row)[PW]) {
-#pragma unroll
-                        for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(row[t], ql) : 0.0;
-                    };
-                    switch (qs) {
-                        case 0: get(p[0]); break;
-                        case 1: get(p[1]); break;
-                        case 2: get(p[2]); break;
-                        default: get(p[3]); break;
-                    }
-                } else {
-                    // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
-#pragma unroll
-                    for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(p[0][t], c) : 0.0;
-                }
-                const double piv = prow[c];
-                if (lane == 0 && kb + c < nvalid) {
-                    const double a = fabs(piv);
-                    if (s_bad < 0 && (!isfinite(a) || a <= tol_abs)) s_bad = col0 + kb + c;
-                    if (s_bad < 0) {
-                        s_min = fmin(s_min, a);
-                        s_max = fmax(s_max, a);
-                    }
-                }
-                const double rp = 1.0 / piv;
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int r = s * 64 + lane;
-                    if ((PIV ? !done[s] : r > c) && r < rows) {
-                        const double l = p[s][c] * rp;
-                        p[s][c] = l;
-#pragma unroll
-                        for (int t = 0; t < PW; ++t)
-                            if (t > c) p[s][t] = fma(-l, prow[t], p[s][t]);
-                    }
+                    for (int t = 0; t < PW; ++t)
+                        if (t > c) p[s][t] = fma(-l, prow[t], p[s][t]);
                 }
             }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = s * 64 + lane;
+            if (r < rows) {
+#pragma unroll
+                for (int c = 0; c < PW; ++c) {
+                    D[(long long)(kb + pos[s]) * ldd + kb + c] = (T)p[s][c];
+                    Lp[pos[s]][c] = p[s][c];
+                }
+            }
+        }
+        if (PIV) {
+            // the panel's net row movement (ptmp: new position -> old position) and the
+            // block's permutation so far, from the rows' final positions
+            int ob[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) ob[s] = s * 64 + lane < rows ? bperm[kb + s * 64 + lane] : 0;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int r = s * 64 + lane;
                 if (r < rows) {
+                    ptmp[kb + pos[s]] = kb + r;
+                    bperm[kb + pos[s]] = ob[s];
+                }
+            }
+        }
+    };
+    // trailing block at row and column kb+16: A22 -= L21 U12 on 16 x 16 tiles, TB per batch of
+    // loads; this wave's tiles are entries first, first + 1, ... of a list of total tiles, TB at
+    // a time every stride entries, entry e being tile tile_of(e) = (ti, tj).  f64 16x16x4
+    // layout: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16); accumulator
+    // lane l, element r -> (row l/16 + 4r, col l%16).  to_lds: the tiles (which form the next
+    // panel) go to Ln at the storage precision instead of D.
+    auto update_tiles = [&](int kb, const double (*Lc)[PW + 1], int total, int first, int stride, auto tile_of,
+                            double (*Ln)[PW + 1]) {
+        for (int t0 = first; t0 < total; t0 += stride) {
+            f64x4 acc[TB];
 #pragma unroll
-                    for (int c = 0; c < PW; ++c) {
-                        D[(long long)(kb + pos[s]) * ldd + kb + c] = (T)p[s][c];
-                        Ls[pos[s]][c] = p[s][c];
+            for (int b = 0; b < TB; ++b) {
+                const int e = t0 + b;
+                const int2 tt = tile_of(e < total ? e : t0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = kb + PW + tt.x * 16 + lq + 4 * r, col = kb + PW + tt.y * 16 + lr;
+                    acc[b][r] = (e < total) ? (double)D[(long long)row * ldd + col] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                const int e = t0 + b;
+                if (e < total) {
+                    const int2 tt = tile_of(e);
+#pragma unroll
+                    for (int kk = 0; kk < PW; kk += 4) {
+                        const double a = Lc[PW + tt.x * 16 + lr][kk + lq];
+                        const double bb = Rs[kk + lq][tt.y * 16 + lr];
+                        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, bb, acc[b], 0, 0, 0);
                     }
                 }
             }
-            if (PIV) {
-                // the panel's net row movement (ptmp: new position -> old position) and the
-                // block's permutation so far, from the rows' final positions
-                int ob[4];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) ob[s] = s * 64 + lane < rows ? bperm[kb + s * 64 + lane] : 0;
+            for (int b = 0; b < TB; ++b) {
+                const int e = t0 + b;
+                if (e < total) {
+                    const int2 tt = tile_of(e);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int r = s * 64 + lane;
-                    if (r < rows) {
-                        ptmp[kb + pos[s]] = kb + r;
-                        bperm[kb + pos[s]] = ob[s];
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = kb + PW + tt.x * 16 + lq + 4 * r, col = kb + PW + tt.y * 16 + lr;
+                        if (Ln)
+                            Ln[tt.x * 16 + lq + 4 * r][lr] = (double)(T)acc[b][r];
+                        else
+                            D[(long long)row * ldd + col] = (T)acc[b][r];
                     }
                 }
             }
         }
-        __syncthreads();
+    };
+    if (wave == 0) factor_panel(0, Ls[0], false);
+    for (int kb = 0; kb < nb; kb += PW) {
+        const int rows = nb - kb;
+        double (*Lc)[PW + 1] = Ls[(kb / PW) & 1];
+        double (*Ln)[PW + 1] = Ls[((kb / PW) & 1) ^ 1];
+        __syncthreads();   // the panel at kb factored; the previous trailing update stored
         if (PIV) {
             // rows that move: kb..kb+15 and the rows they were exchanged with
             const int j = tid;
@@ -251,7 +314,7 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                 for (int t = 0; t < PW; ++t)
 #pragma unroll
                     for (int i = 0; i < PW; ++i)
-                        if (i > t) x[i] = fma(-Ls[i][t], x[t], x[i]);
+                        if (i > t) x[i] = fma(-Lc[i][t], x[t], x[i]);
 #pragma unroll
                 for (int i = 0; i < PW; ++i) {
                     D[(long long)(kb + i) * ldd + kb + PW + tid] = (T)x[i];
@@ -259,51 +322,18 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                 }
             }
             __syncthreads();
-            // trailing block rows/cols kb+16..: 16 x 16 tiles, A22 -= L21 U12 on the matrix cores.
-            // f64 16x16x4 layout: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
-            // accumulator lane l, element r -> (row l/16 + 4r, col l%16).
-            const int nt = ncols / PW, ntiles = nt * nt;
-            const int lr = lane & 15, lq = lane >> 4;
-            for (int t0 = wave * TB; t0 < ntiles; t0 += 4 * TB) {
-                f64x4 acc[TB];
-#pragma unroll
-                for (int b = 0; b < TB; ++b) {
-                    const int tile = t0 + b;
-                    const int ti = tile / nt, tj = tile % nt;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = kb + PW + ti * 16 + lq + 4 * r, col = kb + PW + tj * 16 + lr;
-                        acc[b][r] = (tile < ntiles) ? (double)D[(long long)row * ldd + col] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < TB; ++b) {
-                    const int tile = t0 + b;
-                    if (tile < ntiles) {
-                        const int ti = tile / nt, tj = tile % nt;
-#pragma unroll
-                        for (int kk = 0; kk < PW; kk += 4) {
-                            const double a = Ls[PW + ti * 16 + lr][kk + lq];
-                            const double bb = Rs[kk + lq][tj * 16 + lr];
-                            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, bb, acc[b], 0, 0, 0);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < TB; ++b) {
-                    const int tile = t0 + b;
-                    if (tile < ntiles) {
-                        const int ti = tile / nt, tj = tile % nt;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int row = kb + PW + ti * 16 + lq + 4 * r, col = kb + PW + tj * 16 + lr;
-                            D[(long long)row * ldd + col] = (T)acc[b][r];
-                        }
-                    }
-                }
+            const int nt = ncols / PW;
+            if (wave == 0) {
+                // the next panel's column of tiles, then that panel, while waves 1-3 update the rest
+                update_tiles(kb, Lc, nt, 0, TB, [](int e) { return make_int2(e, 0); }, Ln);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                factor_panel(kb + PW, Ln, true);
+            } else if (nt > 1) {
+                const int w1 = nt - 1;
+                update_tiles(kb, Lc, nt * w1, (wave - 1) * TB, 3 * TB,
+                             [w1](int e) { return make_int2(e / w1, 1 + e % w1); }, nullptr);
             }
         }
-        __syncthreads();
     }
     if (tid == 0) {
         st->min_abs = s_min;
