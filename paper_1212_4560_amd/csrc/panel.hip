@@ -284,32 +284,46 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
         double (*Lc)[PW + 1] = Ls[(kb / PW) & 1];
         double (*Ln)[PW + 1] = Ls[((kb / PW) & 1) ^ 1];
         __syncthreads();   // the panel at kb factored; the previous trailing update stored
-        if (PIV) {
-            // rows that move: kb..kb+15 and the rows they were exchanged with
+        const int ncols = rows - PW;
+        // one thread per column j of the block outside the panel.  PIV: rows kb..kb+15 and the
+        // rows they were exchanged with take the panel's net movement (all loads before any
+        // store).  Right of the panel (j >= kb+16) rows kb..kb+15 of column j then take
+        // x <- L11^{-1} x (unit lower, column sweep): the rows of U12, also kept in Rs.
+        {
             const int j = tid;
-            if (j < nb && (j < kb || j >= kb + PW)) {
+            const bool right = j >= kb + PW && j < nb;
+            if (PIV && j < nb && (j < kb || j >= kb + PW)) {
                 double v[2 * PW];
 #pragma unroll
                 for (int i = 0; i < 2 * PW; ++i) {
                     const int q = i < PW ? kb + i : sw[kb + i - PW];
                     const int src = ptmp[q];
-                    v[i] = src != q ? (double)D[(long long)src * ldd + j] : 0.0;
+                    v[i] = (src != q || (right && i < PW)) ? (double)D[(long long)src * ldd + j] : 0.0;
+                }
+                if (right) {
+#pragma unroll
+                    for (int t = 0; t < PW; ++t)
+#pragma unroll
+                        for (int i = 0; i < PW; ++i)
+                            if (i > t) v[i] = fma(-Lc[i][t], v[t], v[i]);
+#pragma unroll
+                    for (int i = 0; i < PW; ++i) {
+                        D[(long long)(kb + i) * ldd + j] = (T)v[i];
+                        Rs[i][j - kb - PW] = v[i];
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < 2 * PW; ++i) {
+                    // right of the panel rows kb..kb+15 already hold their rows of U12, also
+                    // where one is named again as an exchange partner
                     const int q = i < PW ? kb + i : sw[kb + i - PW];
-                    if (ptmp[q] != q) D[(long long)q * ldd + j] = (T)v[i];
+                    const bool done_u = right && q >= kb && q < kb + PW;
+                    if (ptmp[q] != q && !done_u) D[(long long)q * ldd + j] = (T)v[i];
                 }
-            }
-            __syncthreads();
-        }
-        const int ncols = rows - PW;
-        if (ncols > 0) {
-            if (tid < ncols) {
-                // rows kb..kb+15, column kb+16+tid: x <- L11^{-1} x (unit lower, column sweep)
+            } else if (!PIV && right) {
                 double x[PW];
 #pragma unroll
-                for (int i = 0; i < PW; ++i) x[i] = (double)D[(long long)(kb + i) * ldd + kb + PW + tid];
+                for (int i = 0; i < PW; ++i) x[i] = (double)D[(long long)(kb + i) * ldd + j];
 #pragma unroll
                 for (int t = 0; t < PW; ++t)
 #pragma unroll
@@ -317,10 +331,12 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                         if (i > t) x[i] = fma(-Lc[i][t], x[t], x[i]);
 #pragma unroll
                 for (int i = 0; i < PW; ++i) {
-                    D[(long long)(kb + i) * ldd + kb + PW + tid] = (T)x[i];
-                    Rs[i][tid] = x[i];
+                    D[(long long)(kb + i) * ldd + j] = (T)x[i];
+                    Rs[i][j - kb - PW] = x[i];
                 }
             }
+        }
+        if (ncols > 0) {
             __syncthreads();
             const int nt = ncols / PW;
             if (wave == 0) {
