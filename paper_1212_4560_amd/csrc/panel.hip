@@ -134,14 +134,15 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                     int bp = 1 << 30, bi = c;
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
+                        if (s * 64 >= rows) break;   // no rows of the block in this slot (uniform)
                         const int r = s * 64 + lane;
                         const double a = fabs(p[s][c]);
                         const double key = a == a ? a : -0.5;
-                        if (!done[s] && kb + r < nvalid && (key > best || (key == best && pos[s] < bp))) {
-                            best = key;
-                            bp = pos[s];
-                            bi = r;
-                        }
+                        // one basic block: the conditions evaluated in full, the result selected
+                        const bool take = (!done[s]) & (kb + r < nvalid) & ((key > best) | ((key == best) & (pos[s] < bp)));
+                        best = take ? key : best;
+                        bp = take ? pos[s] : bp;
+                        bi = take ? r : bi;
                     }
                     const double m = wave_max_d(best);
                     unsigned long long hold = __ballot(best == m);
@@ -191,6 +192,7 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
             const double rp = 1.0 / piv;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
+                if (s * 64 >= rows) break;   // the whole slot below the block (uniform)
                 const int r = s * 64 + lane;
                 if ((PIV ? !done[s] : r > c) && r < rows) {
                     const double l = p[s][c] * rp;
