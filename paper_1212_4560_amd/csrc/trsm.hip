@@ -566,8 +566,8 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
 // block p in solve order, T(t, p) is staged through LDS (prefetched one block ahead through
 // registers) and the values of X_p are polled straight into B operands, one 16-row tile of p
 // at a time in the order p solves its tiles: the product with a block overlaps the end of
-// that block's own solve; a lane's sixteen values of p are requested in one go and only the
-// ones still unset are polled again.  Then the diagonal block is solved in place in the
+// that block's own solve; a lane's sixteen values of p are requested in one go, one block
+// ahead, and only the ones still unset are polled again.  Then the diagonal block is solved in place in the
 // accumulators, tile by tile: substitution row by row with a cross-lane broadcast of each
 // solved row (pivots applied as reciprocals taken when the block is loaded, so no division
 // sits on the chain), then the MFMA update of the tiles still to be solved.  Each tile is
@@ -631,21 +631,29 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[b][r] = cok ? X[(r0 + 16 * b + lq + 4 * r) * ldx + cc] : 0.0;
     __syncthreads();
-    for (int s_ = 0; s_ < q; ++s_) {
-        const int p = order(s_);
-        const int buf = s_ & 1;
-        if (s_ + 1 < q) load_blk(t, order(s_ + 1), vn);
-        // all sixteen values of this lane for block p requested at once (one round trip when p
-        // is long solved); a tile's values still unset are polled again before its products
-        const unsigned long long* srcp = pub + (long long)p * BS * 64 + (long long)lq * 64 + cc;
-        unsigned long long pv[4][4];
+    // the sixteen values of this lane for a block are requested one block ahead (in flight
+    // during the products with the block before it); those still unset when their tile is
+    // reached are polled again before its products
+    auto request = [&](int pblk, unsigned long long (&v)[4][4]) {
+        const unsigned long long* src = pub + (long long)pblk * BS * 64 + (long long)lq * 64 + cc;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                pv[j][u] = cok ? __hip_atomic_load(srcp + (16 * tord(j) + 4 * u) * 64, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT)
-                               : 0ull;
+                v[j][u] = cok ? __hip_atomic_load(src + (16 * tord(j) + 4 * u) * 64, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : 0ull;
+    };
+    unsigned long long pv[4][4], pvn[4][4];
+    if (q > 0) request(order(0), pv);
+    for (int s_ = 0; s_ < q; ++s_) {
+        const int p = order(s_);
+        const int buf = s_ & 1;
+        if (s_ + 1 < q) {
+            load_blk(t, order(s_ + 1), vn);
+            request(order(s_ + 1), pvn);
+        }
+        const unsigned long long* srcp = pub + (long long)p * BS * 64 + (long long)lq * 64 + cc;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int pb = tord(j);
@@ -672,7 +680,13 @@ trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
                     acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-To[buf][16 * b + lr][16 * pb + 4 * u + lq], bq[u],
                                                                   acc[b], 0, 0, 0);
         }
-        if (s_ + 1 < q) store_blk(To[buf ^ 1], vn);
+        if (s_ + 1 < q) {
+            store_blk(To[buf ^ 1], vn);
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pv[jj][u] = pvn[jj][u];
+        }
         __syncthreads();
     }
 #pragma unroll
