@@ -419,7 +419,8 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
 // Publication: each solved value is its own flag.  pub (n_pad x NR, row-major) holds
 // a signalling-NaN bit pattern (kUnset) before the launch; the writer stores x_t into
 // it with device-scope relaxed atomic stores, and a reader polls the values it needs
-// with device-scope relaxed atomic loads until none is kUnset.  Arithmetic never
+// with device-scope relaxed atomic loads until none is kUnset (the first request for a
+// block goes out one block ahead, during the products with the block before it).  Arithmetic never
 // produces kUnset (a NaN result is quiet), and each 8-byte value is written and read
 // whole, so no fence or separate flag sits on the chain.  sync[0]: ticket, sync[1]:
 // sticky error word (a wait exceeded spin_limit polls: the result is invalid).  The
@@ -490,20 +491,30 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
     double bv[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) bv[c] = (part == 0) ? X[(r0 + ri) * ldx + c] : 0.0;
+    // this thread's published value of a block is requested one block ahead (in flight during
+    // the products with the block before it) and polled again while it is unset
+    unsigned long long pnext = (q > 0 && tid < BS * NR)
+                                   ? __hip_atomic_load(pub + (long long)order(0) * BS * NR + tid, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : 0ull;
     for (int s_ = 0; s_ < q; ++s_) {
         const int p = order(s_);
         const int buf = s_ & 1;
         if (s_ + 1 < q) load_blk(t, order(s_ + 1), vn);
         if (tid < BS * NR) {
             unsigned long long* src = pub + (long long)p * BS * NR + tid;
-            unsigned long long v;
+            unsigned long long v = pnext;
+            if (s_ + 1 < q)
+                pnext = __hip_atomic_load(pub + (long long)order(s_ + 1) * BS * NR + tid, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
             unsigned it = 0;
-            while ((v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kUnset) {
+            while (v == kUnset) {
                 if (++it > spin_limit) {
                     __hip_atomic_fetch_or(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
+                v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             xs[tid / NR][tid % NR] = __longlong_as_double((long long)v);
         }
