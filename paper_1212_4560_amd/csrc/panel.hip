@@ -125,6 +125,7 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
 #pragma unroll
         for (int c = 0; c < PW; ++c) {
             double prow[PW];
+            double rp;
             if (PIV) {
                 // pivot: the largest |entry| of column c among the rows not yet taken (valid
                 // rows only; a NaN counts below every number), the smallest position on ties
@@ -166,8 +167,11 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                     }
                 }
                 auto get = [&](const double (&row)[PW]) {
+                    // the pivot first: its reciprocal is under way while the rest of the row is read
+                    const double pv = readlane_d(row[c], ql);
+                    rp = 1.0 / pv;
 #pragma unroll
-                    for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(row[t], ql) : 0.0;
+                    for (int t = 0; t < PW; ++t) prow[t] = (t > c) ? readlane_d(row[t], ql) : (t == c ? pv : 0.0);
                 };
                 switch (qs) {
                     case 0: get(p[0]); break;
@@ -177,19 +181,12 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                 }
             } else {
                 // pivot row c is row c of the panel: lane c, slot 0 (its first c entries are L)
+                const double pv = readlane_d(p[0][c], c);
+                rp = 1.0 / pv;
 #pragma unroll
-                for (int t = 0; t < PW; ++t) prow[t] = (t >= c) ? readlane_d(p[0][t], c) : 0.0;
+                for (int t = 0; t < PW; ++t) prow[t] = (t > c) ? readlane_d(p[0][t], c) : (t == c ? pv : 0.0);
             }
             const double piv = prow[c];
-            if (lane == 0 && kb + c < nvalid) {
-                const double a = fabs(piv);
-                if (s_bad < 0 && (!isfinite(a) || a <= tol_abs)) s_bad = col0 + kb + c;
-                if (s_bad < 0) {
-                    s_min = fmin(s_min, a);
-                    s_max = fmax(s_max, a);
-                }
-            }
-            const double rp = 1.0 / piv;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 if (s * 64 >= rows) break;   // the whole slot below the block (uniform)
@@ -200,6 +197,14 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
 #pragma unroll
                     for (int t = 0; t < PW; ++t)
                         if (t > c) p[s][t] = fma(-l, prow[t], p[s][t]);
+                }
+            }
+            if (lane == 0 && kb + c < nvalid) {
+                const double a = fabs(piv);
+                if (s_bad < 0 && (!isfinite(a) || a <= tol_abs)) s_bad = col0 + kb + c;
+                if (s_bad < 0) {
+                    s_min = fmin(s_min, a);
+                    s_max = fmax(s_max, a);
                 }
             }
         }
