@@ -134,8 +134,9 @@ hipError_t launch_convert_toep(const double* p, int n, int n_pad, float* out, in
 
 // Diagonal block LU (no pivoting) in place, one workgroup; records PanelStats.
 // FP64 256 x 256 diagonal block as two LDS-resident 128 blocks, the panel solves and one update
+// (rcp: the panel solves' pivots as reciprocals, as for launch_panel_trsm)
 hipError_t launch_diag_lu_split(void* Dblk, long long ldd, int nvalid, long long col0, const double* maxc,
-                                double pivot_tol, PanelStats* st, hipStream_t s);
+                                double pivot_tol, PanelStats* st, int rcp, hipStream_t s);
 hipError_t launch_diag_lu(int prec, void* Dblk, long long ldd, int nb, int nvalid,
                           long long col0, const double* maxc, double pivot_tol,
                           PanelStats* st, hipStream_t s);
@@ -216,8 +217,10 @@ hipError_t launch_circ_apply(int n, int nvec, int conj, const double* x, long lo
 // The two block solves of an elimination step in one launch: A12 <- L11^{-1} A12
 // (nb x m) and A21 <- A21 U11^{-1} (m x nb), with L11 \ U11 the factored diagonal
 // block D.  nb in {64, 128, 256}; f32: D, A12 and A21 are FP32 (arithmetic in FP64).
-hipError_t launch_panel_trsm(int f32, const void* D, long long ldd, int nb, void* A12, void* A21, long long ldx,
-                             int m, hipStream_t s);
+// rcp (FP64 only): the pivots applied as reciprocals taken once per 16-row tile instead of
+// a division per row (faster; each result may differ in its last bit).
+hipError_t launch_panel_trsm(int f32, int rcp, const void* D, long long ldd, int nb, void* A12, void* A21,
+                             long long ldx, int m, hipStream_t s);
 // Whole triangular solve T X = B (T = the n_pad x n_pad factor as in launch_trsm's kinds,
 // except TRSM_RIGHT_U) for 1..4 right-hand sides, one launch per bs-row block.
 // The same solve (T = the n_pad x n_pad factor, kinds as above except TRSM_RIGHT_U) in one

@@ -1265,13 +1265,13 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
                                      c->perm + k, st));
             HIPCK(launch_block_row_perm((double*)c->C, ldc, k, (int)nb, (int)np, c->perm + k, st));
         } else if (c->diag_split && c->prec == GENP_F64 && nb == 256)
-            HIPCK(launch_diag_lu_split(at(k, k), ldc, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+            HIPCK(launch_diag_lu_split(at(k, k), ldc, nvalid, k, maxc, pivot_tol, c->stats + j, 1, st));
         else if (c->diag_split && nb == 256) {
             // FP32 storage: the block widened into an FP64 scratch block, factored there by the
             // same two-half kernels (FP64 arithmetic), and rounded back to FP32; one scratch
             // block serves every step since the diagonal blocks run one after another on st
             HIPCK(launch_convert_f32_f64((const float*)at(k, k), ldc, c->dwork, 256, 256, 256, st));
-            HIPCK(launch_diag_lu_split(c->dwork, 256, nvalid, k, maxc, pivot_tol, c->stats + j, st));
+            HIPCK(launch_diag_lu_split(c->dwork, 256, nvalid, k, maxc, pivot_tol, c->stats + j, 0, st));
             HIPCK(launch_convert_f64_f32(c->dwork, 256, (float*)at(k, k), ldc, 256, 256, st));
         } else
             HIPCK(launch_diag_lu(c->prec, at(k, k), ldc, (int)nb, nvalid, k, maxc, pivot_tol, c->stats + j, st));
@@ -1281,7 +1281,7 @@ static int factor_impl(genp_ctx* c, double pivot_tol, int64_t* breakdown_col, bo
         const int64_t k = j * nb;
         const int64_t m = np - k - nb;
         if (m > 0)
-            HIPCK(launch_panel_trsm(lp, at(k, k), ldc, (int)nb, at(k, k + nb), at(k + nb, k), ldc, (int)m, st));
+            HIPCK(launch_panel_trsm(lp, !lp, at(k, k), ldc, (int)nb, at(k, k + nb), at(k + nb, k), ldc, (int)m, st));
         HIPCK(hipEventRecord(ev(j, 3), st));
         return GENP_OK;
     };

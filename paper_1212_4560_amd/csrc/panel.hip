@@ -602,13 +602,13 @@ hipError_t launch_iota(int* p, int n, hipStream_t s) {
 // blocked elimination with nb = 128); A22 -= L21 U12; GENP of A22 in LDS.  This is block
 // Gaussian elimination (Theorem 2.2) on the block itself, with the same pivots.
 hipError_t launch_diag_lu_split(void* Dblk, long long ldd, int nvalid, long long col0, const double* maxc,
-                                double pivot_tol, PanelStats* st, hipStream_t s) {
+                                double pivot_tol, PanelStats* st, int rcp, hipStream_t s) {
     double* D = (double*)Dblk;
     hipLaunchKernelGGL(lu128_lds_kernel, dim3(1), dim3(256), 0, s, D, ldd, std::min(nvalid, 128), col0, maxc,
                        pivot_tol, st, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_panel_trsm(0, D, ldd, 128, D + 128, D + 128 * ldd, ldd, 128, s);
+    e = launch_panel_trsm(0, rcp, D, ldd, 128, D + 128, D + 128 * ldd, ldd, 128, s);
     if (e != hipSuccess) return e;
     GemmF64Args g{};
     g.M = g.N = g.K = 128;

@@ -123,6 +123,13 @@ trsm_cols_kernel(const TF* __restrict__ T, long long ldt, int nb, TX* X, long lo
     }
 }
 
+__device__ inline double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Lower-triangular solve T Y = Z by 16 x 16 blocks, T = L (unit, TT = false) or U^T
 // (TT = true, T(i, k) = U[k][i]).  Y(i, c): XT = false -> X[i * ldx + c] (the columns
 // of X are the right-hand sides), XT = true -> X[c * ldx + i] (its rows are).
@@ -131,12 +138,13 @@ trsm_cols_kernel(const TF* __restrict__ T, long long ldt, int nb, TX* X, long lo
 // acc[b] is exactly the B operand of the 16x16x4 MFMA for rows 16 b + 4 q .. + 3 of
 // Y (lane l: k = l / 16, column l % 16), so the solved tiles feed the update of the
 // tiles below with no data movement.  The diagonal blocks are solved by
-// substitution in the same order as a column sweep, with division by the pivot,
+// substitution in the same order as a column sweep, scaled by the pivot's reciprocal
+// (RCP) or divided by the pivot,
 // in place in the accumulators (cross-lane broadcast of each solved row).
 // T is staged through LDS one 16-column strip at a time (rows 16 b .. NB - 1),
 // prefetched one strip ahead through registers.  Only LDS traffic is fenced at the
 // barriers, so the prefetch stays in flight across them.
-template <int NBLK, bool TT, bool UNIT, bool XT, typename TF, typename TX>
+template <int NBLK, bool TT, bool UNIT, bool XT, bool RCP, typename TF, typename TX>
 __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], const TF* __restrict__ T,
                                                 long long ldt, TX* X, long long ldx, int ncols, int wg) {
     constexpr int NB = NBLK * 16;
@@ -191,14 +199,18 @@ __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], con
             }
         }
         // diagonal block, in place in the accumulator layout: row s of every right-hand
-        // side sits in lane group s % 4, element s / 4; the owner divides by the pivot,
+        // side sits in lane group s % 4, element s / 4; the owner scales it by the pivot,
         // the value is broadcast to the other three lane groups of the same column, and
         // each lane updates its rows below s (a column sweep: the operations and their
         // order per element are those of substitution)
+        // RCP: the pivots' reciprocals, one per lane (lane l: row l % 16 of the tile), taken
+        // once per tile so that no division sits on the substitution's chain; otherwise a
+        // division per row
+        const double rdv = (UNIT || !RCP) ? 1.0 : 1.0 / Ts[cur][16 * b + lr][lr];
 #pragma unroll
         for (int s_ = 0; s_ < 16; ++s_) {
             double v = acc[b][s_ >> 2];
-            if (!UNIT) v = v / Ts[cur][16 * b + s_][s_];
+            if (!UNIT) v = RCP ? v * readlane_d(rdv, s_) : v / Ts[cur][16 * b + s_][s_];
             const double ys = __shfl(v, (s_ & 3) * 16 + lr, 64);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -237,28 +249,22 @@ __device__ __forceinline__ void blk_lower_solve(double (*Ts)[NBLK * 16][17], con
 // workgroups [0, nwg) compute U12 = L11^{-1} A12 in place (the columns of A12 are the
 // right-hand sides), workgroups [nwg, 2 nwg) compute L21 = A21 U11^{-1}, i.e.
 // U11^T L21^T = A21^T (the rows of A21 are the right-hand sides).
-template <int NBLK, typename TF, typename TX>
+template <int NBLK, typename TF, typename TX, bool RCP>
 __global__ void __launch_bounds__(256, 2)
 panel_trsm_kernel(const TF* __restrict__ D, long long ldd, TX* A12, TX* A21, long long ldx, int m, int nwg) {
     __shared__ double Ts[2][NBLK * 16][17];
-    if ((int)blockIdx.x < nwg) blk_lower_solve<NBLK, false, true, false>(Ts, D, ldd, A12, ldx, m, blockIdx.x);
-    else blk_lower_solve<NBLK, true, false, true>(Ts, D, ldd, A21, ldx, m, blockIdx.x - nwg);
+    if ((int)blockIdx.x < nwg) blk_lower_solve<NBLK, false, true, false, RCP>(Ts, D, ldd, A12, ldx, m, blockIdx.x);
+    else blk_lower_solve<NBLK, true, false, true, RCP>(Ts, D, ldd, A21, ldx, m, blockIdx.x - nwg);
 }
 
-template <int NBLK, typename TF, typename TX>
+template <int NBLK, typename TF, typename TX, bool RCP = false>
 hipError_t panel_go(const void* D, long long ldd, void* A12, void* A21, long long ldx, int m, hipStream_t s) {
     const int nwg = (m + 63) / 64;
-    hipLaunchKernelGGL((panel_trsm_kernel<NBLK, TF, TX>), dim3(2 * nwg), dim3(256), 0, s, (const TF*)D, ldd,
+    hipLaunchKernelGGL((panel_trsm_kernel<NBLK, TF, TX, RCP>), dim3(2 * nwg), dim3(256), 0, s, (const TF*)D, ldd,
                        (TX*)A12, (TX*)A21, ldx, m, nwg);
     return hipGetLastError();
 }
 
-__device__ inline double readlane_d(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // One elimination step of the blocked substitution for 1..4 right-hand sides,
 // block size BS.  Block t is solved here; the block p solved by the previous
@@ -776,15 +782,23 @@ hipError_t launch_trsm(int kind, int t_f32, int x_f32, const void* T, long long 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_panel_trsm(int f32, const void* D, long long ldd, int nb, void* A12, void* A21, long long ldx,
-                             int m, hipStream_t s) {
+hipError_t launch_panel_trsm(int f32, int rcp, const void* D, long long ldd, int nb, void* A12, void* A21,
+                             long long ldx, int m, hipStream_t s) {
     if (m <= 0) return hipSuccess;
+    if (f32) {
+        switch (nb) {
+            case 64: return panel_go<4, float, float>(D, ldd, A12, A21, ldx, m, s);
+            case 128: return panel_go<8, float, float>(D, ldd, A12, A21, ldx, m, s);
+            case 256: return panel_go<16, float, float>(D, ldd, A12, A21, ldx, m, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (nb) {
-        case 64: return f32 ? panel_go<4, float, float>(D, ldd, A12, A21, ldx, m, s)
+        case 64: return rcp ? panel_go<4, double, double, true>(D, ldd, A12, A21, ldx, m, s)
                             : panel_go<4, double, double>(D, ldd, A12, A21, ldx, m, s);
-        case 128: return f32 ? panel_go<8, float, float>(D, ldd, A12, A21, ldx, m, s)
+        case 128: return rcp ? panel_go<8, double, double, true>(D, ldd, A12, A21, ldx, m, s)
                              : panel_go<8, double, double>(D, ldd, A12, A21, ldx, m, s);
-        case 256: return f32 ? panel_go<16, float, float>(D, ldd, A12, A21, ldx, m, s)
+        case 256: return rcp ? panel_go<16, double, double, true>(D, ldd, A12, A21, ldx, m, s)
                              : panel_go<16, double, double>(D, ldd, A12, A21, ldx, m, s);
         default: return hipErrorInvalidValue;
     }
