@@ -140,7 +140,8 @@ diag_lu_kernel(T* __restrict__ D, long long ldd, int nb, int nvalid, long long c
                         const double a = fabs(p[s][c]);
                         const double key = a == a ? a : -0.5;
                         // one basic block: the conditions evaluated in full, the result selected
-                        const bool take = (!done[s]) & (kb + r < nvalid) & ((key > best) | ((key == best) & (pos[s] < bp)));
+                        const bool take =
+                            (!done[s]) & (kb + r < nvalid) & ((key > best) | ((key == best) & (pos[s] < bp)));
                         best = take ? key : best;
                         bp = take ? pos[s] : bp;
                         bi = take ? r : bi;

@@ -265,7 +265,6 @@ hipError_t panel_go(const void* D, long long ldd, void* A12, void* A21, long lon
     return hipGetLastError();
 }
 
-
 // One elimination step of the blocked substitution for 1..4 right-hand sides,
 // block size BS.  Block t is solved here; the block p solved by the previous
 // launch (p = t-1 forward, t+1 backward) is applied first.  Workgroup 0 stages
@@ -426,9 +425,9 @@ trsv_step_kernel(const TF* __restrict__ T, long long ldt, int n_pad, int t, doub
 // a signalling-NaN bit pattern (kUnset) before the launch; the writer stores x_t into
 // it with device-scope relaxed atomic stores, and a reader polls the values it needs
 // with device-scope relaxed atomic loads until none is kUnset (the first request for a
-// block goes out one block ahead, during the products with the block before it).  Arithmetic never
-// produces kUnset (a NaN result is quiet), and each 8-byte value is written and read
-// whole, so no fence or separate flag sits on the chain.  sync[0]: ticket, sync[1]:
+// block goes out one block ahead, during the products with the block before it).
+// Arithmetic never produces kUnset (a NaN result is quiet), and each 8-byte value is
+// written and read whole, so no fence or separate flag sits on the chain.  sync[0]: ticket, sync[1]:
 // sticky error word (a wait exceeded spin_limit polls: the result is invalid).  The
 // caller resets sync[0] and pub before every launch.
 constexpr unsigned long long kUnset = 0x7ff4a5a5a5a5a5a5ull;
@@ -584,11 +583,11 @@ trsv_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, 
 // registers) and the values of X_p are polled straight into B operands, one 16-row tile of p
 // at a time in the order p solves its tiles: the product with a block overlaps the end of
 // that block's own solve; a lane's sixteen values of p are requested in one go, one block
-// ahead, and only the ones still unset are polled again.  Then the diagonal block is solved in place in the
-// accumulators, tile by tile: substitution row by row with a cross-lane broadcast of each
-// solved row (pivots applied as reciprocals taken when the block is loaded, so no division
-// sits on the chain), then the MFMA update of the tiles still to be solved.  Each tile is
-// published as soon as it is final.
+// ahead, and only the ones still unset are polled again.  Then the diagonal block is solved
+// in place in the accumulators, tile by tile: substitution row by row with a cross-lane
+// broadcast of each solved row (pivots applied as reciprocals taken when the block is
+// loaded, so no division sits on the chain), then the MFMA update of the tiles still to be
+// solved.  Each tile is published as soon as it is final.
 template <bool LOWER, bool UNIT, bool TT, typename TF>
 __global__ void __launch_bounds__(256)
 trsm_chain_kernel(const TF* __restrict__ T, long long ldt, int nblk, double* X, long long ldx, int ncols,
